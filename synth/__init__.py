@@ -1,0 +1,142 @@
+"""Seeded synthetic inputs for the smallest-enclosing-sphere (SES) and
+hard-margin SVM workloads.
+
+This module only draws numbers: it holds none of the method's arithmetic and is
+shared, unchanged, by the FP64 reference checker and the GPU path's tests and
+benchmark.  Every generator takes an explicit seed and uses numpy's PCG64.
+
+Workload shapes follow the paper's experiments (random point sets, Section 5;
+n swept 2^10..2^20 at d = 64 and d swept 2..512 at n = 1e5), scaled to the
+sizes the library is measured on:
+
+* ``ses_uniform``   -- points uniform in the cube [-1, 1]^d (small SES case).
+* ``ses_gaussian_outliers`` -- i.i.d. N(0, I) with a fraction of rows scaled
+  (large SES case: n = 1e6, d = 100, 1 % outliers scaled x5).
+* ``svm_planted``   -- two Gaussian classes N(+-0.1 u, I) filtered to a planted
+  margin |u.x| >= 0.05 about the hyperplane u.x = 0 (rows of class +1 first).
+* ``ses_ellipsoid`` -- points uniform in a random ellipsoid (batched case).
+
+``bf16_round`` / ``bf16_to_f32`` give the round-to-nearest-even BF16 storage
+of FP32 values, so a checker can be fed exactly the values a BF16-stored
+matrix holds without reading them back from the GPU.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "rng",
+    "ses_uniform",
+    "ses_gaussian_outliers",
+    "svm_planted",
+    "ses_ellipsoid",
+    "bf16_round",
+    "bf16_to_f32",
+    "CONFIGS",
+]
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def ses_uniform(n: int, d: int, seed: int) -> np.ndarray:
+    """n x d points uniform in [-1, 1]^d, FP64, row-major."""
+    return rng(seed).uniform(-1.0, 1.0, size=(n, d))
+
+
+def ses_gaussian_outliers(n: int, d: int, seed: int, frac: float = 0.01,
+                          scale: float = 5.0, dtype=np.float64) -> np.ndarray:
+    """n x d rows i.i.d. N(0, I); ``round(frac * n)`` distinct rows scaled by
+    ``scale``.  Generated in FP64 (or float32 directly when asked, to bound
+    host memory at n = 1e6) and returned row-major."""
+    g = rng(seed)
+    if dtype == np.float32:
+        x = g.standard_normal(size=(n, d), dtype=np.float32)
+    else:
+        x = g.standard_normal(size=(n, d))
+    k = int(round(frac * n))
+    if k > 0:
+        idx = g.choice(n, k, replace=False)
+        x[idx] *= scale
+    return x
+
+
+def svm_planted(n_pos: int, n_neg: int, d: int, seed: int, shift: float = 0.1,
+                margin: float = 0.05, dtype=np.float64):
+    """Two classes drawn N(+shift*u, I) and N(-shift*u, I) for a seeded unit
+    vector u, keeping only rows with u.x >= margin (class +1) or
+    u.x <= -margin (class -1).  Returns (X, u) with X = [P rows; Q rows]."""
+    g = rng(seed)
+    u = g.standard_normal(d)
+    u /= np.linalg.norm(u)
+    uf = u.astype(dtype)
+
+    def draw(count: int, sign: float) -> np.ndarray:
+        out = np.empty((count, d), dtype=dtype)
+        got = 0
+        chunk = max(1024, min(1 << 16, 2 * count))
+        while got < count:
+            if dtype == np.float32:
+                z = g.standard_normal(size=(chunk, d), dtype=np.float32)
+            else:
+                z = g.standard_normal(size=(chunk, d))
+            z += (sign * shift) * uf
+            proj = z @ uf
+            keep = z[(sign * proj) >= margin]
+            take = min(count - got, keep.shape[0])
+            out[got:got + take] = keep[:take]
+            got += take
+        return out
+
+    X = np.concatenate([draw(n_pos, +1.0), draw(n_neg, -1.0)], axis=0)
+    return X, u
+
+
+def ses_ellipsoid(n: int, d: int, seed: int) -> np.ndarray:
+    """Points uniform in a seeded random ellipsoid: z uniform in the unit ball
+    (Gaussian direction times U^(1/d)), then y = Q diag(sigma) z + c with Q a
+    random orthogonal matrix, sigma ~ logU[0.1, 1], c ~ N(0, I)."""
+    g = rng(seed)
+    z = g.standard_normal(size=(n, d))
+    z /= np.linalg.norm(z, axis=1, keepdims=True)
+    z *= g.uniform(0.0, 1.0, size=(n, 1)) ** (1.0 / d)
+    q, r = np.linalg.qr(g.standard_normal(size=(d, d)))
+    q *= np.sign(np.diag(r))
+    sigma = np.exp(g.uniform(math.log(0.1), 0.0, size=d))
+    c = g.standard_normal(d)
+    return (z * sigma) @ q.T + c
+
+
+def bf16_round(x32: np.ndarray) -> np.ndarray:
+    """FP32 -> BF16 bit patterns (uint16), round to nearest, ties to even.
+    NaN stays NaN (quiet)."""
+    b = np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32)
+    lsb = (b >> np.uint32(16)) & np.uint32(1)
+    r = (b + np.uint32(0x7FFF) + lsb) >> np.uint32(16)
+    nan = np.isnan(np.ascontiguousarray(x32, dtype=np.float32))
+    r = np.where(nan, (b >> np.uint32(16)) | np.uint32(0x40), r)
+    return r.astype(np.uint16)
+
+
+def bf16_to_f32(h: np.ndarray) -> np.ndarray:
+    """BF16 bit patterns (uint16) -> the FP32 values they encode."""
+    return (np.asarray(h, dtype=np.uint16).astype(np.uint32) << np.uint32(16)).view(np.float32)
+
+
+# The five measured workloads, by name.  Sizes, distributions and tolerances
+# are what the tests and the benchmark use.
+CONFIGS = {
+    "ses_small_f64": dict(problem="ses", n=2000, d=3, eps=1e-3, t_cap=20000,
+                          gen="uniform", seeds=list(range(10))),
+    "ses_1m_d100": dict(problem="ses", n=1_000_000, d=100, eps=1e-3, t_cap=20000,
+                        gen="gaussian_outliers", seeds=[0, 1, 2]),
+    "svm_500k_d256": dict(problem="svm", n_pos=250_000, n_neg=250_000, d=256,
+                          eps=1e-3, t_cap=20000, gen="planted", seeds=[0]),
+    "ses_batched": dict(problem="ses", instances=4096, n_lo=1000, n_hi=100_000,
+                        dims=[2, 3, 16, 64], gen="ellipsoid", seeds=[0]),
+    "ses_diff_d64": dict(problem="ses", n=200_000, d=64, T=2000, checkpoint=50,
+                         gen="gaussian", seeds=[0]),
+}
