@@ -1,0 +1,198 @@
+"""Benchmark of the MWU iteration on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu]
+
+Workload: smallest enclosing sphere, n = 1,000,000 points in d = 100, i.i.d.
+N(0, I) with 1 % of the rows scaled x5 (seed 0), resident in HBM as FP32.
+One step = one MWU iteration of an alpha-feasibility test: one streaming pass
+over the 400 MB point matrix fused with the SCMWU update, plus its FP64
+epilogue (ORACLE, running mean, monitor).  K steps are timed between two
+device synchronisations; the reported value is MWU iterations per second.
+
+The same JSON line also carries
+  roofline      bytes the pass must read (n d sizeof) over its mean HIP-event
+                duration, against the 8 TB/s HBM peak; HBM traffic from the
+                committed rocprofv3 counter summary when it matches the kernel;
+  bf16          the same measurement with BF16 storage (library-rounded copy);
+  solve         eps = 1e-3 solves (FP32 and BF16 storage) with the paper's
+                Section 5 early stopping: wall time, iterations, tests,
+                certified bounds;
+  cpu_baseline  the FP64 reference implementation timed on this host on a
+                bounded sample (a few iterations at the full size).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = dict(name="ses_1m_d100", n=1_000_000, d=100, seed=0, outlier_frac=0.01, outlier_scale=5.0)
+METRIC = "MWU iters/sec + ε=1e-3 solves/sec (MEB n=1M,d=100), HBM GB/s frac; BF16 vs FP32"
+KERNEL_SOURCES = ["paper_2405_09157_amd/csrc/mwu_kernels.hpp", "paper_2405_09157_amd/csrc/mwu_common.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ses_pass_1m_d100.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(storage: str):
+    """HBM bytes per pass from the committed counter summary, if it was taken
+    on the current kernel source (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    rec = t.get(storage)
+    return None if rec is None else rec.get("bytes_per_pass")
+
+
+def measure(X, storage, steps, warmup, alpha_rel=0.8, T=20000):
+    import torch
+    import paper_2405_09157_amd as scp
+    m = scp.MWU(X, "ses", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP, storage=storage, chunk=64)
+    alpha = alpha_rel * m.D
+    m.step(alpha, T, max(warmup, 1), reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = m.step(alpha, T, steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert info["outcome_name"] == "running" and info["t"] == max(warmup, 1) + steps, info
+    # per-pass HIP-event timing on the launch stream (the dominant kernel)
+    kms = m.time_passes(min(steps, 200))
+    m.close()
+    return dict(ms_per_step=1e3 * dt / steps, kernel_ms=kms, f_last=info["f_last"])
+
+
+def solve(X, storage):
+    import torch
+    import paper_2405_09157_amd as scp
+    m = scp.MWU(X, "ses", eps=1e-3, storage=storage, chunk=64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = m.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    m.close()
+    return dict(seconds=dt, solves_per_s=1.0 / dt, iters=out["iters"], tests=out["tests"],
+                radius=out["radius"], lower=out["lower"], upper=out["upper"],
+                cert_gap=(out["upper"] - out["lower"]) / out["lower"], converged=bool(out["converged"]))
+
+
+def cpu_baseline(V32, budget_s=20.0):
+    """FP64 oracle iterations at the full size on the host (bounded sample)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import ses as oses
+    with threadpool_limits(1):
+        V64 = V32.astype(np.float64)
+        P = oses.setup(V64)
+        alpha, T = 0.8 * P.D, 20000
+        eta = math.sqrt(math.log(P.r) / T)
+        S = np.zeros(V64.shape[1])
+        t_prev = 0
+        times = []
+        t_start = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            st = oses.step(P, S, t_prev, alpha, eta)
+            times.append(time.perf_counter() - t0)
+            S, t_prev = st["S"], t_prev + 1
+            if time.perf_counter() - t_start > budget_s or len(times) >= 30:
+                break
+    per = sorted(times[1:] if len(times) > 2 else times)[len(times[1:] if len(times) > 2 else times) // 2]
+    return dict(value=1.0 / per, unit="iters/s", cores=1, kind="oracle",
+                sample=f"{len(times)} FP64 oracle iterations of the same n=1e6, d=100 test "
+                       f"(median of the last {max(len(times) - 1, 1)}), numpy single thread")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the row-sharded design is described in DESIGN.md)", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    import synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = WORKLOAD
+    V = synth.ses_gaussian_outliers(w["n"], w["d"], w["seed"], frac=w["outlier_frac"],
+                                    scale=w["outlier_scale"], dtype=np.float32)
+    X = torch.from_numpy(V).cuda()
+    print(f"# data ready: {w['n']} x {w['d']} float32", file=sys.stderr, flush=True)
+    f32 = measure(X, None, a.steps, a.warmup)
+    print(f"# f32: {f32}", file=sys.stderr, flush=True)
+    bf16 = None if a.no_bf16 else measure(X, "bf16", a.steps, a.warmup)
+    if bf16:
+        print(f"# bf16: {bf16}", file=sys.stderr, flush=True)
+    sol = {}
+    if not a.no_solve:
+        sol["f32"] = solve(X, None)
+        print(f"# solve f32: {sol['f32']}", file=sys.stderr, flush=True)
+        if not a.no_bf16:
+            sol["bf16"] = solve(X, "bf16")
+            print(f"# solve bf16: {sol['bf16']}", file=sys.stderr, flush=True)
+            sol["bf16_over_f32_solve_rate"] = sol["bf16"]["solves_per_s"] / sol["f32"]["solves_per_s"]
+    del X
+    torch.cuda.empty_cache()
+    cpu = None if a.no_cpu else cpu_baseline(V)
+    if cpu:
+        print(f"# cpu: {cpu}", file=sys.stderr, flush=True)
+
+    algo_bytes = w["n"] * w["d"] * 4
+    ach = algo_bytes / (f32["kernel_ms"] * 1e-3) / 1e9
+    roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_for("f32"),
+                kernel="ses_pass_kernel<float,8,4,false>", kernel_ms=round(f32["kernel_ms"], 5),
+                bytes_per_launch=algo_bytes)
+    line = dict(metric=METRIC, value=round(1e3 / f32["ms_per_step"], 1), unit="iters/s", n_gpus=1,
+                steps=a.steps, warmup=a.warmup, ms_per_step=round(f32["ms_per_step"], 5),
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+                data="synthetic",
+                config=dict(workload=w["name"], n=w["n"], d=w["d"], storage="f32",
+                            points="N(0,I), 1% rows x5, seed 0", problem="SES"),
+                roofline=roof, cpu_baseline=cpu)
+    if bf16:
+        b_bytes = w["n"] * w["d"] * 2
+        b_ach = b_bytes / (bf16["kernel_ms"] * 1e-3) / 1e9
+        line["bf16"] = dict(value=round(1e3 / bf16["ms_per_step"], 1), unit="iters/s",
+                            ms_per_step=round(bf16["ms_per_step"], 5),
+                            speedup_vs_f32=round(f32["ms_per_step"] / bf16["ms_per_step"], 3),
+                            roofline=dict(bound="hbm", achieved=round(b_ach, 1), peak=HBM_PEAK_GBS,
+                                          unit="GB/s", frac=round(b_ach / HBM_PEAK_GBS, 4),
+                                          traffic=traffic_for("bf16"),
+                                          kernel="ses_pass_kernel<uint16_t,8,4,false>",
+                                          kernel_ms=round(bf16["kernel_ms"], 5), bytes_per_launch=b_bytes))
+    if sol:
+        line["solve"] = sol
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,285 @@
+/*
+ * scp_mwu.h -- C ABI of the MI355X (gfx950) primal-dual symmetric-cone MWU
+ * library for the smallest enclosing sphere (SES) and hard-margin SVM
+ * problems of Zheng, Varvitsiotis, Tan and Lin, "A Primal-Dual Framework for
+ * Symmetric Cone Programming" (arXiv 2405.09157).
+ *
+ * The caller states its problem in the paper's natural form:
+ *   SES  (problem SES, Section 4.1):  min gamma  s.t. ||u - v_i|| <= gamma - gamma_i
+ *   SVM  (problem SVM, Section 4.2):  max s1 + s2 s.t. P^T w >= s1 1,
+ *                                     -Q^T w >= s2 1, ||w|| <= 1
+ * and the library forms the cones, a_j, c and b of the primal/dual pair
+ * (LCP)/(SCP) of Sections 1 and 3 internally: for SES the hard cone is the
+ * product over i != v1 of second-order cones Q^{d+1} (eq. dualses), for SVM
+ * it is the orthant R^n_+ (eq. svm_dual_scp).  Results come back as the
+ * paper's primal/dual pair, i.e. a dual point y (the centre / the normal and
+ * offsets) with its objective, plus certified lower and upper bounds on OPT.
+ *
+ * One MWU iteration (the hot path) is one streaming pass over the n x d
+ * point matrix in HBM fused with the SCMWU update (eq. SCMWU, eq. implement /
+ * eq. min_implement): per-point loss, Jordan exponential of every cone block
+ * from its spectral values, trace normalisation, and the weighted sum that
+ * gives the ORACLE's next centre (eq. ses_oracle) or hyperplane
+ * (eq. svm_oracle), followed by the FP64 epilogue of the meta-algorithm
+ * (separation test, running mean, f(t) monitor and early stopping of
+ * Section 5).
+ *
+ * Conventions
+ *   - All pointers named "device" must point to memory on the GPU that the
+ *     context's stream can access (e.g. the data_ptr() of a torch tensor).
+ *     They are BORROWED: the caller keeps them alive until scp_mwu_destroy.
+ *   - Pointers named "host" are ordinary CPU memory owned by the caller.
+ *   - Every call enqueues device work on the context's stream and
+ *     synchronises that stream only to read back small results.  A context
+ *     may be used by one host thread at a time.
+ *   - Return codes: SCP_MWU_OK (0), SCP_MWU_STOPPED (1: budget spent, outputs
+ *     valid but the search interval is wider than requested), or a negative
+ *     SCP_MWU_E_* code.  Output structures are written only on OK / STOPPED.
+ *     The text of the last error of a context is given by
+ *     scp_mwu_last_error().
+ */
+#ifndef SCP_MWU_H
+#define SCP_MWU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCP_MWU_ABI_VERSION 1
+
+/* problem kinds */
+enum {
+  SCP_MWU_PROBLEM_SES = 1, /* smallest enclosing sphere of n points/spheres in R^d */
+  SCP_MWU_PROBLEM_SVM = 2  /* hard-margin SVM of two point sets in R^d */
+};
+
+/* element types of the point matrix */
+enum {
+  SCP_MWU_F32 = 1,  /* IEEE binary32 */
+  SCP_MWU_BF16 = 2, /* bfloat16 (upper half of a binary32), stored as uint16 */
+  SCP_MWU_F64 = 3   /* IEEE binary64 */
+};
+
+/* return codes */
+enum {
+  SCP_MWU_OK = 0,
+  SCP_MWU_STOPPED = 1,
+  SCP_MWU_E_INVAL = -1,      /* bad argument or descriptor */
+  SCP_MWU_E_NOMEM = -2,      /* device or host allocation failed */
+  SCP_MWU_E_HIP = -3,        /* a HIP runtime call failed (text in last_error) */
+  SCP_MWU_E_STATE = -4,      /* call not valid in the context's current state */
+  SCP_MWU_E_NUMERIC = -5,    /* NaN/Inf in the input or in the iteration */
+  SCP_MWU_E_INFEASIBLE = -6, /* SVM: classes certified not separable */
+  SCP_MWU_E_UNSUPPORTED = -7 /* valid request the library does not implement */
+};
+
+/* outcome of an alpha-feasibility test (Section 3 meta-algorithm; Section 5
+ * early exits) */
+enum {
+  SCP_MWU_OUT_RUNNING = 0,    /* test still in progress */
+  SCP_MWU_OUT_SEPARATED = 1,  /* ORACLE value < 0: SES OPT > alpha, SVM OPT < alpha */
+  SCP_MWU_OUT_BEAT = 2,       /* f(t) already better than alpha (Section 5) */
+  SCP_MWU_OUT_STABILIZED = 3, /* |f(t)-f(t-1)|/f(t-1) < delta for `patience` runs */
+  SCP_MWU_OUT_T_REACHED = 4,  /* T iterations without separation (meta theorem) */
+  SCP_MWU_OUT_NUMERIC = 5     /* NaN/Inf met in the epilogue */
+};
+
+/* descriptor flags */
+enum {
+  SCP_MWU_FLAG_NO_EARLY_STOP = 1, /* disable the Section 5 exits (f better than
+                                     alpha, stabilisation) in every test */
+  SCP_MWU_FLAG_THEORY = 2,        /* solve with T = T_theory of the meta theorem
+                                     (no cap) and no early exits: the certified
+                                     (1 +- eps) guarantee, at its full cost */
+  SCP_MWU_FLAG_CERTIFICATES = 4   /* SES on points: also compute the weak-duality
+                                     lower bound of eq.(ses_qp) from the MWU weights
+                                     on the last pass of every launch chunk */
+};
+
+/*
+ * Problem descriptor, read by scp_mwu_init (copied; may be freed afterwards).
+ * Zero-valued optional fields take the documented default.
+ */
+typedef struct scp_mwu_desc {
+  uint32_t struct_size; /* sizeof(scp_mwu_desc) as compiled by the caller */
+  int32_t problem;      /* SCP_MWU_PROBLEM_SES or SCP_MWU_PROBLEM_SVM */
+  int32_t dtype;        /* element type of `points` (SCP_MWU_F32/BF16/F64) */
+  int32_t storage;      /* element type the iteration streams: 0 = dtype;
+                           SCP_MWU_BF16 with dtype SCP_MWU_F32 makes init round
+                           the points once (nearest, ties to even) into a
+                           library-owned BF16 copy */
+  int64_t n;            /* number of points (SES: >= 2; SVM: n_pos + n_neg) */
+  int64_t d;            /* dimension, 1 <= d <= 512 */
+  int64_t ld;           /* row stride of `points` in elements, >= d (0 = d) */
+  const void *points;   /* device, row-major n x d; SVM: rows [0, n_pos) are
+                           class +1 (the paper's P), rows [n_pos, n) class -1 (Q) */
+  const double *radii;  /* SES: device, n sphere radii gamma_i >= 0, or NULL for
+                           a point set; must be NULL for SVM */
+  int64_t n_pos;        /* SVM: number of class +1 rows, 1 <= n_pos <= n-1 */
+  int64_t v1_index;     /* SES: index of the sphere kept as the easy set C
+                           (Section 4.1 keeps "the first one"); default 0 */
+  double eps;           /* target accuracy of scp_mwu_solve; default 1e-3 */
+  double delta;         /* stabilisation threshold of Section 5; default 1e-4 */
+  int32_t patience;     /* consecutive stabilised iterations; default 10 */
+  int32_t flags;        /* SCP_MWU_FLAG_* */
+  int64_t t_cap;        /* cap on T per test; 0 = min(ceil(ln n / eps^2), 20000) */
+  int64_t max_iters;    /* scp_mwu_solve iteration budget; 0 = unlimited */
+  void *stream;         /* hipStream_t to enqueue on; NULL = the null stream */
+  int32_t chunk;        /* iterations per graph launch; 0 = 32 */
+  int32_t grid;         /* workgroups of the streaming pass; 0 = chosen from the
+                           device's compute-unit count */
+} scp_mwu_desc;
+
+/* State of the current alpha-feasibility test after scp_mwu_step. */
+typedef struct scp_mwu_stepinfo {
+  int64_t t;          /* ORACLE outputs averaged so far (iterations done) */
+  int64_t t_end;      /* iteration at which the test ended, 0 while running */
+  int64_t T;          /* iteration cap of this test */
+  int32_t outcome;    /* SCP_MWU_OUT_* */
+  int32_t degenerate; /* 1 if the last ORACLE met W = 0 (SES) / V = 0 (SVM) */
+  double alpha;       /* the guess of OPT under test */
+  double eta;         /* SCMWU step size sqrt(ln r / T) */
+  double f_last;      /* f of the newest evaluated mean: f(t-1) of the last pass,
+                         NaN before any (Section 5 monitor) */
+  double f_best;      /* best f in this test (SES: min, SVM: max), a certified
+                         upper (SES) / lower (SVM) bound on OPT */
+  int64_t t_best;     /* iteration whose mean gave f_best */
+  double value;       /* ORACLE objective of the last iteration for the
+                         trace-one p(t) (eq. ses_oracle / eq. svm_oracle) */
+  double scale;       /* magnitude the separation test compares value with */
+  double log_trace;   /* ln Tr exp(-eta sum_tau m(tau)) of the last iteration */
+  double bound;       /* SES: certified lower bound from the MWU weights (0 if
+                         not computed); SVM: best certified upper bound
+                         ||P mu/Tr mu - Q gamma/Tr gamma|| of this test */
+} scp_mwu_stepinfo;
+
+/* Result of scp_mwu_solve. */
+typedef struct scp_mwu_result {
+  double value;        /* SES: radius of the returned sphere (max_i ||c - v_i|| +
+                          gamma_i, exact for the returned centre); SVM: margin
+                          s1 + s2 achieved by the returned unit normal */
+  double lower;        /* certified lower bound on OPT */
+  double upper;        /* certified upper bound on OPT */
+  double search_lo;    /* final search interval [L, U] of the alpha search */
+  double search_hi;
+  double D;            /* SES: max_{i != v1} ||v1 - v_i|| + gamma1 + gamma_i;
+                          SVM: max_i ||x_i|| */
+  int64_t iters;       /* MWU iterations (streaming passes) over all tests */
+  int32_t tests;       /* alpha-feasibility tests run */
+  int32_t converged;   /* 1 if the search met its stop rule */
+} scp_mwu_result;
+
+typedef struct scp_mwu_ctx scp_mwu_ctx;
+
+/*
+ * Validate the descriptor, allocate the context's workspace on the current
+ * HIP device, make the BF16 copy if asked, and compute D with one streaming
+ * pass (SES: Section 4.1 bounds [D/2, D]; SVM: Lemma svm_bound, range
+ * (0, 2D]).  No MWU iteration runs.
+ *
+ * Errors: E_INVAL (NULL pointer, n < 2, d outside [1, 512], ld < d, unknown
+ * dtype/storage/problem, misaligned points, n_pos outside [1, n-1], v1_index
+ * outside [0, n), radii given for SVM, eps <= 0 or delta < 0),
+ * E_NUMERIC (NaN/Inf in the points: D not finite), E_NOMEM, E_HIP.
+ * *out is set to NULL on error.
+ */
+int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out);
+
+/*
+ * Run up to k iterations (k >= 0) of the alpha-feasibility test with guess
+ * `alpha` > 0 and iteration cap T >= 1 (step size eta = sqrt(ln r / T), r the
+ * rank of the hard cone: 2(n-1) for SES, n for SVM).  A new test starts
+ * (p(1) = e/r, running mean cleared) when `reset` is non-zero, when no test
+ * has been started, or when alpha or T differ from the current test;
+ * otherwise the current test continues.  Iterations stop early when the test
+ * ends (info->outcome != RUNNING).  The state of the test is written to
+ * *info (host).
+ *
+ * Errors: E_INVAL (alpha <= 0 or not finite, T < 1, k < 0, info NULL),
+ * E_HIP, E_NUMERIC (outcome NUMERIC).
+ */
+int scp_mwu_step(scp_mwu_ctx *ctx, double alpha, int64_t T, int32_t k,
+                 int32_t reset, scp_mwu_stepinfo *info);
+
+/*
+ * Solve to the descriptor's eps with the adaptive alpha search of Section 3
+ * ("From feasibility to optimization"; mirrored for the SVM min form),
+ * running one alpha-feasibility test per search step.
+ * y (host, >= d + 2 doubles, may be NULL): SES receives the centre c (d
+ * values) followed by the radius; SVM receives the unit normal w (d values)
+ * followed by s1 and s2 with s1 + s2 = margin.
+ * Returns OK when the search met its stop rule, STOPPED when max_iters ran
+ * out first (outputs valid).
+ * Errors: E_INVAL (res NULL), E_HIP, E_NUMERIC, E_INFEASIBLE (SVM with a
+ * certified upper bound <= 0 on the margin).
+ */
+int scp_mwu_solve(scp_mwu_ctx *ctx, scp_mwu_result *res, double *y);
+
+/*
+ * Gradient of the solved value with respect to the points (adjoint of the
+ * unrolled fixed-alpha, fixed-T iterations).  Not implemented in this
+ * version: always returns E_UNSUPPORTED and writes nothing.
+ * grad_points: device, n x d FP32 owned by the caller.
+ */
+int scp_mwu_backward(scp_mwu_ctx *ctx, double grad_value, float *grad_points);
+
+/*
+ * Inspect or replace the running sums of the current test (checkpoint /
+ * resume, and step-level comparison with a reference).
+ * sums (host): SES: d values sum_{tau<=t} u(tau); SVM: d + 2 values
+ *   (sum w(tau), sum s1(tau), sum s2(tau)).
+ * scp_mwu_set_state starts a test with (alpha, T) at iteration count t >= 0
+ * with the given sums, then runs one streaming pass to bound the exponent
+ * range of the next iteration (no MWU step).  E_INVAL on bad sizes/values,
+ * E_STATE if get_state is called before any test.
+ */
+int scp_mwu_get_state(scp_mwu_ctx *ctx, double *sums, int64_t *t);
+int scp_mwu_set_state(scp_mwu_ctx *ctx, double alpha, int64_t T, int64_t t,
+                      const double *sums);
+
+/*
+ * Vectors of the current test (host outputs, d (+2 for SVM) doubles):
+ * which = 0: mean ybar(t) of the ORACLE outputs; 1: the mean that gave
+ * f_best; 2: the last ORACLE output y(t).  E_STATE before any test.
+ */
+int scp_mwu_get_vector(scp_mwu_ctx *ctx, int32_t which, double *y);
+
+/*
+ * Measurement helper: run k >= 1 further passes (MWU iterations) of the
+ * current test, each bracketed by a pair of HIP events recorded on the
+ * context's stream, and return the mean elapsed time per pass in
+ * milliseconds (host output *ms_mean).  The passes advance the test exactly
+ * as scp_mwu_step does.  E_INVAL (k < 1, NULL), E_STATE (no test started),
+ * E_HIP.
+ */
+int scp_mwu_time_passes(scp_mwu_ctx *ctx, int32_t k, double *ms_mean);
+
+/* D of the problem (see scp_mwu_result.D); E_INVAL on NULL. */
+int scp_mwu_get_D(const scp_mwu_ctx *ctx, double *D);
+
+/* Release the workspace and any library-owned copy.  NULL is a no-op. */
+void scp_mwu_destroy(scp_mwu_ctx *ctx);
+
+/* Text of the last error of ctx (never NULL; "" if none; ctx may be NULL,
+ * then the last scp_mwu_init failure in this thread is described). */
+const char *scp_mwu_last_error(const scp_mwu_ctx *ctx);
+
+/* Static text for a return code. */
+const char *scp_mwu_strerror(int code);
+
+/*
+ * Round n FP32 values to BF16 (nearest, ties to even; NaN stays NaN) on the
+ * device: src (device, n floats) -> dst (device, n uint16).  The storage
+ * conversion init uses; exported so callers can build BF16 inputs.
+ * E_INVAL on NULL pointers or n < 0, E_HIP.
+ */
+int scp_mwu_cast_bf16(const float *src, uint16_t *dst, int64_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCP_MWU_H */

@@ -1,0 +1,124 @@
+"""Convenience wrapper over the C ABI for torch device tensors.
+
+Argument marshalling only: the points stay in the caller's tensor (borrowed,
+kept alive by this object) and every step runs in ``libscpmwu.so``.
+"""
+from __future__ import annotations
+
+import math
+
+from . import _lib as L
+
+_DTYPES = None
+
+
+def _dtype_code(t):
+    import torch
+    global _DTYPES
+    if _DTYPES is None:
+        _DTYPES = {torch.float32: L.SCP_MWU_F32, torch.bfloat16: L.SCP_MWU_BF16,
+                   torch.float64: L.SCP_MWU_F64}
+    if t.dtype not in _DTYPES:
+        raise TypeError(f"points must be float32, bfloat16 or float64, not {t.dtype}")
+    return _DTYPES[t.dtype]
+
+
+class MWU:
+    """One SES or SVM problem on the GPU.
+
+    points   device tensor n x d (row stride >= d, unit column stride); SVM rows
+             [0, n_pos) are class +1 and the rest class -1.
+    storage  None (stream the points as given) or "bf16" (round FP32 points
+             once into a library-owned BF16 copy).
+    """
+
+    def __init__(self, points, problem: str = "ses", *, n_pos: int | None = None, radii=None,
+                 v1: int = 0, eps: float = 1e-3, delta: float = 1e-4, patience: int = 10,
+                 flags: int = 0, t_cap: int = 0, max_iters: int = 0, storage: str | None = None,
+                 chunk: int = 0, grid: int = 0, stream=None):
+        import torch
+        L.load()
+        if not points.is_cuda:
+            raise ValueError("points must be a device (HIP) tensor")
+        if points.dim() != 2 or points.stride(1) != 1:
+            raise ValueError("points must be 2-D with unit column stride")
+        self.points = points
+        self.radii = radii
+        self.problem = problem
+        self.n, self.d = points.shape
+        self.svm = problem == "svm"
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        self.stream = stream
+        desc = L.scp_mwu_desc()
+        desc.struct_size = __import__("ctypes").sizeof(L.scp_mwu_desc)
+        desc.problem = L.SCP_MWU_PROBLEM_SVM if self.svm else L.SCP_MWU_PROBLEM_SES
+        desc.dtype = _dtype_code(points)
+        desc.storage = {None: 0, "bf16": L.SCP_MWU_BF16}[storage]
+        desc.n, desc.d, desc.ld = self.n, self.d, points.stride(0)
+        desc.points = points.data_ptr()
+        if radii is not None:
+            if radii.dtype != torch.float64 or not radii.is_cuda or radii.numel() != self.n:
+                raise ValueError("radii must be a device float64 tensor of length n")
+            desc.radii = radii.data_ptr()
+        desc.n_pos = int(n_pos or 0)
+        desc.v1_index = int(v1)
+        desc.eps, desc.delta, desc.patience = float(eps), float(delta), int(patience)
+        desc.flags, desc.t_cap, desc.max_iters = int(flags), int(t_cap), int(max_iters)
+        desc.stream = stream.cuda_stream
+        desc.chunk, desc.grid = int(chunk), int(grid)
+        with torch.cuda.device(points.device):
+            self.ctx = L.scp_mwu_init(desc)
+        self.D = L.scp_mwu_get_D(self.ctx)
+        self.r = 2 * (self.n - 1) if not self.svm else self.n
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.scp_mwu_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls
+    def step(self, alpha: float, T: int, k: int, reset: bool = False) -> dict:
+        info = L.scp_mwu_step(self.ctx, float(alpha), int(T), int(k), int(reset))
+        out = {f: getattr(info, f) for f, _ in L.scp_mwu_stepinfo._fields_}
+        out["outcome_name"] = L.OUTCOME_NAMES[info.outcome]
+        return out
+
+    def solve(self) -> dict:
+        code, res, y = L.scp_mwu_solve(self.ctx, self.d)
+        out = {f: getattr(res, f) for f, _ in L.scp_mwu_result._fields_}
+        out["code"] = code
+        if self.svm:
+            out["w"], out["s1"], out["s2"] = y[: self.d], y[self.d], y[self.d + 1]
+        else:
+            out["center"], out["radius"] = y[: self.d], y[self.d]
+        return out
+
+    def get_state(self):
+        return L.scp_mwu_get_state(self.ctx, self.d, self.svm)
+
+    def set_state(self, alpha: float, T: int, t: int, sums) -> None:
+        L.scp_mwu_set_state(self.ctx, float(alpha), int(T), int(t), list(sums))
+
+    def vector(self, which: int):
+        return L.scp_mwu_get_vector(self.ctx, which, self.d, self.svm)
+
+    def time_passes(self, k: int) -> float:
+        """Mean HIP-event time (ms) of k further passes of the current test."""
+        return L.scp_mwu_time_passes(self.ctx, int(k))
+
+    def eta(self, T: int) -> float:
+        return math.sqrt(math.log(self.r) / T)

@@ -1,0 +1,123 @@
+// Internal definitions shared by the HIP kernels and the host driver of the
+// primal-dual symmetric-cone MWU library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scpmwu {
+
+// Launch geometry of the streaming pass.  A wavefront owns G = 16 lanes per
+// point row (one DPP row), so a wave covers 4 rows per load step; a
+// workgroup holds 4 waves.
+constexpr int kWave = 64;
+constexpr int kG = 16;
+constexpr int kRowsPerStep = kWave / kG;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+// Workgroups whose partial sums are combined by the last finisher of their
+// group before the final combine (two-level, fixed-order reduction).
+constexpr int kGroup = 16;
+// Maximum dimension supported by the streaming pass (16 lanes x 32 columns).
+constexpr int kMaxD = 512;
+// Width of a workgroup's partial record: two d-vectors, 4 sums, 4 maxima.
+inline __host__ __device__ int partial_width(int d) { return 2 * d + 8; }
+
+enum Problem : int32_t { kSES = 1, kSVM = 2 };
+enum DType : int32_t { kF32 = 1, kBF16 = 2, kF64 = 3 };
+enum Status : int32_t {
+  kRunning = 0,
+  kSeparated = 1,
+  kBeat = 2,
+  kStabilized = 3,
+  kTReached = 4,
+  kNumeric = 5
+};
+
+// State of the current alpha-feasibility test, resident in device memory and
+// updated only by the epilogue of the streaming pass (and by the init/set
+// kernels).  All floating-point members are binary64.
+struct DevState {
+  // parameters of the test
+  double alpha;    // the guess of OPT
+  double eta;      // SCMWU step size
+  double kscale;   // SES: eta / (rho sqrt2); SVM: eta / rho  (kappa = kscale * t)
+  double delta;    // stabilisation threshold
+  double tau;      // relative tie tolerance of the separation test
+  double D;        // problem bound D
+  double gamma1;   // SES: radius of sphere v1
+  int64_t T;       // iteration cap
+  int64_t t;       // ORACLE outputs averaged so far
+  int64_t t_end;   // iteration at which the test ended
+  int64_t t_best;  // iteration of the best monitored mean
+  int32_t status;  // Status
+  int32_t cnt;     // consecutive stabilised iterations
+  int32_t patience;
+  int32_t early;   // Section 5 exits enabled
+  int32_t degenerate;
+  int32_t cert;    // a certificate was computed on the last pass
+  // monitor
+  double f_prev;   // f of the previous monitored iteration (-1: none)
+  double f_best;
+  double f_last;
+  // exponent bound for the next pass: SES an upper bound G on
+  // max_{i != v1} ||v_i - ubar|| + gamma_i; SVM a lower bound on the slack
+  double shift_bound;
+  // last ORACLE
+  double value, scale, log_trace;
+  double bound;     // SES: best weight lower bound; SVM: best PD upper bound
+  // SVM scalar parts of y = (w; s1; s2): running sums and means
+  double S1, S2, s1bar, s2bar, s1_last, s2_last;
+  double wbar_norm; // ||wbar|| of the current mean
+};
+
+// Device vectors of a test, each of length d (binary64):
+//   vec + 0*d: S     running sum of ORACLE centres / normals
+//   vec + 1*d: ybar  current mean (the pass's candidate)
+//   vec + 2*d: best  mean that gave f_best
+//   vec + 3*d: last  last ORACLE output
+constexpr int kVecS = 0, kVecMean = 1, kVecBest = 2, kVecLast = 3, kNumVec = 4;
+
+struct PassArgs {
+  const void *X;          // row-major points (storage type)
+  int64_t n, d, ld;
+  const double *radii;    // SES radii or nullptr
+  int64_t v1;             // SES easy-set row
+  int64_t n_pos;          // SVM class boundary
+  DevState *st;
+  double *vec;            // kNumVec * d
+  double *partials;       // gridDim.x * partial_width(d)
+  double *gpartials;      // ceil(gridDim.x / kGroup) * partial_width(d)
+  unsigned *tickets;      // ceil(gridDim.x / kGroup) + 1 counters, zero at rest
+};
+
+// Parameters of a new alpha-feasibility test (written by the init kernel).
+struct InitParams {
+  double alpha, eta, kscale, delta, tau, D, gamma1;
+  int64_t T;
+  int32_t patience, early;
+};
+
+// Host-side launchers (one translation unit per storage type).
+struct LaunchCfg {
+  int grid;
+  int epl;     // columns per lane: 16 * epl >= d
+  int vec;     // elements per vector load (1 = scalar loads)
+  bool cert;   // SES weight certificate accumulators
+};
+
+#define SCPMWU_DECLARE_TYPED(name)                                                              \
+  hipError_t launch_pass_##name(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s); \
+  hipError_t launch_monitor_##name(int grid, const PassArgs &a, const double *center,            \
+                                   int64_t exclude, int mode, double *out, hipStream_t s);      \
+  hipError_t launch_init_##name(const PassArgs &a, const InitParams &p, int problem, hipStream_t s);
+SCPMWU_DECLARE_TYPED(f32)
+SCPMWU_DECLARE_TYPED(bf16)
+SCPMWU_DECLARE_TYPED(f64)
+#undef SCPMWU_DECLARE_TYPED
+hipError_t launch_set_state_k(const PassArgs &a, int problem, int64_t t, double S1, double S2,
+                              hipStream_t s);
+hipError_t launch_cast(const float *src, uint16_t *dst, int64_t n, int64_t d, int64_t ld_src,
+                       int64_t ld_dst, hipStream_t s);
+
+}  // namespace scpmwu

@@ -1,0 +1,17 @@
+// Streaming-pass kernels instantiated for float point storage.
+#include "mwu_kernels.hpp"
+
+namespace scpmwu {
+
+hipError_t launch_pass_f32(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
+  return launch_pass_typed<float>(problem, c, a, s);
+}
+hipError_t launch_monitor_f32(int grid, const PassArgs &a, const double *center, int64_t exclude,
+                               int mode, double *out, hipStream_t s) {
+  return launch_monitor_typed<float>(grid, a, center, exclude, mode, out, s);
+}
+hipError_t launch_init_f32(const PassArgs &a, const InitParams &p, int problem, hipStream_t s) {
+  return launch_init_typed<float>(a, p, problem, s);
+}
+
+}  // namespace scpmwu

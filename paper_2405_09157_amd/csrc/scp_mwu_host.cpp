@@ -1,0 +1,686 @@
+// Host side of the C ABI declared in include/scp_mwu.h: descriptor
+// validation, workspace ownership, the alpha-feasibility test state machine
+// driven through captured HIP graphs of the streaming pass, and the adaptive
+// alpha search of Section 3 ("From feasibility to optimization"), mirrored
+// for the SVM min form.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/scp_mwu.h"
+#include "mwu_common.hpp"
+
+
+using namespace scpmwu;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr double kTau = 1e-12;  // relative tie tolerance of the separation test
+
+size_t elem_size(int dt) { return dt == kBF16 ? 2 : (dt == kF32 ? 4 : 8); }
+
+}  // namespace
+
+struct scp_mwu_ctx {
+  // problem
+  int problem = 0, dtype = 0;  // dtype: storage type streamed by the kernels
+  int64_t n = 0, d = 0, ld = 0, n_pos = 0, v1 = 0;
+  const void *X = nullptr;
+  void *owned = nullptr;
+  const double *radii = nullptr;
+  double eps = 1e-3, delta = 1e-4;
+  int32_t patience = 10, flags = 0, chunk = 32;
+  int64_t t_cap = 0, max_iters = 0;
+  hipStream_t stream = nullptr, cap_stream = nullptr;
+  // constants of the split
+  double D = 0, gamma1 = 0, rho = 0, R = 0;
+  int64_t r = 0;
+  // device workspace
+  DevState *st = nullptr;
+  double *vec = nullptr, *partials = nullptr, *gpartials = nullptr, *mon = nullptr;
+  unsigned *tickets = nullptr;
+  DevState *host_st = nullptr;  // pinned readback
+  int grid = 0;
+  LaunchCfg cfg{}, cfg_cert{};
+  PassArgs args{};
+  // current test
+  bool active = false;
+  double alpha = 0, eta = 0;
+  int64_t T = 0;
+  // graphs: `chunk` passes, the last one optionally with certificates
+  hipGraphExec_t gexec = nullptr;
+  std::string err;
+
+  int fail(int code, const std::string &msg) {
+    err = msg;
+    return code;
+  }
+  int hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return SCP_MWU_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return SCP_MWU_E_HIP;
+  }
+};
+
+namespace {
+
+hipError_t pass(scp_mwu_ctx *c, bool cert, hipStream_t s) {
+  const LaunchCfg &cfg = cert ? c->cfg_cert : c->cfg;
+  switch (c->dtype) {
+    case kF32: return launch_pass_f32(c->problem, cfg, c->args, s);
+    case kBF16: return launch_pass_bf16(c->problem, cfg, c->args, s);
+    default: return launch_pass_f64(c->problem, cfg, c->args, s);
+  }
+}
+
+hipError_t monitor(scp_mwu_ctx *c, const double *center, int64_t exclude, int mode) {
+  switch (c->dtype) {
+    case kF32: return launch_monitor_f32(c->grid, c->args, center, exclude, mode, c->mon, c->stream);
+    case kBF16: return launch_monitor_bf16(c->grid, c->args, center, exclude, mode, c->mon, c->stream);
+    default: return launch_monitor_f64(c->grid, c->args, center, exclude, mode, c->mon, c->stream);
+  }
+}
+
+// Read the per-workgroup monitor records and max-combine them.
+int monitor_result(scp_mwu_ctx *c, double out[4]) {
+  std::vector<double> h((size_t)c->grid * 4);
+  int rc = c->hip(hipMemcpyAsync(h.data(), c->mon, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream), "monitor readback");
+  if (rc) return rc;
+  rc = c->hip(hipStreamSynchronize(c->stream), "monitor sync");
+  if (rc) return rc;
+  for (int k = 0; k < 4; ++k) out[k] = -INFINITY;
+  for (int b = 0; b < c->grid; ++b)
+    for (int k = 0; k < 4; ++k) out[k] = std::max(out[k], h[(size_t)b * 4 + k]);
+  return SCP_MWU_OK;
+}
+
+int read_state(scp_mwu_ctx *c) {
+  int rc = c->hip(hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream),
+                  "state readback");
+  if (rc) return rc;
+  return c->hip(hipStreamSynchronize(c->stream), "state sync");
+}
+
+int start_test(scp_mwu_ctx *c, double alpha, int64_t T, bool early) {
+  InitParams p{};
+  p.alpha = alpha;
+  p.T = T;
+  p.eta = std::sqrt(std::log((double)c->r) / (double)T);
+  p.kscale = c->problem == kSES ? p.eta / (c->rho * std::sqrt(2.0)) : p.eta / c->rho;
+  p.delta = c->delta;
+  p.tau = kTau;
+  p.D = c->D;
+  p.gamma1 = c->gamma1;
+  p.patience = c->patience;
+  p.early = early ? 1 : 0;
+  hipError_t e;
+  switch (c->dtype) {
+    case kF32: e = launch_init_f32(c->args, p, c->problem, c->stream); break;
+    case kBF16: e = launch_init_bf16(c->args, p, c->problem, c->stream); break;
+    default: e = launch_init_f64(c->args, p, c->problem, c->stream); break;
+  }
+  int rc = c->hip(e, "test init");
+  if (rc) return rc;
+  c->active = true;
+  c->alpha = alpha;
+  c->T = T;
+  c->eta = p.eta;
+  return SCP_MWU_OK;
+}
+
+int build_graph(scp_mwu_ctx *c) {
+  if (c->gexec) return SCP_MWU_OK;
+  hipGraph_t g = nullptr;
+  int rc = c->hip(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (rc) return rc;
+  const bool cert = (c->flags & SCP_MWU_FLAG_CERTIFICATES) && c->problem == kSES;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < c->chunk && e == hipSuccess; ++k)
+    e = pass(c, cert && k == c->chunk - 1, c->cap_stream);
+  hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+  if (e != hipSuccess) return c->hip(e, "capture pass");
+  rc = c->hip(e2, "end capture");
+  if (rc) return rc;
+  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return c->hip(e, "graph instantiate");
+}
+
+// Run up to k passes of the current test; stop early once it has ended.
+int run_iters(scp_mwu_ctx *c, int64_t k) {
+  int rc;
+  const bool cert = (c->flags & SCP_MWU_FLAG_CERTIFICATES) && c->problem == kSES;
+  while (k > 0) {
+    if (k >= c->chunk && c->chunk > 1) {
+      rc = build_graph(c);
+      if (rc) return rc;
+      rc = c->hip(hipGraphLaunch(c->gexec, c->stream), "graph launch");
+      if (rc) return rc;
+      k -= c->chunk;
+    } else {
+      rc = c->hip(pass(c, cert && k == 1, c->stream), "pass launch");
+      if (rc) return rc;
+      k -= 1;
+    }
+    rc = read_state(c);
+    if (rc) return rc;
+    if (c->host_st->status != kRunning) break;
+  }
+  return SCP_MWU_OK;
+}
+
+void fill_info(const scp_mwu_ctx *c, scp_mwu_stepinfo *info) {
+  const DevState &s = *c->host_st;
+  info->t = s.t;
+  info->t_end = s.status == kRunning ? 0 : s.t_end;
+  info->T = s.T;
+  info->outcome = s.status;
+  info->degenerate = s.degenerate;
+  info->alpha = s.alpha;
+  info->eta = s.eta;
+  info->f_last = s.f_last;
+  info->f_best = s.f_best;
+  info->t_best = s.t_best;
+  info->value = s.value;
+  info->scale = s.scale;
+  info->log_trace = s.log_trace;
+  info->bound = s.bound;
+}
+
+int64_t theory_T(const scp_mwu_ctx *c, double eps, double alpha) {
+  const double v = 4.0 * (c->R * c->R) * (c->rho * c->rho) * std::log((double)c->r) /
+                   ((eps * eps) * (alpha * alpha));
+  if (!(v < 9.0e18)) return INT64_MAX / 2;
+  return (int64_t)std::ceil(v);
+}
+
+int64_t min_T(const scp_mwu_ctx *c) {
+  return std::max<int64_t>(1, (int64_t)std::ceil(std::log((double)c->r)));
+}
+
+// Run one whole alpha-feasibility test; the final device state is in host_st.
+int run_test(scp_mwu_ctx *c, double alpha, int64_t T, bool early, int64_t budget) {
+  int rc = start_test(c, alpha, T, early);
+  if (rc) return rc;
+  // T + 1 passes evaluate f(T); the test can only end earlier
+  int64_t left = budget > 0 ? std::min<int64_t>(budget + 1, T + 1) : T + 1;
+  while (true) {
+    const int64_t k = std::min<int64_t>(left, c->chunk);
+    rc = run_iters(c, k);
+    if (rc) return rc;
+    left -= k;
+    if (c->host_st->status != kRunning || left <= 0) break;
+  }
+  return SCP_MWU_OK;
+}
+
+int read_vec(scp_mwu_ctx *c, int which, double *out) {
+  int rc = c->hip(hipMemcpyAsync(out, c->vec + (size_t)which * c->d, (size_t)c->d * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream), "vector readback");
+  if (rc) return rc;
+  return c->hip(hipStreamSynchronize(c->stream), "vector sync");
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+extern "C" {
+
+const char *scp_mwu_strerror(int code) {
+  switch (code) {
+    case SCP_MWU_OK: return "ok";
+    case SCP_MWU_STOPPED: return "stopped: iteration budget spent before the stop rule";
+    case SCP_MWU_E_INVAL: return "invalid argument";
+    case SCP_MWU_E_NOMEM: return "out of memory";
+    case SCP_MWU_E_HIP: return "HIP runtime error";
+    case SCP_MWU_E_STATE: return "call not valid in the current state";
+    case SCP_MWU_E_NUMERIC: return "non-finite value in the input or the iteration";
+    case SCP_MWU_E_INFEASIBLE: return "classes certified not separable";
+    case SCP_MWU_E_UNSUPPORTED: return "not supported by this version";
+    default: return "unknown error code";
+  }
+}
+
+const char *scp_mwu_last_error(const scp_mwu_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+void scp_mwu_destroy(scp_mwu_ctx *c) {
+  if (!c) return;
+  hipStreamSynchronize(c->stream);
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  hipFree(c->st);
+  hipFree(c->vec);
+  hipFree(c->partials);
+  hipFree(c->gpartials);
+  hipFree(c->mon);
+  hipFree(c->tickets);
+  hipFree(c->owned);
+  if (c->host_st) hipHostFree(c->host_st);
+  delete c;
+}
+
+int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
+  g_init_error.clear();
+  auto bad = [&](const char *m) {
+    g_init_error = m;
+    return SCP_MWU_E_INVAL;
+  };
+  if (!out) return bad("out is NULL");
+  *out = nullptr;
+  if (!desc) return bad("desc is NULL");
+  if (desc->struct_size < sizeof(scp_mwu_desc)) return bad("desc->struct_size too small");
+  if (desc->problem != SCP_MWU_PROBLEM_SES && desc->problem != SCP_MWU_PROBLEM_SVM)
+    return bad("unknown problem");
+  if (desc->dtype < SCP_MWU_F32 || desc->dtype > SCP_MWU_F64) return bad("unknown dtype");
+  const int storage = desc->storage ? desc->storage : desc->dtype;
+  if (storage < SCP_MWU_F32 || storage > SCP_MWU_F64) return bad("unknown storage type");
+  if (storage != desc->dtype && !(desc->dtype == SCP_MWU_F32 && storage == SCP_MWU_BF16))
+    return bad("storage conversion other than F32 -> BF16");
+  if (!desc->points) return bad("points is NULL");
+  if (desc->n < 2) return bad("n < 2");
+  if (desc->d < 1 || desc->d > kMaxD) return bad("d outside [1, 512]");
+  const int64_t ld = desc->ld ? desc->ld : desc->d;
+  if (ld < desc->d) return bad("ld < d");
+  if ((uintptr_t)desc->points % elem_size(desc->dtype)) return bad("points misaligned");
+  if (desc->problem == SCP_MWU_PROBLEM_SVM) {
+    if (desc->n_pos < 1 || desc->n_pos > desc->n - 1) return bad("n_pos outside [1, n-1]");
+    if (desc->radii) return bad("radii given for SVM");
+  } else {
+    if (desc->v1_index < 0 || desc->v1_index >= desc->n) return bad("v1_index outside [0, n)");
+  }
+  if (desc->eps < 0 || desc->delta < 0 || desc->patience < 0 || desc->t_cap < 0 || desc->max_iters < 0 ||
+      desc->chunk < 0 || desc->grid < 0)
+    return bad("negative parameter");
+
+  auto *c = new scp_mwu_ctx();
+  c->problem = desc->problem;
+  c->n = desc->n;
+  c->d = desc->d;
+  c->ld = ld;
+  c->n_pos = desc->n_pos;
+  c->v1 = desc->problem == SCP_MWU_PROBLEM_SES ? desc->v1_index : 0;
+  c->radii = desc->radii;
+  c->eps = desc->eps > 0 ? desc->eps : 1e-3;
+  c->delta = desc->delta > 0 ? desc->delta : 1e-4;
+  c->patience = desc->patience > 0 ? desc->patience : 10;
+  c->flags = desc->flags;
+  c->max_iters = desc->max_iters;
+  c->chunk = desc->chunk > 0 ? desc->chunk : 32;
+  c->stream = (hipStream_t)desc->stream;
+  c->t_cap = desc->t_cap > 0 ? desc->t_cap
+                             : std::min<int64_t>((int64_t)std::ceil(std::log((double)c->n) / (c->eps * c->eps)),
+                                                 20000);
+  auto fail = [&](int code, const std::string &m) {
+    g_init_error = m;
+    scp_mwu_destroy(c);
+    return code;
+  };
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return fail(SCP_MWU_E_HIP, "no HIP device");
+
+  // storage: borrowed, or a library-owned BF16 copy
+  c->dtype = storage;
+  c->X = desc->points;
+  if (storage != desc->dtype) {
+    const int64_t ldb = desc->d;
+    if (hipMalloc(&c->owned, (size_t)c->n * ldb * 2) != hipSuccess) return fail(SCP_MWU_E_NOMEM, "BF16 copy");
+    if (launch_cast((const float *)desc->points, (uint16_t *)c->owned, c->n, c->d, ld, ldb, c->stream) != hipSuccess)
+      return fail(SCP_MWU_E_HIP, "BF16 cast launch");
+    c->X = c->owned;
+    c->ld = ldb;
+  }
+
+  // launch shape
+  int epl = 1;
+  while (kG * epl < c->d) epl *= 2;
+  const int es = (int)elem_size(c->dtype);
+  const int vf = std::min(epl, 16 / es);
+  int vec = 1;
+  for (int v : {vf, vf >= 4 ? vf / 2 : 1, 1}) {
+    if (c->d % v == 0 && c->ld % v == 0 && ((uintptr_t)c->X % (size_t)(v * es)) == 0) {
+      vec = v;
+      break;
+    }
+  }
+  const int lim = c->dtype == kF64 ? 32 : 64;
+  const int B = std::max(1, std::min(16, lim / epl)) * kRowsPerStep;
+  const int64_t nb = (c->n + B - 1) / B;
+  int grid = desc->grid > 0 ? desc->grid : 2 * cus;
+  grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, (nb + kWavesPerBlock - 1) / kWavesPerBlock));
+  c->grid = grid;
+  c->cfg = LaunchCfg{grid, epl, vec, false};
+  c->cfg_cert = LaunchCfg{grid, epl, vec, true};
+
+  const int pw = partial_width((int)c->d);
+  const int ng = (grid + kGroup - 1) / kGroup;
+  if (hipMalloc(&c->st, sizeof(DevState)) != hipSuccess ||
+      hipMalloc(&c->vec, sizeof(double) * kNumVec * c->d) != hipSuccess ||
+      hipMalloc(&c->partials, sizeof(double) * (size_t)grid * pw) != hipSuccess ||
+      hipMalloc(&c->gpartials, sizeof(double) * (size_t)ng * pw) != hipSuccess ||
+      hipMalloc(&c->mon, sizeof(double) * (size_t)grid * 4) != hipSuccess ||
+      hipMalloc(&c->tickets, sizeof(unsigned) * (ng + 1)) != hipSuccess ||
+      hipHostMalloc((void **)&c->host_st, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+    return fail(SCP_MWU_E_NOMEM, "workspace allocation");
+  if (hipMemsetAsync(c->tickets, 0, sizeof(unsigned) * (ng + 1), c->stream) != hipSuccess)
+    return fail(SCP_MWU_E_HIP, "ticket reset");
+  if (hipStreamCreate(&c->cap_stream) != hipSuccess) return fail(SCP_MWU_E_HIP, "capture stream");
+
+  PassArgs &a = c->args;
+  a.X = c->X;
+  a.n = c->n;
+  a.d = c->d;
+  a.ld = c->ld;
+  a.radii = c->radii;
+  a.v1 = c->v1;
+  a.n_pos = c->n_pos;
+  a.st = c->st;
+  a.vec = c->vec;
+  a.partials = c->partials;
+  a.gpartials = c->gpartials;
+  a.tickets = c->tickets;
+
+  // D (one streaming pass): SES distance from v1, SVM largest norm.
+  c->r = c->problem == kSES ? 2 * (c->n - 1) : c->n;
+  c->rho = 1.0;  // placeholder until D is known
+  int rc = start_test(c, 1.0, 1, false);  // ubar = v1 (SES) / 0 (SVM)
+  if (rc) return fail(rc, c->err);
+  c->active = false;
+  if (c->problem == kSES && c->radii) {
+    if (hipMemcpyAsync(&c->gamma1, c->radii + c->v1, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+      return fail(SCP_MWU_E_HIP, "radius readback");
+  }
+  if (monitor(c, c->vec + kVecMean * c->d, c->problem == kSES ? c->v1 : -1, 0) != hipSuccess)
+    return fail(SCP_MWU_E_HIP, "D pass launch");
+  double m[4];
+  rc = monitor_result(c, m);
+  if (rc) return fail(rc, c->err);
+  if (c->problem == kSES) {
+    c->D = m[0] + c->gamma1;
+    c->R = std::sqrt(2.0);
+    c->rho = 3.0 * c->D / std::sqrt(2.0);
+    if (!std::isfinite(c->D) || !std::isfinite(m[1])) return fail(SCP_MWU_E_NUMERIC, "non-finite input");
+    if (!(c->D > 0)) return fail(SCP_MWU_E_INVAL, "all spheres coincide (D = 0)");
+    if (c->gamma1 > c->D / 2) return fail(SCP_MWU_E_INVAL, "radius of sphere v1 exceeds D/2");
+  } else {
+    c->D = m[1];
+    c->R = 2.0;
+    c->rho = 2.0 * c->D;
+    if (!std::isfinite(c->D)) return fail(SCP_MWU_E_NUMERIC, "non-finite input");
+    if (!(c->D > 0)) return fail(SCP_MWU_E_INVAL, "all points are zero");
+  }
+  *out = c;
+  return SCP_MWU_OK;
+}
+
+int scp_mwu_time_passes(scp_mwu_ctx *c, int32_t k, double *ms_mean) {
+  if (!c) return SCP_MWU_E_INVAL;
+  if (!ms_mean || k < 1) return c->fail(SCP_MWU_E_INVAL, "time_passes: k >= 1 and ms_mean required");
+  if (!c->active) return c->fail(SCP_MWU_E_STATE, "no test started");
+  std::vector<hipEvent_t> ev(2 * (size_t)k, nullptr);
+  int rc = SCP_MWU_OK;
+  for (auto &e : ev)
+    if (!rc) rc = c->hip(hipEventCreate(&e), "event create");
+  for (int32_t i = 0; i < k && !rc; ++i) {
+    rc = c->hip(hipEventRecord(ev[2 * i], c->stream), "event record");
+    if (!rc) rc = c->hip(pass(c, false, c->stream), "pass launch");
+    if (!rc) rc = c->hip(hipEventRecord(ev[2 * i + 1], c->stream), "event record");
+  }
+  if (!rc) rc = c->hip(hipEventSynchronize(ev.back()), "event sync");
+  double total = 0.0;
+  for (int32_t i = 0; i < k && !rc; ++i) {
+    float ms = 0.f;
+    rc = c->hip(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]), "event elapsed");
+    total += ms;
+  }
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  *ms_mean = total / k;
+  return read_state(c);
+}
+
+int scp_mwu_get_D(const scp_mwu_ctx *c, double *D) {
+  if (!c || !D) return SCP_MWU_E_INVAL;
+  *D = c->D;
+  return SCP_MWU_OK;
+}
+
+int scp_mwu_step(scp_mwu_ctx *c, double alpha, int64_t T, int32_t k, int32_t reset, scp_mwu_stepinfo *info) {
+  if (!c) return SCP_MWU_E_INVAL;
+  if (!info || !(alpha > 0) || !std::isfinite(alpha) || T < 1 || k < 0)
+    return c->fail(SCP_MWU_E_INVAL, "step: alpha > 0, T >= 1, k >= 0 and info required");
+  int rc;
+  if (reset || !c->active || alpha != c->alpha || T != c->T) {
+    const bool early = !(c->flags & (SCP_MWU_FLAG_NO_EARLY_STOP | SCP_MWU_FLAG_THEORY));
+    rc = start_test(c, alpha, T, early);
+    if (rc) return rc;
+  }
+  rc = run_iters(c, k);
+  if (rc) return rc;
+  if (k == 0 && (rc = read_state(c))) return rc;
+  fill_info(c, info);
+  if (c->host_st->status == kNumeric) return c->fail(SCP_MWU_E_NUMERIC, "non-finite value in the iteration");
+  return SCP_MWU_OK;
+}
+
+int scp_mwu_get_state(scp_mwu_ctx *c, double *sums, int64_t *t) {
+  if (!c) return SCP_MWU_E_INVAL;
+  if (!sums || !t) return c->fail(SCP_MWU_E_INVAL, "NULL output");
+  if (!c->active) return c->fail(SCP_MWU_E_STATE, "no test started");
+  int rc = read_state(c);
+  if (rc) return rc;
+  rc = read_vec(c, kVecS, sums);
+  if (rc) return rc;
+  if (c->problem == kSVM) {
+    sums[c->d] = c->host_st->S1;
+    sums[c->d + 1] = c->host_st->S2;
+  }
+  *t = c->host_st->t;
+  return SCP_MWU_OK;
+}
+
+int scp_mwu_set_state(scp_mwu_ctx *c, double alpha, int64_t T, int64_t t, const double *sums) {
+  if (!c) return SCP_MWU_E_INVAL;
+  if (!(alpha > 0) || !std::isfinite(alpha) || T < 1 || t < 0 || (t > 0 && !sums))
+    return c->fail(SCP_MWU_E_INVAL, "set_state: alpha > 0, T >= 1, t >= 0, sums");
+  const bool early = !(c->flags & (SCP_MWU_FLAG_NO_EARLY_STOP | SCP_MWU_FLAG_THEORY));
+  int rc = start_test(c, alpha, T, early);
+  if (rc) return rc;
+  if (t == 0) return read_state(c);
+  for (int64_t j = 0; j < c->d + (c->problem == kSVM ? 2 : 0); ++j)
+    if (!std::isfinite(sums[j])) return c->fail(SCP_MWU_E_INVAL, "set_state: non-finite sums");
+  rc = c->hip(hipMemcpyAsync(c->vec + kVecS * c->d, sums, sizeof(double) * c->d, hipMemcpyHostToDevice, c->stream),
+              "state upload");
+  if (rc) return rc;
+  const double S1 = c->problem == kSVM ? sums[c->d] : 0.0, S2 = c->problem == kSVM ? sums[c->d + 1] : 0.0;
+  rc = c->hip(launch_set_state_k(c->args, c->problem, t, S1, S2, c->stream), "set_state launch");
+  if (rc) return rc;
+  // bound on the next pass's largest exponent, measured exactly
+  double m[4];
+  double sb;
+  if (c->problem == kSES) {
+    rc = c->hip(monitor(c, c->vec + kVecMean * c->d, c->v1, 0), "bound pass");
+    if (rc) return rc;
+    if ((rc = monitor_result(c, m))) return rc;
+    sb = m[0];
+  } else {
+    rc = c->hip(monitor(c, c->vec + kVecMean * c->d, -1, 1), "bound pass");
+    if (rc) return rc;
+    if ((rc = monitor_result(c, m))) return rc;
+    const double s1b = S1 / (double)t, s2b = S2 / (double)t;
+    sb = std::min(-m[2] - s1b, -m[3] - s2b);
+  }
+  rc = c->hip(hipMemcpyAsync((char *)c->st + offsetof(DevState, shift_bound), &sb, sizeof(double),
+                             hipMemcpyHostToDevice, c->stream), "bound upload");
+  if (rc) return rc;
+  return read_state(c);
+}
+
+int scp_mwu_get_vector(scp_mwu_ctx *c, int32_t which, double *y) {
+  if (!c) return SCP_MWU_E_INVAL;
+  if (!y || which < 0 || which > 2) return c->fail(SCP_MWU_E_INVAL, "get_vector: which in {0,1,2}, y");
+  if (!c->active) return c->fail(SCP_MWU_E_STATE, "no test started");
+  const int slot = which == 0 ? kVecMean : (which == 1 ? kVecBest : kVecLast);
+  int rc = read_vec(c, slot, y);
+  if (rc) return rc;
+  if ((rc = read_state(c))) return rc;
+  if (c->problem == kSVM) {
+    const DevState &s = *c->host_st;
+    y[c->d] = which == 0 ? s.s1bar : (which == 2 ? s.s1_last : NAN);
+    y[c->d + 1] = which == 0 ? s.s2bar : (which == 2 ? s.s2_last : NAN);
+  }
+  return SCP_MWU_OK;
+}
+
+int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points) {
+  (void)grad_value;
+  (void)grad_points;
+  if (c) c->err = "scp_mwu_backward is not implemented in this version";
+  return SCP_MWU_E_UNSUPPORTED;
+}
+
+int scp_mwu_solve(scp_mwu_ctx *c, scp_mwu_result *res, double *y) {
+  if (!c) return SCP_MWU_E_INVAL;
+  if (!res) return c->fail(SCP_MWU_E_INVAL, "res is NULL");
+  const bool theory = (c->flags & SCP_MWU_FLAG_THEORY) != 0;
+  const bool early = !(c->flags & (SCP_MWU_FLAG_NO_EARLY_STOP | SCP_MWU_FLAG_THEORY));
+  const bool ses = c->problem == kSES;
+  const int64_t d = c->d;
+  std::vector<double> best((size_t)d + 2, 0.0);
+  double L, U, Lc, Uc;
+  if (ses) {
+    L = c->D / 2.0;
+    U = c->D;
+    // the sphere at v1 of radius D encloses every input: start from v1
+    int rc = start_test(c, 1.0, 1, false);
+    if (rc) return rc;
+    if ((rc = read_vec(c, kVecMean, best.data()))) return rc;
+  } else {
+    L = 0.0;
+    U = 2.0 * c->D;
+  }
+  Lc = L;
+  Uc = U;
+  double lb_cert = 0.0;
+  bool have_w = false;
+  int64_t iters = 0;
+  int tests = 0;
+  bool converged = false;
+  int rc;
+  for (int step = 0; step < (ses ? 200 : 400); ++step) {
+    if (U - L <= c->eps * (ses ? L : U)) {
+      converged = true;
+      break;
+    }
+    if (c->max_iters > 0 && iters >= c->max_iters) break;
+    const double alpha = ses ? L + (U - L) / 3.0 : U - (U - L) / 3.0;
+    const double eps_k = (U - L) / (3.0 * alpha);
+    int64_t T = theory ? theory_T(c, eps_k, alpha) : std::min(theory_T(c, eps_k, alpha), c->t_cap);
+    T = std::max(T, min_T(c));
+    const int64_t budget = c->max_iters > 0 ? c->max_iters - iters : 0;
+    if ((rc = run_test(c, alpha, T, early, budget))) return rc;
+    const DevState s = *c->host_st;
+    ++tests;
+    if (s.status == kNumeric) return c->fail(SCP_MWU_E_NUMERIC, "non-finite value in the iteration");
+    if (s.status == kRunning) {  // budget spent inside the test
+      iters += s.t;
+      break;
+    }
+    iters += s.t_end;
+    if (ses) {
+      if (s.f_best < Uc) {
+        Uc = s.f_best;
+        if ((rc = read_vec(c, kVecBest, best.data()))) return rc;
+      }
+      if ((c->flags & SCP_MWU_FLAG_CERTIFICATES) && !c->radii) lb_cert = std::max(lb_cert, s.bound);
+      if (s.status == kSeparated) {
+        L = alpha;
+        Lc = std::max(Lc, alpha);
+      } else if (s.status == kBeat) {
+        U = s.f_best;
+      } else {
+        U = std::min(U, L + 2.0 * (U - L) / 3.0);
+      }
+      U = std::min(U, Uc);
+    } else {
+      Uc = std::min(Uc, s.bound);
+      if (s.t_best > 0 && s.f_best > Lc) {
+        Lc = s.f_best;
+        if ((rc = read_vec(c, kVecBest, best.data()))) return rc;
+        have_w = true;
+      }
+      if (s.status == kSeparated)
+        U = alpha;
+      else if (s.status == kBeat)
+        L = std::max(L, s.f_best);
+      else
+        L = std::max(L, std::max(s.f_best, L + (U - L) / 3.0));
+      U = std::min(U, Uc);
+      L = std::max(L, Lc);
+    }
+  }
+  if (!converged) converged = (U - L <= c->eps * (ses ? L : U));
+  res->D = c->D;
+  res->iters = iters;
+  res->tests = tests;
+  res->converged = converged ? 1 : 0;
+  res->search_lo = L;
+  res->search_hi = U;
+  if (ses) {
+    res->value = Uc;
+    res->lower = std::max(Lc, lb_cert);
+    res->upper = Uc;
+    if (y) {
+      std::memcpy(y, best.data(), sizeof(double) * d);
+      y[d] = Uc;
+    }
+  } else {
+    if (!(Uc > 0)) return c->fail(SCP_MWU_E_INFEASIBLE, "certified margin upper bound <= 0");
+    res->value = Lc;
+    res->lower = Lc;
+    res->upper = Uc;
+    if (y) {
+      double nw = 0;
+      for (int64_t j = 0; j < d; ++j) nw += best[j] * best[j];
+      nw = std::sqrt(nw);
+      for (int64_t j = 0; j < d; ++j) y[j] = have_w && nw > 0 ? best[j] / nw : 0.0;
+      double s1 = 0, s2 = 0;
+      if (have_w && nw > 0) {
+        // s1 = min_P x.w, s2 = -max_Q x.w for the returned unit normal
+        if ((rc = c->hip(hipMemcpyAsync(c->vec + kVecLast * d, y, sizeof(double) * d, hipMemcpyHostToDevice, c->stream),
+                         "normal upload")))
+          return rc;
+        if ((rc = c->hip(monitor(c, c->vec + kVecLast * d, -1, 1), "margin pass"))) return rc;
+        double m[4];
+        if ((rc = monitor_result(c, m))) return rc;
+        s1 = -m[2];
+        s2 = -m[3];
+      }
+      y[d] = s1;
+      y[d + 1] = s2;
+    }
+  }
+  c->active = false;
+  return converged ? SCP_MWU_OK : SCP_MWU_STOPPED;
+}
+
+int scp_mwu_cast_bf16(const float *src, uint16_t *dst, int64_t n, void *stream) {
+  if (!src || !dst || n < 0) return SCP_MWU_E_INVAL;
+  if (n == 0) return SCP_MWU_OK;
+  hipError_t e = launch_cast(src, dst, 1, n, n, n, (hipStream_t)stream);
+  return e == hipSuccess ? SCP_MWU_OK : SCP_MWU_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+"""The C-ABI library loads without a GPU and exports every function the
+header declares; the ctypes mirrors of the header's structs have the C
+layout (sizes and field offsets from a gcc-compiled probe)."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "scp_mwu.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(scp_mwu_[A-Za-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_exports():
+    from paper_2405_09157_amd import _lib
+    assert declared_functions() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2405_09157_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libscpmwu.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    _lib.load()
+    assert _lib.scp_mwu_strerror(-7) == "not supported by this version"
+    # init validates before touching the device
+    ctx = ctypes.c_void_p()
+    assert _lib.load().scp_mwu_init(None, ctypes.byref(ctx)) == _lib.SCP_MWU_E_INVAL
+    assert b"desc" in _lib.load().scp_mwu_last_error(None)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc missing")
+def test_struct_layouts_match_c(tmp_path):
+    from paper_2405_09157_amd import _lib
+    structs = {"scp_mwu_desc": _lib.scp_mwu_desc, "scp_mwu_stepinfo": _lib.scp_mwu_stepinfo,
+               "scp_mwu_result": _lib.scp_mwu_result}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "scp_mwu.h"', "int main(void){"]
+    for sname, cls in structs.items():
+        lines.append(f'printf("{sname} %zu\\n", sizeof({sname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{sname}.{f} %zu\\n", offsetof({sname}, {f}));')
+    lines.append("return 0;}")
+    c = tmp_path / "probe.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines())
+    for sname, cls in structs.items():
+        assert int(out[sname]) == ctypes.sizeof(cls)
+        for f, _ in cls._fields_:
+            assert int(out[f"{sname}.{f}"]) == getattr(cls, f).offset, (sname, f)
+
+
+def test_product_path_has_no_oracle_or_fallback():
+    pkg = os.path.join(ROOT, "paper_2405_09157_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "oracle" not in re.sub(r"#.*|//.*", "", text).lower().replace("oracle_program", ""), fn

@@ -1,0 +1,308 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances.  The kernels compute every point-data operation in binary64
+(distances, dot products, exponentials, weighted sums), so the only
+difference from the oracle is the order of floating-point summation.  The
+bars written below are the spec bars (1e-6 relative for F32 storage,
+1e-3 for BF16 storage against the original points) and, where noted, the
+tighter bound the arithmetic gives: summation-order error of an n-term FP64
+sum is below n * 2^-53 relative to the sum of magnitudes, times the
+cancellation ratio of the weighted sum W; 1e-9 covers n <= 1e6 with a
+cancellation ratio up to 1e2.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ses as oses
+from oracle import svm as osvm
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = 1e-9
+NORTH_STAR_F32 = 1e-6
+NORTH_STAR_BF16 = 1e-3
+
+
+def dev(x, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def mwu(*a, **k):
+    import paper_2405_09157_amd as scp
+    return scp.MWU(*a, **k)
+
+
+def bf16_points(V32):
+    """BF16 storage of FP32 points (nearest-even), as bits and as the values it holds."""
+    h = synth.bf16_round(V32.astype(np.float32))
+    return h, synth.bf16_to_f32(h).astype(np.float64)
+
+
+# ------------------------------------------------------------------ SES
+def ses_compare_steps(V_dev, V64, alpha, T, K, flags_noearly=True, radii=None, v1=0, tol=TIGHT, **kw):
+    import paper_2405_09157_amd as scp
+    P = oses.setup(V64, radii, v1)
+    eta = math.sqrt(math.log(P.r) / T)
+    g = None
+    if radii is not None:
+        import torch
+        g = torch.from_numpy(radii).cuda()
+    m = mwu(V_dev, "ses", radii=g, v1=v1, flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP if flags_noearly else 0, **kw)
+    assert abs(m.D - P.D) <= 1e-12 * P.D
+    S = np.zeros(V64.shape[1])
+    worst = dict(u=0.0, ubar=0.0, value=0.0, logC=0.0, f=0.0)
+    for t in range(1, K + 1):
+        st = oses.step(P, S, t - 1, alpha, eta)
+        info = m.step(alpha, T, 1)
+        u_gpu = np.array(m.vector(2))
+        worst["u"] = max(worst["u"], np.linalg.norm(u_gpu - st["u"]) / alpha)
+        worst["value"] = max(worst["value"], abs(info["value"] - st["value"]) / st["scale"])
+        worst["logC"] = max(worst["logC"], abs(info["log_trace"] - st["logC"]) / max(1.0, abs(st["logC"])))
+        if st["f_prev"] is not None:
+            worst["f"] = max(worst["f"], abs(info["f_last"] - st["f_prev"]) / st["f_prev"])
+        if st["separated"]:
+            assert info["outcome_name"] == "separated" and info["t_end"] == t
+            break
+        assert info["outcome_name"] == "running", (t, info)
+        S = st["S"]
+        ubar_gpu = np.array(m.vector(0))
+        worst["ubar"] = max(worst["ubar"], np.linalg.norm(ubar_gpu - st["ubar"]) / alpha)
+    m.close()
+    for k, v in worst.items():
+        assert v <= tol, (k, v, worst)
+    return worst
+
+
+@pytest.mark.parametrize("n,d", [(3000, 100), (1001, 3), (517, 64), (2000, 256), (300, 7), (64, 1), (2, 5)])
+def test_ses_step_parity_f32(n, d):
+    import torch
+    V = synth.ses_gaussian_outliers(n, d, seed=n + d).astype(np.float32)
+    V64 = V.astype(np.float64)
+    P = oses.setup(V64)
+    ses_compare_steps(dev(V, torch.float32), V64, 0.8 * P.D, 3000, 40)
+
+
+def test_ses_step_parity_f64_small_config():
+    import torch
+    V = synth.ses_uniform(2000, 3, 0)
+    P = oses.setup(V)
+    ses_compare_steps(dev(V, torch.float64), V, 0.65 * P.D, 20000, 60)
+
+
+def test_ses_step_parity_spheres_and_v1():
+    import torch
+    V = synth.ses_uniform(700, 5, 3).astype(np.float32)
+    V64 = V.astype(np.float64)
+    g = np.random.Generator(np.random.PCG64(5)).uniform(0, 0.1, 700)
+    P = oses.setup(V64, g, 699)
+    ses_compare_steps(dev(V, torch.float32), V64, 0.7 * P.D, 1000, 40, radii=g, v1=699)
+
+
+def test_ses_step_parity_strided_rows():
+    import torch
+    Vbig = synth.ses_gaussian_outliers(999, 36, seed=4).astype(np.float32)
+    Vt = dev(Vbig, torch.float32)[:, :33]          # ld = 36 > d = 33
+    V64 = Vbig[:, :33].astype(np.float64)
+    P = oses.setup(V64)
+    ses_compare_steps(Vt, V64, 0.75 * P.D, 500, 30)
+
+
+def test_ses_separation_iteration_matches():
+    import torch
+    V = synth.ses_uniform(1500, 3, 2).astype(np.float32)
+    V64 = V.astype(np.float64)
+    P = oses.setup(V64)
+    alpha = 0.55 * P.D      # below OPT for a cube sample: the test must separate
+    ses_compare_steps(dev(V, torch.float32), V64, alpha, 400, 400)
+
+
+def test_ses_bf16_step_parity_on_stored_values():
+    import torch
+    V = synth.ses_gaussian_outliers(4000, 100, seed=9).astype(np.float32)
+    h, Vq = bf16_points(V)
+    Vb = torch.from_numpy(h.view(np.int16)).cuda().view(torch.bfloat16)
+    P = oses.setup(Vq)
+    ses_compare_steps(Vb, Vq, 0.8 * P.D, 3000, 30)
+    # the library's own F32 -> BF16 conversion feeds the same values
+    ses_compare_steps(dev(V, torch.float32), Vq, 0.8 * P.D, 3000, 10, storage="bf16")
+
+
+def test_bf16_cast_bit_exact():
+    import torch
+    import paper_2405_09157_amd as scp
+    g = np.random.Generator(np.random.PCG64(11))
+    x = np.concatenate([g.standard_normal(300001).astype(np.float32) * 100,
+                        (g.integers(0, 1 << 15, 4096, dtype=np.uint32) << 16 | 0x8000).view(np.float32)])
+    x = x[np.isfinite(x)]
+    src = torch.from_numpy(x).cuda()
+    dst = torch.empty(x.size, dtype=torch.int16, device="cuda")
+    scp.scp_mwu_cast_bf16(src.data_ptr(), dst.data_ptr(), x.size, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert np.array_equal(dst.cpu().numpy().view(np.uint16), synth.bf16_round(x))
+
+
+def test_ses_fixed_schedule_and_determinism():
+    import torch
+    import paper_2405_09157_amd as scp
+    V = synth.ses_gaussian_outliers(20000, 100, seed=1).astype(np.float32)
+    V64 = V.astype(np.float64)
+    P = oses.setup(V64)
+    # alpha above OPT (an actual enclosing radius), so the test cannot separate
+    alpha, T = 1.01 * oses.monitor(P, V64.mean(axis=0)), 300
+    eta = math.sqrt(math.log(P.r) / T)
+    r = oses.ftp(P, alpha, T, eta, early_stop=False)
+    Vd = dev(V, torch.float32)
+    outs = []
+    for rep in range(2):
+        m = mwu(Vd, "ses", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP, chunk=32)
+        info = m.step(alpha, T, T + 1)
+        outs.append((np.array(m.vector(0)), info))
+        m.close()
+    (ub0, i0), (ub1, i1) = outs
+    assert np.array_equal(ub0, ub1) and i0["f_best"] == i1["f_best"]       # bitwise reproducible
+    assert r.outcome == oses.T_REACHED and i0["outcome_name"] == "t_reached" and i0["t_end"] == T
+    assert np.linalg.norm(ub0 - r.S / T) / alpha <= TIGHT
+    assert abs(i0["f_best"] - r.f_best) / r.f_best <= TIGHT
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_ses_end_to_end_small_config(seed):
+    import torch
+    V = synth.ses_uniform(2000, 3, seed)
+    ref = oses.solve(V, eps=1e-3)
+    m = mwu(dev(V, torch.float64), "ses", eps=1e-3)
+    out = m.solve()
+    m.close()
+    assert out["tests"] == len(ref.steps) and out["iters"] == ref.iters
+    assert abs(out["radius"] - ref.radius) / ref.radius <= NORTH_STAR_F32
+    assert np.linalg.norm(np.array(out["center"]) - ref.center) / ref.radius <= NORTH_STAR_F32
+    assert abs(out["lower"] - ref.lower) / ref.radius <= NORTH_STAR_F32
+    assert bool(out["converged"]) == ref.converged
+
+
+def test_ses_bf16_vs_original_points():
+    import torch
+    V = synth.ses_uniform(2000, 3, 1).astype(np.float32)
+    ref = oses.solve(V.astype(np.float64), eps=1e-3)
+    m = mwu(dev(V, torch.float32), "ses", eps=1e-3, storage="bf16")
+    out = m.solve()
+    m.close()
+    assert abs(out["radius"] - ref.radius) / ref.radius <= NORTH_STAR_BF16 * 10  # see below
+    # BF16 keeps 8 significand bits: each coordinate moves by up to 2^-9 relative,
+    # so radii differ by up to ~2^-9 * max|v| / R (about 4e-3 here); the
+    # spec 1e-3 bar is checked at scale on the large configuration.
+
+
+def test_ses_state_roundtrip_and_resume():
+    import torch
+    import paper_2405_09157_amd as scp
+    V = synth.ses_gaussian_outliers(5000, 20, seed=3).astype(np.float32)
+    V64 = V.astype(np.float64)
+    P = oses.setup(V64)
+    alpha, T = 0.8 * P.D, 1000
+    eta = math.sqrt(math.log(P.r) / T)
+    m = mwu(dev(V, torch.float32), "ses", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP)
+    m.step(alpha, T, 25)
+    sums, t = m.get_state()
+    assert t == 25
+    m.set_state(alpha, T, t, sums)          # resume from a checkpoint
+    info = m.step(alpha, T, 1)
+    st = oses.step(P, np.array(sums), t, alpha, eta)
+    assert np.linalg.norm(np.array(m.vector(2)) - st["u"]) / alpha <= TIGHT
+    assert abs(info["f_last"] - st["f_prev"]) / st["f_prev"] <= TIGHT
+    m.close()
+
+
+def test_invalid_descriptors_raise():
+    import torch
+    import paper_2405_09157_amd as scp
+    V = dev(np.zeros((1, 3), np.float32), torch.float32)
+    with pytest.raises(scp.ScpMwuError):
+        mwu(V, "ses")                          # n < 2
+    V = dev(np.ones((10, 3), np.float32), torch.float32)
+    with pytest.raises(scp.ScpMwuError):
+        mwu(V, "ses")                          # all points coincide: D = 0
+    X = dev(np.random.default_rng(0).standard_normal((10, 3)).astype(np.float32), torch.float32)
+    with pytest.raises(scp.ScpMwuError):
+        mwu(X, "svm", n_pos=0)
+    Xn = np.ones((10, 3), np.float32)
+    Xn[3, 1] = np.nan
+    with pytest.raises(scp.ScpMwuError):
+        mwu(dev(Xn, torch.float32), "ses")
+    m = mwu(X, "ses")
+    with pytest.raises(scp.ScpMwuError):
+        m.step(-1.0, 10, 1)
+    with pytest.raises(scp.ScpMwuError):
+        scp.scp_mwu_backward(m.ctx, 1.0, 0)
+    m.close()
+
+
+# ------------------------------------------------------------------ SVM
+def svm_compare_steps(X_dev, X64, n_pos, alpha, T, K, tol=TIGHT, **kw):
+    import paper_2405_09157_amd as scp
+    Pb = osvm.setup(X64, n_pos)
+    eta = math.sqrt(math.log(Pb.r) / T)
+    m = mwu(X_dev, "svm", n_pos=n_pos, flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP, **kw)
+    assert abs(m.D - Pb.D) <= 1e-12 * Pb.D
+    Sw, S1, S2 = np.zeros(X64.shape[1]), 0.0, 0.0
+    worst = dict(w=0.0, wbar=0.0, value=0.0, logC=0.0, f=0.0, ub=0.0)
+    ub_best = math.inf
+    for t in range(1, K + 1):
+        st = osvm.step(Pb, Sw, S1, S2, t - 1, alpha, eta)
+        ub_best = min(ub_best, st["ub"])
+        info = m.step(alpha, T, 1)
+        y = np.array(m.vector(2))
+        worst["w"] = max(worst["w"], np.linalg.norm(y[:-2] - st["w"]))
+        worst["value"] = max(worst["value"], abs(info["value"] - st["value"]) / st["scale"])
+        worst["logC"] = max(worst["logC"], abs(info["log_trace"] - st["logC"]) / max(1.0, abs(st["logC"])))
+        worst["ub"] = max(worst["ub"], abs(info["bound"] - ub_best) / ub_best)
+        if st["f_prev"] is not None and st["f_prev"] > 0:
+            worst["f"] = max(worst["f"], abs(info["f_last"] - st["f_prev"]) / st["f_prev"])
+        if st["separated"]:
+            assert info["outcome_name"] == "separated" and info["t_end"] == t
+            break
+        assert info["outcome_name"] == "running", (t, info)
+        Sw, S1, S2 = st["Sw"], st["S1"], st["S2"]
+        yb = np.array(m.vector(0))
+        worst["wbar"] = max(worst["wbar"], np.linalg.norm(yb[:-2] - Sw / t))
+    m.close()
+    for k, v in worst.items():
+        assert v <= tol, (k, v, worst)
+    return worst
+
+
+@pytest.mark.parametrize("n1,n2,d", [(1500, 1300, 256), (700, 900, 16), (40, 25, 2), (1, 1, 3)])
+def test_svm_step_parity_f32(n1, n2, d):
+    import torch
+    X, _ = synth.svm_planted(n1, n2, d, seed=d)
+    X = X.astype(np.float32)
+    X64 = X.astype(np.float64)
+    Pb = osvm.setup(X64, n1)
+    svm_compare_steps(dev(X, torch.float32), X64, n1, 0.5 * Pb.D, 2000, 40)
+
+
+def test_svm_separation_matches():
+    import torch
+    X, _ = synth.svm_planted(800, 800, 8, seed=2, shift=0.5, margin=0.2)
+    X = X.astype(np.float32)
+    X64 = X.astype(np.float64)
+    Pb = osvm.setup(X64, 800)
+    svm_compare_steps(dev(X, torch.float32), X64, 800, 1.5 * Pb.D, 3000, 300)
+
+
+def test_svm_end_to_end():
+    import torch
+    X, _ = synth.svm_planted(600, 500, 2, seed=5, shift=0.6, margin=0.3)
+    ref = osvm.solve(X, 600, eps=1e-3)
+    m = mwu(dev(X, torch.float64), "svm", n_pos=600, eps=1e-3)
+    out = m.solve()
+    m.close()
+    assert out["tests"] == len(ref.steps) and out["iters"] == ref.iters
+    assert abs(out["value"] - ref.margin) / ref.margin <= NORTH_STAR_F32
+    assert abs(out["upper"] - ref.upper) / ref.upper <= NORTH_STAR_F32
+    assert np.linalg.norm(np.array(out["w"]) - ref.w) <= NORTH_STAR_F32
+    assert abs(out["s1"] + out["s2"] - ref.margin) / ref.margin <= NORTH_STAR_F32
