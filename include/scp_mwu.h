@@ -248,14 +248,15 @@ int scp_mwu_set_state(scp_mwu_ctx *ctx, double alpha, int64_t T, int64_t t,
 int scp_mwu_get_vector(scp_mwu_ctx *ctx, int32_t which, double *y);
 
 /*
- * Measurement helper: run k >= 1 further passes (MWU iterations) of the
- * current test, each bracketed by a pair of HIP events recorded on the
- * context's stream, and return the mean elapsed time per pass in
- * milliseconds (host output *ms_mean).  The passes advance the test exactly
- * as scp_mwu_step does.  E_INVAL (k < 1, NULL), E_STATE (no test started),
- * E_HIP.
+ * Measurement helper: run k >= 1 further MWU iterations of the current test
+ * with HIP events recorded on the context's stream before each streaming
+ * pass, between the pass and its combine/epilogue kernel, and after it.
+ * Returns (host outputs, milliseconds) the mean duration of the streaming
+ * pass kernel (*ms_pass) and of the whole iteration (*ms_iter).  The
+ * iterations advance the test exactly as scp_mwu_step does.
+ * E_INVAL (k < 1, NULL), E_STATE (no test started), E_HIP.
  */
-int scp_mwu_time_passes(scp_mwu_ctx *ctx, int32_t k, double *ms_mean);
+int scp_mwu_time_passes(scp_mwu_ctx *ctx, int32_t k, double *ms_pass, double *ms_iter);
 
 /* D of the problem (see scp_mwu_result.D); E_INVAL on NULL. */
 int scp_mwu_get_D(const scp_mwu_ctx *ctx, double *D);

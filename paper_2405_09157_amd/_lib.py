@@ -118,7 +118,7 @@ def load() -> ctypes.CDLL:
         "scp_mwu_last_error": (ctypes.c_char_p, [vp]),
         "scp_mwu_strerror": (ctypes.c_char_p, [i32]),
         "scp_mwu_cast_bf16": (i32, [vp, vp, i64, vp]),
-        "scp_mwu_time_passes": (i32, [vp, i32, P(f64)]),
+        "scp_mwu_time_passes": (i32, [vp, i32, P(f64), P(f64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -200,10 +200,11 @@ def scp_mwu_cast_bf16(src_ptr: int, dst_ptr: int, n: int, stream: int = 0) -> No
     _check(load().scp_mwu_cast_bf16(src_ptr, dst_ptr, n, stream))
 
 
-def scp_mwu_time_passes(ctx, k: int) -> float:
-    ms = ctypes.c_double()
-    _check(load().scp_mwu_time_passes(ctx, k, ctypes.byref(ms)), ctx)
-    return ms.value
+def scp_mwu_time_passes(ctx, k: int):
+    """(mean streaming-pass kernel ms, mean whole-iteration ms) over k iterations."""
+    mp, mi = ctypes.c_double(), ctypes.c_double()
+    _check(load().scp_mwu_time_passes(ctx, k, ctypes.byref(mp), ctypes.byref(mi)), ctx)
+    return mp.value, mi.value
 
 
 def scp_mwu_strerror(code: int) -> str:

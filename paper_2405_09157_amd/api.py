@@ -116,8 +116,8 @@ class MWU:
     def vector(self, which: int):
         return L.scp_mwu_get_vector(self.ctx, which, self.d, self.svm)
 
-    def time_passes(self, k: int) -> float:
-        """Mean HIP-event time (ms) of k further passes of the current test."""
+    def time_passes(self, k: int):
+        """(pass-kernel ms, whole-iteration ms): HIP-event means over k further iterations."""
         return L.scp_mwu_time_passes(self.ctx, int(k))
 
     def eta(self, T: int) -> float:

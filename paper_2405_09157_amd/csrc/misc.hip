@@ -20,7 +20,7 @@ __global__ __launch_bounds__(kBlock) void set_state_kernel(PassArgs a, int probl
       a.vec[kVecMean * d + c] = y;
       wn += y * y;
     }
-  wn = block_sum(wn, s_red);
+  wn = block_sum<kBlock>(wn, s_red);
   if (tid == 0) {
     st->t = t;
     if (problem == kSVM) {

@@ -15,9 +15,12 @@ constexpr int kG = 16;
 constexpr int kRowsPerStep = kWave / kG;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-// Workgroups whose partial sums are combined by the last finisher of their
-// group before the final combine (two-level, fixed-order reduction).
-constexpr int kGroup = 16;
+// The streaming pass runs 8 waves per workgroup, one workgroup per compute
+// unit; its per-workgroup records are combined by one workgroup of
+// kCombBlock threads.
+constexpr int kPassWaves = 8;
+constexpr int kPassBlock = kPassWaves * kWave;
+constexpr int kCombBlock = 1024;
 // Maximum dimension supported by the streaming pass (16 lanes x 32 columns).
 constexpr int kMaxD = 512;
 // Width of a workgroup's partial record: two d-vectors, 4 sums, 4 maxima.
@@ -86,9 +89,7 @@ struct PassArgs {
   int64_t n_pos;          // SVM class boundary
   DevState *st;
   double *vec;            // kNumVec * d
-  double *partials;       // gridDim.x * partial_width(d)
-  double *gpartials;      // ceil(gridDim.x / kGroup) * partial_width(d)
-  unsigned *tickets;      // ceil(gridDim.x / kGroup) + 1 counters, zero at rest
+  double *partials;       // gridDim.x * partial_width(d), 16-byte aligned
 };
 
 // Parameters of a new alpha-feasibility test (written by the init kernel).
@@ -108,6 +109,7 @@ struct LaunchCfg {
 
 #define SCPMWU_DECLARE_TYPED(name)                                                              \
   hipError_t launch_pass_##name(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s); \
+  hipError_t launch_epilogue_##name(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s); \
   hipError_t launch_monitor_##name(int grid, const PassArgs &a, const double *center,            \
                                    int64_t exclude, int mode, double *out, hipStream_t s);      \
   hipError_t launch_init_##name(const PassArgs &a, const InitParams &p, int problem, hipStream_t s);

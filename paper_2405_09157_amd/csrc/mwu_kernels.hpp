@@ -101,11 +101,12 @@ __device__ __forceinline__ double to_reg<double>(double x) {
 
 // Batch shape: SB load steps of 4 rows; the batch's row data (SB * EPL
 // elements per lane, 64 VGPRs) stays in registers through the three phases.
-template <int EPL, int ESZ>
+template <int EPL, int ESZ, int PROB = kSES>
 struct Shape {
-  static constexpr int LIM = ESZ == 8 ? 32 : 64;
-  static constexpr int SB = (LIM / EPL) < 16 ? ((LIM / EPL) > 0 ? LIM / EPL : 1) : 16;
-  static constexpr int B = SB * kRowsPerStep;  // rows per batch (<= 64)
+  // SVM keeps two binary64 class accumulators per column: half the batch.
+  static constexpr int LIM = (ESZ == 8 ? 32 : 64) / (PROB == kSVM ? 2 : 1);
+  static constexpr int SB = (LIM / EPL) < 8 ? ((LIM / EPL) > 0 ? LIM / EPL : 1) : 8;
+  static constexpr int B = SB * kRowsPerStep;  // rows per batch (<= 32)
 };
 
 // Forces the compiler to keep x in its (narrow) register type across the
@@ -138,13 +139,34 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Sum over the workgroup; every thread must call it; all get the same value.
+// Fixed-order sum / max over the waves of a pass workgroup.
+template <int W>
+__device__ __forceinline__ double sum_waves(const double (*v)[W], int c) {
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < kPassWaves; ++w) r += v[w][c];
+  return r;
+}
+template <int W>
+__device__ __forceinline__ double max_waves(const double (*v)[W], int c) {
+  double r = -INFINITY;
+#pragma unroll
+  for (int w = 0; w < kPassWaves; ++w) r = fmax(r, v[w][c]);
+  return r;
+}
+
+// Sum over a workgroup of NT threads; every thread must call it; all get the
+// same value (fixed order).
+template <int NT>
 __device__ __forceinline__ double block_sum(double v, double *s_red) {
   v = wave_sum(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
   __syncthreads();
-  return (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) r += s_red[w];
+  return r;
 }
 
 // Load one row's EPL columns owned by lane `cl` (zeros outside [0,n) x [0,d)).
@@ -161,66 +183,6 @@ __device__ __forceinline__ void load_row(const T *__restrict__ X, int64_t row, i
     if (rv && (cl * EPL + q * VEC) < d) v = *reinterpret_cast<const VecT<T, VEC> *>(rp + q * VEC);
     raw[q] = v;
   }
-}
-
-// ------------------------------------------------- grid combine (two-level)
-// Writes this workgroup's record, then the last finisher of its group sums
-// the group's records (fixed order) and the last group finisher sums the
-// group records into s_comb.  Returns true only in that final workgroup.
-// Entries [0, nsum) are summed, [nsum, pw) are max-combined.
-__device__ inline bool grid_combine(const PassArgs &a, int pw, int nsum, const double *s_mine,
-                             double *s_comb, int *s_flag) {
-  const int tid = threadIdx.x;
-  const int P = gridDim.x;
-  const int ng = (P + kGroup - 1) / kGroup;
-  const int grp = blockIdx.x / kGroup;
-  double *mine = a.partials + (int64_t)blockIdx.x * pw;
-  for (int c = tid; c < pw; c += kBlock) mine[c] = s_mine[c];
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const int gsize = min(kGroup, P - grp * kGroup);
-    const unsigned prev = atomicAdd(&a.tickets[grp], 1u);
-    *s_flag = (prev == (unsigned)(gsize - 1));
-  }
-  __syncthreads();
-  if (!*s_flag) return false;
-  __threadfence();
-  {
-    const int first = grp * kGroup, cnt = min(kGroup, P - first);
-    double *gdst = a.gpartials + (int64_t)grp * pw;
-    for (int c = tid; c < pw; c += kBlock) {
-      const double *src = a.partials + (int64_t)first * pw + c;
-      double acc = c < nsum ? 0.0 : -INFINITY;
-      for (int j = 0; j < cnt; ++j) {
-        const double v = __builtin_nontemporal_load(src + (int64_t)j * pw);
-        acc = c < nsum ? acc + v : fmax(acc, v);
-      }
-      gdst[c] = acc;
-    }
-  }
-  if (tid == 0) a.tickets[grp] = 0u;
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned prev = atomicAdd(&a.tickets[ng], 1u);
-    *s_flag = (prev == (unsigned)(ng - 1));
-  }
-  __syncthreads();
-  if (!*s_flag) return false;
-  __threadfence();
-  for (int c = tid; c < pw; c += kBlock) {
-    const double *src = a.gpartials + c;
-    double acc = c < nsum ? 0.0 : -INFINITY;
-    for (int j = 0; j < ng; ++j) {
-      const double v = __builtin_nontemporal_load(src + (int64_t)j * pw);
-      acc = c < nsum ? acc + v : fmax(acc, v);
-    }
-    s_comb[c] = acc;
-  }
-  if (tid == 0) a.tickets[ng] = 0u;
-  __syncthreads();
-  return true;
 }
 
 // Section 5 monitor for a mean evaluated by this pass (iteration k-1 >= 1).
@@ -255,7 +217,7 @@ __device__ __forceinline__ int monitor_rules(DevState *st, int64_t k, double f, 
 }
 
 // =========================================================== SES pass
-template <typename T>
+template <typename T, int NT>
 __device__ void ses_epilogue(const PassArgs &a, const double *comb, bool cert, double *s_red,
                              int *s_int) {
   DevState *st = a.st;
@@ -277,7 +239,7 @@ __device__ void ses_epilogue(const PassArgs &a, const double *comb, bool cert, d
   }
   __syncthreads();
   if (s_int[1])
-    for (int c = tid; c < d; c += kBlock) best[c] = ybar[c];
+    for (int c = tid; c < d; c += NT) best[c] = ybar[c];
   if (s_int[0] != kRunning) {
     if (tid == 0) {
       st->status = s_int[0];
@@ -286,22 +248,22 @@ __device__ void ses_epilogue(const PassArgs &a, const double *comb, bool cert, d
     return;
   }
   // W = sum_i a_i (v_i - ubar) from the pass's sum a_i v_i and sum a_i.
-  double Wr[kMaxD / kBlock];
+  double Wr[(kMaxD + NT - 1) / NT];
   double p = 0.0;
 #pragma unroll
-  for (int j = 0; j < kMaxD / kBlock; ++j) {
-    const int c = tid + j * kBlock;
+  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
+    const int c = tid + j * NT;
     Wr[j] = c < d ? comb[c] - Asum * ybar[c] : 0.0;
     p += Wr[j] * Wr[j];
   }
-  const double nW = sqrt(block_sum(p, s_red));
+  const double nW = sqrt(block_sum<NT>(p, s_red));
   const double alpha = st->alpha, g1 = st->gamma1;
   const T *v1 = reinterpret_cast<const T *>(a.X) + a.v1 * a.ld;
-  double u[kMaxD / kBlock];
+  double u[(kMaxD + NT - 1) / NT];
   double q = 0.0;
 #pragma unroll
-  for (int j = 0; j < kMaxD / kBlock; ++j) {
-    const int c = tid + j * kBlock;
+  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
+    const int c = tid + j * NT;
     u[j] = 0.0;
     if (c < d) {
       const double v1c = to_f64(v1[c]);
@@ -311,17 +273,17 @@ __device__ void ses_epilogue(const PassArgs &a, const double *comb, bool cert, d
   }
   // sum_i (u - v_i).w_i + (alpha - gamma_i) s_i, scaled by sqrt2 C e^{-M}:
   // (u - ubar).W - sum (e+ - e-) d_i + alpha sum b_i - sum gamma_i b_i.
-  const double dotp = block_sum(q, s_red);
+  const double dotp = block_sum<NT>(q, s_red);
   const double obj = dotp - Esum + alpha * Bsum - Gsum;
   const double scale = alpha * (nW + Bsum);
   double lb2 = 0.0;
   if (cert) {
     double cc = 0.0;
-    for (int c = tid; c < d; c += kBlock) {
+    for (int c = tid; c < d; c += NT) {
       const double cv = comb[d + c] - Bsum * ybar[c];  // sum_i b_i (v_i - ubar)
       cc += cv * cv;
     }
-    const double cn2 = block_sum(cc, s_red);
+    const double cn2 = block_sum<NT>(cc, s_red);
     lb2 = BD2 / Bsum - cn2 / (Bsum * Bsum);
   }
   const bool bad = !isfinite(obj) || !(Bsum > 0.0) || !isfinite(nW);
@@ -336,8 +298,8 @@ __device__ void ses_epilogue(const PassArgs &a, const double *comb, bool cert, d
     if (cert && a.radii == nullptr) st->bound = fmax(st->bound, sqrt(fmax(lb2, 0.0)));
   }
 #pragma unroll
-  for (int j = 0; j < kMaxD / kBlock; ++j) {
-    const int c = tid + j * kBlock;
+  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
+    const int c = tid + j * NT;
     if (c < d) last[c] = u[j];
   }
   if (bad || separated) {
@@ -349,8 +311,8 @@ __device__ void ses_epilogue(const PassArgs &a, const double *comb, bool cert, d
   }
   double dl = 0.0;
 #pragma unroll
-  for (int j = 0; j < kMaxD / kBlock; ++j) {
-    const int c = tid + j * kBlock;
+  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
+    const int c = tid + j * NT;
     if (c < d) {
       const double s = Sv[c] + u[j];
       Sv[c] = s;
@@ -360,7 +322,7 @@ __device__ void ses_epilogue(const PassArgs &a, const double *comb, bool cert, d
       ybar[c] = yn;
     }
   }
-  const double Delta = sqrt(block_sum(dl, s_red));
+  const double Delta = sqrt(block_sum<NT>(dl, s_red));
   if (tid == 0) {
     // ||v_i - ubar(k)|| <= ||v_i - ubar(k-1)|| + ||ubar(k) - ubar(k-1)||
     st->shift_bound = gmax + Delta;
@@ -369,18 +331,15 @@ __device__ void ses_epilogue(const PassArgs &a, const double *comb, bool cert, d
 }
 
 template <typename T, int EPL, int VEC, bool CERT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
+__global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
 void ses_pass_kernel(PassArgs a) {
   using Sh = Shape<EPL, (int)sizeof(typename RegT<T>::type)>;
   constexpr int SB = Sh::SB, B = Sh::B;
-  __shared__ double s_part[kWavesPerBlock][B][kG + 1];
-  __shared__ double s_wa[kWavesPerBlock][B];
-  __shared__ double s_wb[kWavesPerBlock][CERT ? B : 1];
-  __shared__ double s_vec[kWavesPerBlock][kG * EPL];
-  __shared__ double s_sc[kWavesPerBlock][8];
-  __shared__ double s_rec[2 * kMaxD + 8];
-  __shared__ double s_red[kWavesPerBlock];
-  __shared__ int s_int[4];
+  __shared__ double s_part[kPassWaves][B][kG + 1];
+  __shared__ double s_wa[kPassWaves][B];
+  __shared__ double s_wb[kPassWaves][CERT ? B : 1];
+  __shared__ double s_vec[kPassWaves][kG * EPL];
+  __shared__ double s_sc[kPassWaves][8];
 
   DevState *st = a.st;
   if (st->status != kRunning) return;
@@ -410,8 +369,8 @@ void ses_pass_kernel(PassArgs a) {
   double asum = 0.0, bsum = 0.0, esum = 0.0, gsum = 0.0, bd2 = 0.0, gmax = -INFINITY, fall = -INFINITY;
 
   const int64_t nb = (n + B - 1) / B;
-  const int64_t GW = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t b = (int64_t)blockIdx.x * kWavesPerBlock + wave; b < nb; b += GW) {
+  const int64_t GW = (int64_t)gridDim.x * kPassWaves;
+  for (int64_t b = (int64_t)blockIdx.x * kPassWaves + wave; b < nb; b += GW) {
     const int64_t r0 = b * B;
     using R = typename RegT<T>::type;
     R xs[SB][EPL];
@@ -506,8 +465,8 @@ void ses_pass_kernel(PassArgs a) {
     s_sc[wave][6] = fall;
   }
   __syncthreads();
-  for (int c = tid; c < d; c += kBlock)
-    s_rec[c] = (s_vec[0][c] + s_vec[1][c]) + (s_vec[2][c] + s_vec[3][c]);
+  double *rec = a.partials + (int64_t)blockIdx.x * pw;
+  for (int c = tid; c < d; c += kPassBlock) rec[c] = sum_waves(s_vec, c);
   __syncthreads();
   if (CERT) {
 #pragma unroll
@@ -519,28 +478,24 @@ void ses_pass_kernel(PassArgs a) {
 #pragma unroll
       for (int k = 0; k < EPL; ++k) s_vec[wave][cl * EPL + k] = cacc[k];
     __syncthreads();
-    for (int c = tid; c < d; c += kBlock)
-      s_rec[d + c] = (s_vec[0][c] + s_vec[1][c]) + (s_vec[2][c] + s_vec[3][c]);
+    for (int c = tid; c < d; c += kPassBlock) rec[d + c] = sum_waves(s_vec, c);
   } else {
-    for (int c = tid; c < d; c += kBlock) s_rec[d + c] = 0.0;
+    for (int c = tid; c < d; c += kPassBlock) rec[d + c] = 0.0;
   }
   if (tid < 8) {
     double v;
     if (tid < 5)
-      v = (s_sc[0][tid] + s_sc[1][tid]) + (s_sc[2][tid] + s_sc[3][tid]);
+      v = sum_waves(s_sc, tid);
     else if (tid < 7)
-      v = fmax(fmax(s_sc[0][tid], s_sc[1][tid]), fmax(s_sc[2][tid], s_sc[3][tid]));
+      v = max_waves(s_sc, tid);
     else
       v = -INFINITY;
-    s_rec[2 * d + tid] = v;
+    rec[2 * d + tid] = v;
   }
-  __syncthreads();
-  if (!grid_combine(a, pw, 2 * d + 5, s_rec, s_rec, s_int)) return;
-  ses_epilogue<T>(a, s_rec, CERT, s_red, s_int);
 }
 
 // =========================================================== SVM pass
-template <typename T>
+template <typename T, int NT>
 __device__ void svm_epilogue(const PassArgs &a, const double *comb, double *s_red, int *s_int) {
   DevState *st = a.st;
   const int d = (int)a.d;
@@ -564,7 +519,7 @@ __device__ void svm_epilogue(const PassArgs &a, const double *comb, double *s_re
   }
   __syncthreads();
   if (s_int[1])
-    for (int c = tid; c < d; c += kBlock) best[c] = wbar[c];
+    for (int c = tid; c < d; c += NT) best[c] = wbar[c];
   if (s_int[0] != kRunning) {
     if (tid == 0) {
       st->status = s_int[0];
@@ -576,7 +531,7 @@ __device__ void svm_epilogue(const PassArgs &a, const double *comb, double *s_re
   const double *AP = comb, *AQ = comb + d;
   double p = 0.0, pu = 0.0;
   const bool both = T1 > 0.0 && T2 > 0.0;
-  for (int c = tid; c < d; c += kBlock) {
+  for (int c = tid; c < d; c += NT) {
     const double V = AP[c] - AQ[c];
     p += V * V;
     if (both) {
@@ -584,8 +539,8 @@ __device__ void svm_epilogue(const PassArgs &a, const double *comb, double *s_re
       pu += U * U;
     }
   }
-  const double nV = sqrt(block_sum(p, s_red));
-  const double ub = both ? sqrt(block_sum(pu, s_red)) : INFINITY;
+  const double nV = sqrt(block_sum<NT>(p, s_red));
+  const double ub = both ? sqrt(block_sum<NT>(pu, s_red)) : INFINITY;
   const double alpha = st->alpha, D = st->D;
   const double s1 = (T1 <= T2) ? D : alpha - D;
   const double s2 = alpha - s1;
@@ -603,10 +558,10 @@ __device__ void svm_epilogue(const PassArgs &a, const double *comb, double *s_re
     st->s1_last = s1;
     st->s2_last = s2;
   }
-  double w[kMaxD / kBlock];
+  double w[(kMaxD + NT - 1) / NT];
 #pragma unroll
-  for (int j = 0; j < kMaxD / kBlock; ++j) {
-    const int c = tid + j * kBlock;
+  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
+    const int c = tid + j * NT;
     w[j] = 0.0;
     if (c < d) {
       w[j] = nV > 0.0 ? (AP[c] - AQ[c]) / nV : 0.0;
@@ -622,8 +577,8 @@ __device__ void svm_epilogue(const PassArgs &a, const double *comb, double *s_re
   }
   double dl = 0.0, wn = 0.0;
 #pragma unroll
-  for (int j = 0; j < kMaxD / kBlock; ++j) {
-    const int c = tid + j * kBlock;
+  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
+    const int c = tid + j * NT;
     if (c < d) {
       const double s = Sv[c] + w[j];
       Sv[c] = s;
@@ -634,8 +589,8 @@ __device__ void svm_epilogue(const PassArgs &a, const double *comb, double *s_re
       wbar[c] = yn;
     }
   }
-  const double Dw = sqrt(block_sum(dl, s_red));
-  const double nwb = sqrt(block_sum(wn, s_red));
+  const double Dw = sqrt(block_sum<NT>(dl, s_red));
+  const double nwb = sqrt(block_sum<NT>(wn, s_red));
   if (tid == 0) {
     st->S1 += s1;
     st->S2 += s2;
@@ -651,17 +606,14 @@ __device__ void svm_epilogue(const PassArgs &a, const double *comb, double *s_re
 }
 
 template <typename T, int EPL, int VEC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
+__global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
 void svm_pass_kernel(PassArgs a) {
-  using Sh = Shape<EPL, (int)sizeof(typename RegT<T>::type)>;
+  using Sh = Shape<EPL, (int)sizeof(typename RegT<T>::type), kSVM>;
   constexpr int SB = Sh::SB, B = Sh::B;
-  __shared__ double s_part[kWavesPerBlock][B][kG + 1];
-  __shared__ double s_wa[kWavesPerBlock][B];
-  __shared__ double s_vec[kWavesPerBlock][kG * EPL];
-  __shared__ double s_sc[kWavesPerBlock][8];
-  __shared__ double s_rec[2 * kMaxD + 8];
-  __shared__ double s_red[kWavesPerBlock];
-  __shared__ int s_int[4];
+  __shared__ double s_part[kPassWaves][B][kG + 1];
+  __shared__ double s_wa[kPassWaves][B];
+  __shared__ double s_vec[kPassWaves][kG * EPL];
+  __shared__ double s_sc[kPassWaves][8];
 
   DevState *st = a.st;
   if (st->status != kRunning) return;
@@ -688,8 +640,8 @@ void svm_pass_kernel(PassArgs a) {
   double t1 = 0.0, t2 = 0.0, nminP = -INFINITY, maxQ = -INFINITY, nslmin = -INFINITY;
 
   const int64_t nb = (n + B - 1) / B;
-  const int64_t GW = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t b = (int64_t)blockIdx.x * kWavesPerBlock + wave; b < nb; b += GW) {
+  const int64_t GW = (int64_t)gridDim.x * kPassWaves;
+  for (int64_t b = (int64_t)blockIdx.x * kPassWaves + wave; b < nb; b += GW) {
     const int64_t r0 = b * B;
     using R = typename RegT<T>::type;
     R xv[SB][EPL];
@@ -783,30 +735,73 @@ void svm_pass_kernel(PassArgs a) {
     s_sc[wave][6] = nslmin;
   }
   __syncthreads();
-  for (int c = tid; c < d; c += kBlock)
-    s_rec[c] = (s_vec[0][c] + s_vec[1][c]) + (s_vec[2][c] + s_vec[3][c]);
+  double *rec = a.partials + (int64_t)blockIdx.x * pw;
+  for (int c = tid; c < d; c += kPassBlock) rec[c] = sum_waves(s_vec, c);
   __syncthreads();
   if (g == 0)
 #pragma unroll
     for (int k = 0; k < EPL; ++k) s_vec[wave][cl * EPL + k] = accQ[k];
   __syncthreads();
-  for (int c = tid; c < d; c += kBlock)
-    s_rec[d + c] = (s_vec[0][c] + s_vec[1][c]) + (s_vec[2][c] + s_vec[3][c]);
+  for (int c = tid; c < d; c += kPassBlock) rec[d + c] = sum_waves(s_vec, c);
   if (tid < 8) {
     double v;
     if (tid < 2)
-      v = (s_sc[0][tid] + s_sc[1][tid]) + (s_sc[2][tid] + s_sc[3][tid]);
+      v = sum_waves(s_sc, tid);
     else if (tid < 4)
       v = 0.0;
     else if (tid < 7)
-      v = fmax(fmax(s_sc[0][tid], s_sc[1][tid]), fmax(s_sc[2][tid], s_sc[3][tid]));
+      v = max_waves(s_sc, tid);
     else
       v = -INFINITY;
-    s_rec[2 * d + tid] = v;
+    rec[2 * d + tid] = v;
+  }
+}
+
+// ===================================================== combine + epilogue
+// One workgroup: sums the per-workgroup records of the pass that just ran
+// (fixed order: a transposed pass over record pairs, then over the row
+// groups) and runs the FP64 epilogue of the iteration.  The kernel boundary
+// after the pass makes every record visible; no fences are needed.
+template <typename T, int PROB, bool CERT>
+__global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P) {
+  __shared__ double s_acc[2 * kCombBlock];
+  __shared__ double s_comb[2 * kMaxD + 8];
+  __shared__ double s_red[kCombBlock / 64];
+  __shared__ int s_int[4];
+  DevState *st = a.st;
+  if (st->status != kRunning) return;
+  const int d = (int)a.d;
+  const int pw = partial_width(d);
+  const int nsum = PROB == kSES ? 2 * d + 5 : 2 * d + 4;
+  const int npairs = pw / 2;
+  const int groups = kCombBlock / npairs;
+  const int tid = threadIdx.x;
+  const int j = tid % npairs, grp = tid / npairs;
+  if (grp < groups) {
+    const int c0 = 2 * j;
+    const bool s0 = c0 < nsum, s1 = c0 + 1 < nsum;
+    double acc0 = s0 ? 0.0 : -INFINITY, acc1 = s1 ? 0.0 : -INFINITY;
+#pragma unroll 8
+    for (int b = grp; b < P; b += groups) {
+      const double2 v = *reinterpret_cast<const double2 *>(a.partials + (int64_t)b * pw + c0);
+      acc0 = s0 ? acc0 + v.x : fmax(acc0, v.x);
+      acc1 = s1 ? acc1 + v.y : fmax(acc1, v.y);
+    }
+    s_acc[grp * pw + c0] = acc0;
+    s_acc[grp * pw + c0 + 1] = acc1;
   }
   __syncthreads();
-  if (!grid_combine(a, pw, 2 * d + 4, s_rec, s_rec, s_int)) return;
-  svm_epilogue<T>(a, s_rec, s_red, s_int);
+  for (int c = tid; c < pw; c += kCombBlock) {
+    const bool sm = c < nsum;
+    double r = sm ? 0.0 : -INFINITY;
+    for (int g = 0; g < groups; ++g) r = sm ? r + s_acc[g * pw + c] : fmax(r, s_acc[g * pw + c]);
+    s_comb[c] = r;
+  }
+  __syncthreads();
+  if (PROB == kSES)
+    ses_epilogue<T, kCombBlock>(a, s_comb, CERT, s_red, s_int);
+  else
+    svm_epilogue<T, kCombBlock>(a, s_comb, s_red, s_int);
 }
 
 // ========================================================== monitor pass
@@ -916,11 +911,24 @@ template <typename T, int EPL, int VEC>
 hipError_t launch_pass_t(int problem, bool cert, int grid, const PassArgs &a, hipStream_t s) {
   if (problem == kSES) {
     if (cert)
-      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, true>), dim3(grid), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, true>), dim3(grid), dim3(kPassBlock), 0, s, a);
     else
-      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, false>), dim3(grid), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, false>), dim3(grid), dim3(kPassBlock), 0, s, a);
   } else {
-    hipLaunchKernelGGL((svm_pass_kernel<T, EPL, VEC>), dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((svm_pass_kernel<T, EPL, VEC>), dim3(grid), dim3(kPassBlock), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_epilogue_typed(int problem, bool cert, int grid, const PassArgs &a, hipStream_t s) {
+  if (problem == kSES) {
+    if (cert)
+      hipLaunchKernelGGL((epilogue_kernel<T, kSES, true>), dim3(1), dim3(kCombBlock), 0, s, a, grid);
+    else
+      hipLaunchKernelGGL((epilogue_kernel<T, kSES, false>), dim3(1), dim3(kCombBlock), 0, s, a, grid);
+  } else {
+    hipLaunchKernelGGL((epilogue_kernel<T, kSVM, false>), dim3(1), dim3(kCombBlock), 0, s, a, grid);
   }
   return hipGetLastError();
 }

@@ -6,6 +6,9 @@ namespace scpmwu {
 hipError_t launch_pass_bf16(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
   return launch_pass_typed<uint16_t>(problem, c, a, s);
 }
+hipError_t launch_epilogue_bf16(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
+  return launch_epilogue_typed<uint16_t>(problem, c.cert, c.grid, a, s);
+}
 hipError_t launch_monitor_bf16(int grid, const PassArgs &a, const double *center, int64_t exclude,
                                int mode, double *out, hipStream_t s) {
   return launch_monitor_typed<uint16_t>(grid, a, center, exclude, mode, out, s);

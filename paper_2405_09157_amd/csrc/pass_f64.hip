@@ -6,6 +6,9 @@ namespace scpmwu {
 hipError_t launch_pass_f64(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
   return launch_pass_typed<double>(problem, c, a, s);
 }
+hipError_t launch_epilogue_f64(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
+  return launch_epilogue_typed<double>(problem, c.cert, c.grid, a, s);
+}
 hipError_t launch_monitor_f64(int grid, const PassArgs &a, const double *center, int64_t exclude,
                                int mode, double *out, hipStream_t s) {
   return launch_monitor_typed<double>(grid, a, center, exclude, mode, out, s);

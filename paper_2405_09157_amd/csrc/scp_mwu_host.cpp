@@ -45,8 +45,7 @@ struct scp_mwu_ctx {
   int64_t r = 0;
   // device workspace
   DevState *st = nullptr;
-  double *vec = nullptr, *partials = nullptr, *gpartials = nullptr, *mon = nullptr;
-  unsigned *tickets = nullptr;
+  double *vec = nullptr, *partials = nullptr, *mon = nullptr;
   DevState *host_st = nullptr;  // pinned readback
   int grid = 0;
   LaunchCfg cfg{}, cfg_cert{};
@@ -72,13 +71,31 @@ struct scp_mwu_ctx {
 
 namespace {
 
-hipError_t pass(scp_mwu_ctx *c, bool cert, hipStream_t s) {
+// The streaming pass kernel of one MWU iteration (no epilogue).
+hipError_t pass_kernel(scp_mwu_ctx *c, bool cert, hipStream_t s) {
   const LaunchCfg &cfg = cert ? c->cfg_cert : c->cfg;
   switch (c->dtype) {
     case kF32: return launch_pass_f32(c->problem, cfg, c->args, s);
     case kBF16: return launch_pass_bf16(c->problem, cfg, c->args, s);
     default: return launch_pass_f64(c->problem, cfg, c->args, s);
   }
+}
+
+// The combine + FP64 epilogue kernel of one MWU iteration.
+hipError_t epilogue_kernel(scp_mwu_ctx *c, bool cert, hipStream_t s) {
+  const LaunchCfg &cfg = cert ? c->cfg_cert : c->cfg;
+  switch (c->dtype) {
+    case kF32: return launch_epilogue_f32(c->problem, cfg, c->args, s);
+    case kBF16: return launch_epilogue_bf16(c->problem, cfg, c->args, s);
+    default: return launch_epilogue_f64(c->problem, cfg, c->args, s);
+  }
+}
+
+// One MWU iteration: streaming pass, then combine + epilogue.
+hipError_t pass(scp_mwu_ctx *c, bool cert, hipStream_t s) {
+  hipError_t e = pass_kernel(c, cert, s);
+  if (e != hipSuccess) return e;
+  return epilogue_kernel(c, cert, s);
 }
 
 hipError_t monitor(scp_mwu_ctx *c, const double *center, int64_t exclude, int mode) {
@@ -262,9 +279,7 @@ void scp_mwu_destroy(scp_mwu_ctx *c) {
   hipFree(c->st);
   hipFree(c->vec);
   hipFree(c->partials);
-  hipFree(c->gpartials);
   hipFree(c->mon);
-  hipFree(c->tickets);
   hipFree(c->owned);
   if (c->host_st) hipHostFree(c->host_st);
   delete c;
@@ -354,27 +369,22 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
       break;
     }
   }
-  const int lim = c->dtype == kF64 ? 32 : 64;
-  const int B = std::max(1, std::min(16, lim / epl)) * kRowsPerStep;
+  const int lim = (c->dtype == kF64 ? 32 : 64) / (c->problem == kSVM ? 2 : 1);
+  const int B = std::max(1, std::min(8, lim / epl)) * kRowsPerStep;
   const int64_t nb = (c->n + B - 1) / B;
-  int grid = desc->grid > 0 ? desc->grid : 2 * cus;
-  grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, (nb + kWavesPerBlock - 1) / kWavesPerBlock));
+  int grid = desc->grid > 0 ? desc->grid : cus;
+  grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, (nb + kPassWaves - 1) / kPassWaves));
   c->grid = grid;
   c->cfg = LaunchCfg{grid, epl, vec, false};
   c->cfg_cert = LaunchCfg{grid, epl, vec, true};
 
   const int pw = partial_width((int)c->d);
-  const int ng = (grid + kGroup - 1) / kGroup;
   if (hipMalloc(&c->st, sizeof(DevState)) != hipSuccess ||
       hipMalloc(&c->vec, sizeof(double) * kNumVec * c->d) != hipSuccess ||
       hipMalloc(&c->partials, sizeof(double) * (size_t)grid * pw) != hipSuccess ||
-      hipMalloc(&c->gpartials, sizeof(double) * (size_t)ng * pw) != hipSuccess ||
       hipMalloc(&c->mon, sizeof(double) * (size_t)grid * 4) != hipSuccess ||
-      hipMalloc(&c->tickets, sizeof(unsigned) * (ng + 1)) != hipSuccess ||
       hipHostMalloc((void **)&c->host_st, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
     return fail(SCP_MWU_E_NOMEM, "workspace allocation");
-  if (hipMemsetAsync(c->tickets, 0, sizeof(unsigned) * (ng + 1), c->stream) != hipSuccess)
-    return fail(SCP_MWU_E_HIP, "ticket reset");
   if (hipStreamCreate(&c->cap_stream) != hipSuccess) return fail(SCP_MWU_E_HIP, "capture stream");
 
   PassArgs &a = c->args;
@@ -388,8 +398,6 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   a.st = c->st;
   a.vec = c->vec;
   a.partials = c->partials;
-  a.gpartials = c->gpartials;
-  a.tickets = c->tickets;
 
   // D (one streaming pass): SES distance from v1, SVM largest norm.
   c->r = c->problem == kSES ? 2 * (c->n - 1) : c->n;
@@ -424,30 +432,37 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   return SCP_MWU_OK;
 }
 
-int scp_mwu_time_passes(scp_mwu_ctx *c, int32_t k, double *ms_mean) {
+int scp_mwu_time_passes(scp_mwu_ctx *c, int32_t k, double *ms_pass, double *ms_iter) {
   if (!c) return SCP_MWU_E_INVAL;
-  if (!ms_mean || k < 1) return c->fail(SCP_MWU_E_INVAL, "time_passes: k >= 1 and ms_mean required");
+  if (!ms_pass || !ms_iter || k < 1)
+    return c->fail(SCP_MWU_E_INVAL, "time_passes: k >= 1 and both outputs required");
   if (!c->active) return c->fail(SCP_MWU_E_STATE, "no test started");
-  std::vector<hipEvent_t> ev(2 * (size_t)k, nullptr);
+  // three events per iteration: before the pass, between pass and epilogue, after
+  std::vector<hipEvent_t> ev(3 * (size_t)k, nullptr);
   int rc = SCP_MWU_OK;
   for (auto &e : ev)
     if (!rc) rc = c->hip(hipEventCreate(&e), "event create");
   for (int32_t i = 0; i < k && !rc; ++i) {
-    rc = c->hip(hipEventRecord(ev[2 * i], c->stream), "event record");
-    if (!rc) rc = c->hip(pass(c, false, c->stream), "pass launch");
-    if (!rc) rc = c->hip(hipEventRecord(ev[2 * i + 1], c->stream), "event record");
+    rc = c->hip(hipEventRecord(ev[3 * i], c->stream), "event record");
+    if (!rc) rc = c->hip(pass_kernel(c, false, c->stream), "pass launch");
+    if (!rc) rc = c->hip(hipEventRecord(ev[3 * i + 1], c->stream), "event record");
+    if (!rc) rc = c->hip(epilogue_kernel(c, false, c->stream), "epilogue launch");
+    if (!rc) rc = c->hip(hipEventRecord(ev[3 * i + 2], c->stream), "event record");
   }
   if (!rc) rc = c->hip(hipEventSynchronize(ev.back()), "event sync");
-  double total = 0.0;
+  double tp = 0.0, ti = 0.0;
   for (int32_t i = 0; i < k && !rc; ++i) {
-    float ms = 0.f;
-    rc = c->hip(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]), "event elapsed");
-    total += ms;
+    float a = 0.f, b = 0.f;
+    rc = c->hip(hipEventElapsedTime(&a, ev[3 * i], ev[3 * i + 1]), "event elapsed");
+    if (!rc) rc = c->hip(hipEventElapsedTime(&b, ev[3 * i], ev[3 * i + 2]), "event elapsed");
+    tp += a;
+    ti += b;
   }
   for (auto &e : ev)
     if (e) (void)hipEventDestroy(e);
   if (rc) return rc;
-  *ms_mean = total / k;
+  *ms_pass = tp / k;
+  *ms_iter = ti / k;
   return read_state(c);
 }
 
