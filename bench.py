@@ -83,6 +83,29 @@ def measure(X, storage, steps, warmup, alpha, T=20000):
     return dict(ms_per_step=1e3 * dt / steps, kernel_ms=kms, iter_event_ms=ims, f_last=info["f_last"])
 
 
+def copy_probe(X, reps=10):
+    """Plain streaming references on the same 400 MB: a read-only reduction
+    (torch sum) and a copy (torch copy_).  They give the achievable streaming
+    rate and the scale of the rocprofv3 FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    Y = torch.empty_like(X)
+    out = {}
+    for name, fn in (("read_sum", lambda: X.sum()), ("copy", lambda: Y.copy_(X))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        moved = X.numel() * X.element_size() * (2 if name == "copy" else 1)
+        out[name] = dict(ms=round(ms, 5), GBs=round(moved / (ms * 1e-3) / 1e9, 1), bytes=moved)
+    del Y
+    return out
+
+
 def solve(X, storage):
     import torch
     import paper_2405_09157_amd as scp
@@ -133,6 +156,8 @@ def main(argv=None):
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also time torch read/copy kernels on the same matrix")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -155,6 +180,9 @@ def main(argv=None):
     bf16 = None if a.no_bf16 else measure(X, "bf16", a.steps, a.warmup, alpha)
     if bf16:
         print(f"# bf16: {bf16}", file=sys.stderr, flush=True)
+    probe = copy_probe(X) if a.copy_probe else None
+    if probe:
+        print(f"# streaming references: {probe}", file=sys.stderr, flush=True)
     sol = {}
     if not a.no_solve:
         sol["f32"] = solve(X, None)
@@ -195,6 +223,9 @@ def main(argv=None):
                                           kernel_ms=round(bf16["kernel_ms"], 5), bytes_per_launch=b_bytes))
     if sol:
         line["solve"] = sol
+    if probe:
+        line["streaming_reference"] = probe
+        line["roofline"]["frac_of_read_reference"] = round(ach / probe["read_sum"]["GBs"], 4)
     print(json.dumps(line), flush=True)
     return 0
 

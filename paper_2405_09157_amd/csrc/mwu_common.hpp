@@ -23,8 +23,9 @@ constexpr int kPassBlock = kPassWaves * kWave;
 constexpr int kCombBlock = 1024;
 // Maximum dimension supported by the streaming pass (16 lanes x 32 columns).
 constexpr int kMaxD = 512;
-// Width of a workgroup's partial record: two d-vectors, 4 sums, 4 maxima.
-inline __host__ __device__ int partial_width(int d) { return 2 * d + 8; }
+// Width of a workgroup's record: two d-vectors (each padded to an even
+// length) around 8 scalars, so that pairs of entries are 16-byte aligned.
+inline __host__ __device__ int partial_width(int d) { return 2 * ((d + 1) & ~1) + 8; }
 
 enum Problem : int32_t { kSES = 1, kSVM = 2 };
 enum DType : int32_t { kF32 = 1, kBF16 = 2, kF64 = 3 };

@@ -169,6 +169,41 @@ __device__ __forceinline__ double block_sum(double v, double *s_red) {
   return r;
 }
 
+// ------------------------------------------------------------ buffer loads
+// Rows [r0, r0 + rows) of X as a raw buffer resource: bytes past the last
+// valid element of the last valid row read as zero (hardware range check),
+// so a batch needs no per-row branch, zero fill or 64-bit address update.
+constexpr int32_t kBufWord3 = 0x00020000;  // raw buffer, gfx9 family
+constexpr int32_t kOffInvalid = 0x40000000;  // a lane offset beyond any batch
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const T *X, int64_t r0, int64_t rows, int64_t ld,
+                                                          int d) {
+  const int32_t num = rows > 0 ? (int32_t)(((rows - 1) * ld + d) * (int64_t)sizeof(T)) : 0;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(X + r0 * ld), (short)0, num, kBufWord3);
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ VecT<T, VEC> buf_load(__amdgpu_buffer_rsrc_t r, int32_t voff, int32_t soff) {
+  VecT<T, VEC> v;
+  constexpr int BYTES = VEC * (int)sizeof(T);
+  if constexpr (BYTES == 16) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    __builtin_memcpy(&v, &x, 16);
+  } else if constexpr (BYTES == 8) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    __builtin_memcpy(&v, &x, 8);
+  } else if constexpr (BYTES == 4) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    __builtin_memcpy(&v, &x, 4);
+  } else {
+    static_assert(BYTES == 2, "load width");
+    const auto x = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+    __builtin_memcpy(&v, &x, 2);
+  }
+  return v;
+}
+
 // Load one row's EPL columns owned by lane `cl` (zeros outside [0,n) x [0,d)).
 template <typename T, int EPL, int VEC>
 __device__ __forceinline__ void load_row(const T *__restrict__ X, int64_t row, int64_t n, int d,
@@ -185,151 +220,17 @@ __device__ __forceinline__ void load_row(const T *__restrict__ X, int64_t row, i
   }
 }
 
-// Section 5 monitor for a mean evaluated by this pass (iteration k-1 >= 1).
-// `better` means f improves on f_best; `beat` means f is already better than
-// alpha.  Runs on one thread; returns the new status.
-__device__ __forceinline__ int monitor_rules(DevState *st, int64_t k, double f, bool better,
-                                             bool beat, int *copy_best) {
-  int status = kRunning;
-  st->f_last = f;
-  if (!isfinite(f)) return kNumeric;
-  if (better) {
-    st->f_best = f;
-    st->t_best = k - 1;
-    *copy_best = 1;
-  }
-  if (st->early) {
-    if (beat) {
-      status = kBeat;
-    } else {
-      if (st->f_prev >= 0.0) {  // a previous monitored iteration exists
-        if (st->f_prev > 0.0 && fabs(f - st->f_prev) / st->f_prev < st->delta)
-          st->cnt += 1;
-        else
-          st->cnt = 0;
-      }
-      st->f_prev = f;
-      if (st->cnt >= st->patience) status = kStabilized;
-    }
-  }
-  if (status == kRunning && k - 1 >= st->T) status = kTReached;
-  return status;
-}
+// ------------------------------------------------------- workgroup records
+// Layout of a workgroup record (binary64): [vec0: d] [8 scalars] [vec1: d],
+// the scalar block starting at the even offset dp = d rounded up to even.
+//   SES: vec0 = sum a_i x_i, scalars = (B, E, G, sum b_i d_i^2, A | gmax, fmax),
+//        vec1 = sum b_i x_i (certificate passes only; not read otherwise)
+//   SVM: vec0 = sum_P e_i x_i, scalars = (T1, T2, 0, 0 | -min_P x.w, max_Q x.w,
+//        -min slack), vec1 = sum_Q e_i x_i
+__host__ __device__ inline int rec_dp(int d) { return (d + 1) & ~1; }
+__host__ __device__ inline int rec_width(int d) { return partial_width(d); }
 
 // =========================================================== SES pass
-template <typename T, int NT>
-__device__ void ses_epilogue(const PassArgs &a, const double *comb, bool cert, double *s_red,
-                             int *s_int) {
-  DevState *st = a.st;
-  const int d = (int)a.d;
-  const int tid = threadIdx.x;
-  double *Sv = a.vec + kVecS * d;
-  double *ybar = a.vec + kVecMean * d;
-  double *best = a.vec + kVecBest * d;
-  double *last = a.vec + kVecLast * d;
-  const int64_t k = st->t + 1;  // iteration index of this pass
-  const double Bsum = comb[2 * d + 0], Esum = comb[2 * d + 1], Gsum = comb[2 * d + 2];
-  const double BD2 = comb[2 * d + 3], Asum = comb[2 * d + 4], gmax = comb[2 * d + 5];
-  const double fall = comb[2 * d + 6];
-  if (tid == 0) {
-    int status = kRunning, copy = 0;
-    if (k >= 2) status = monitor_rules(st, k, fall, fall < st->f_best, fall < st->alpha, &copy);
-    s_int[0] = status;
-    s_int[1] = copy;
-  }
-  __syncthreads();
-  if (s_int[1])
-    for (int c = tid; c < d; c += NT) best[c] = ybar[c];
-  if (s_int[0] != kRunning) {
-    if (tid == 0) {
-      st->status = s_int[0];
-      st->t_end = k - 1;
-    }
-    return;
-  }
-  // W = sum_i a_i (v_i - ubar) from the pass's sum a_i v_i and sum a_i.
-  double Wr[(kMaxD + NT - 1) / NT];
-  double p = 0.0;
-#pragma unroll
-  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
-    const int c = tid + j * NT;
-    Wr[j] = c < d ? comb[c] - Asum * ybar[c] : 0.0;
-    p += Wr[j] * Wr[j];
-  }
-  const double nW = sqrt(block_sum<NT>(p, s_red));
-  const double alpha = st->alpha, g1 = st->gamma1;
-  const T *v1 = reinterpret_cast<const T *>(a.X) + a.v1 * a.ld;
-  double u[(kMaxD + NT - 1) / NT];
-  double q = 0.0;
-#pragma unroll
-  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
-    const int c = tid + j * NT;
-    u[j] = 0.0;
-    if (c < d) {
-      const double v1c = to_f64(v1[c]);
-      u[j] = nW > 0.0 ? v1c + (alpha - g1) * (Wr[j] / nW) : v1c;
-      q += (u[j] - ybar[c]) * Wr[j];
-    }
-  }
-  // sum_i (u - v_i).w_i + (alpha - gamma_i) s_i, scaled by sqrt2 C e^{-M}:
-  // (u - ubar).W - sum (e+ - e-) d_i + alpha sum b_i - sum gamma_i b_i.
-  const double dotp = block_sum<NT>(q, s_red);
-  const double obj = dotp - Esum + alpha * Bsum - Gsum;
-  const double scale = alpha * (nW + Bsum);
-  double lb2 = 0.0;
-  if (cert) {
-    double cc = 0.0;
-    for (int c = tid; c < d; c += NT) {
-      const double cv = comb[d + c] - Bsum * ybar[c];  // sum_i b_i (v_i - ubar)
-      cc += cv * cv;
-    }
-    const double cn2 = block_sum<NT>(cc, s_red);
-    lb2 = BD2 / Bsum - cn2 / (Bsum * Bsum);
-  }
-  const bool bad = !isfinite(obj) || !(Bsum > 0.0) || !isfinite(nW);
-  const bool separated = obj < -st->tau * scale;
-  if (tid == 0) {
-    const double M = st->kscale * (double)st->t * (st->shift_bound - alpha);
-    st->value = obj / (M_SQRT2 * Bsum);
-    st->scale = scale / (M_SQRT2 * Bsum);
-    st->log_trace = M + log(Bsum);
-    st->degenerate = !(nW > 0.0);
-    st->cert = cert ? 1 : 0;
-    if (cert && a.radii == nullptr) st->bound = fmax(st->bound, sqrt(fmax(lb2, 0.0)));
-  }
-#pragma unroll
-  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
-    const int c = tid + j * NT;
-    if (c < d) last[c] = u[j];
-  }
-  if (bad || separated) {
-    if (tid == 0) {
-      st->status = bad ? kNumeric : kSeparated;
-      st->t_end = k;
-    }
-    return;
-  }
-  double dl = 0.0;
-#pragma unroll
-  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
-    const int c = tid + j * NT;
-    if (c < d) {
-      const double s = Sv[c] + u[j];
-      Sv[c] = s;
-      const double yn = s / (double)k;
-      const double dd = yn - ybar[c];
-      dl += dd * dd;
-      ybar[c] = yn;
-    }
-  }
-  const double Delta = sqrt(block_sum<NT>(dl, s_red));
-  if (tid == 0) {
-    // ||v_i - ubar(k)|| <= ||v_i - ubar(k-1)|| + ||ubar(k) - ubar(k-1)||
-    st->shift_bound = gmax + Delta;
-    st->t = k;
-  }
-}
-
 template <typename T, int EPL, int VEC, bool CERT>
 __global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
 void ses_pass_kernel(PassArgs a) {
@@ -340,11 +241,13 @@ void ses_pass_kernel(PassArgs a) {
   __shared__ double s_wb[kPassWaves][CERT ? B : 1];
   __shared__ double s_vec[kPassWaves][kG * EPL];
   __shared__ double s_sc[kPassWaves][8];
+  __shared__ double s_ctr[kG * EPL];  // the candidate (ubar or wbar), zero-padded
 
   DevState *st = a.st;
-  if (st->status != kRunning) return;
+  const int32_t status0 = st->status;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, cl = lane & 15;
   const int64_t n = a.n, ld = a.ld;
   const int d = (int)a.d;
@@ -355,12 +258,7 @@ void ses_pass_kernel(PassArgs a) {
   const double *__restrict__ radii = a.radii;
   const int64_t v1 = a.v1;
 
-  double ub[EPL];
-#pragma unroll
-  for (int k = 0; k < EPL; ++k) {
-    const int c = cl * EPL + k;
-    ub[k] = c < d ? ybar[c] : 0.0;
-  }
+  for (int c = tid; c < kG * EPL; c += kPassBlock) s_ctr[c] = c < d ? ybar[c] : 0.0;
   double wacc[EPL], cacc[CERT ? EPL : 1];
 #pragma unroll
   for (int k = 0; k < EPL; ++k) wacc[k] = 0.0;
@@ -370,19 +268,45 @@ void ses_pass_kernel(PassArgs a) {
 
   const int64_t nb = (n + B - 1) / B;
   const int64_t GW = (int64_t)gridDim.x * kPassWaves;
-  for (int64_t b = (int64_t)blockIdx.x * kPassWaves + wave; b < nb; b += GW) {
+  using R = typename RegT<T>::type;
+  R xs[SB][EPL];
+  // lane offsets (bytes) of the lane's column chunks within its row of a
+  // load step; chunks past column d get an offset beyond the buffer range
+  int32_t voff[EPL / VEC];
+#pragma unroll
+  for (int q = 0; q < EPL / VEC; ++q) {
+    const int c0 = cl * EPL + q * VEC;
+    voff[q] = c0 < d ? (int32_t)(((int64_t)g * ld + c0) * (int64_t)sizeof(T)) : kOffInvalid;
+  }
+  const int32_t step_bytes = (int32_t)(kRowsPerStep * ld * (int64_t)sizeof(T));
+  // rows of batch b into registers (rows >= n read as zeros)
+  auto load_batch = [&](int64_t b) {
     const int64_t r0 = b * B;
-    using R = typename RegT<T>::type;
-    R xs[SB][EPL];
+    const __amdgpu_buffer_rsrc_t rs = rows_rsrc<T>(X, r0, n - r0 < B ? n - r0 : B, ld, d);
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
-      VecT<T, VEC> raw[EPL / VEC];
-      load_row<T, EPL, VEC>(X, r0 + s * kRowsPerStep + g, n, d, ld, cl, raw);
 #pragma unroll
-      for (int q = 0; q < EPL / VEC; ++q)
+      for (int q = 0; q < EPL / VEC; ++q) {
+        const VecT<T, VEC> raw = buf_load<T, VEC>(rs, voff[q], s * step_bytes);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) xs[s][q * VEC + e] = to_reg(raw[q].v[e]);
+        for (int e = 0; e < VEC; ++e) xs[s][q * VEC + e] = to_reg(raw.v[e]);
+      }
     }
+  };
+  const int64_t b0 = (int64_t)blockIdx.x * kPassWaves + wave;
+  // status0 is the same for the whole grid: either every wave returns below
+  // (after this barrier) or none does
+  __syncthreads();
+  for (int64_t b = b0; b < nb; b += GW) {
+    const int64_t r0 = b * B;
+    load_batch(b);
+    // the first batch's loads go out before the state word is waited on
+    if (b == b0 && status0 != kRunning) return;
+    // re-read the candidate each batch: it stays out of registers in phases 2-3
+    asm volatile("" ::: "memory");
+    double ub[EPL];
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) ub[k] = s_ctr[cl * EPL + k];
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       double dsq = 0.0;
@@ -437,6 +361,7 @@ void ses_pass_kernel(PassArgs a) {
     }
     wave_lds_sync();
   }
+  if (status0 != kRunning) return;
 
   // ---- workgroup record: W, C(cert), sums, maxima
 #pragma unroll
@@ -444,7 +369,7 @@ void ses_pass_kernel(PassArgs a) {
     wacc[k] += __shfl_xor(wacc[k], 16);
     wacc[k] += __shfl_xor(wacc[k], 32);
   }
-  const int pw = partial_width(d);
+  const int pw = rec_width(d);
   if (g == 0)
 #pragma unroll
     for (int k = 0; k < EPL; ++k) s_vec[wave][cl * EPL + k] = wacc[k];
@@ -466,6 +391,7 @@ void ses_pass_kernel(PassArgs a) {
   }
   __syncthreads();
   double *rec = a.partials + (int64_t)blockIdx.x * pw;
+  const int dp = rec_dp(d);
   for (int c = tid; c < d; c += kPassBlock) rec[c] = sum_waves(s_vec, c);
   __syncthreads();
   if (CERT) {
@@ -478,9 +404,7 @@ void ses_pass_kernel(PassArgs a) {
 #pragma unroll
       for (int k = 0; k < EPL; ++k) s_vec[wave][cl * EPL + k] = cacc[k];
     __syncthreads();
-    for (int c = tid; c < d; c += kPassBlock) rec[d + c] = sum_waves(s_vec, c);
-  } else {
-    for (int c = tid; c < d; c += kPassBlock) rec[d + c] = 0.0;
+    for (int c = tid; c < d; c += kPassBlock) rec[dp + 8 + c] = sum_waves(s_vec, c);
   }
   if (tid < 8) {
     double v;
@@ -490,121 +414,11 @@ void ses_pass_kernel(PassArgs a) {
       v = max_waves(s_sc, tid);
     else
       v = -INFINITY;
-    rec[2 * d + tid] = v;
+    rec[dp + tid] = v;
   }
 }
 
 // =========================================================== SVM pass
-template <typename T, int NT>
-__device__ void svm_epilogue(const PassArgs &a, const double *comb, double *s_red, int *s_int) {
-  DevState *st = a.st;
-  const int d = (int)a.d;
-  const int tid = threadIdx.x;
-  double *Sv = a.vec + kVecS * d;
-  double *wbar = a.vec + kVecMean * d;
-  double *best = a.vec + kVecBest * d;
-  double *last = a.vec + kVecLast * d;
-  const int64_t k = st->t + 1;
-  const double T1 = comb[2 * d + 0], T2 = comb[2 * d + 1];
-  const double minP = -comb[2 * d + 4], maxQ = comb[2 * d + 5], slmin = -comb[2 * d + 6];
-  if (tid == 0) {
-    int status = kRunning, copy = 0;
-    if (k >= 2) {
-      const double nw = st->wbar_norm;
-      const double f = nw > 0.0 ? fmax((minP - maxQ) / nw, 0.0) : 0.0;
-      status = monitor_rules(st, k, f, f > st->f_best, f > st->alpha, &copy);
-    }
-    s_int[0] = status;
-    s_int[1] = copy;
-  }
-  __syncthreads();
-  if (s_int[1])
-    for (int c = tid; c < d; c += NT) best[c] = wbar[c];
-  if (s_int[0] != kRunning) {
-    if (tid == 0) {
-      st->status = s_int[0];
-      st->t_end = k - 1;
-    }
-    return;
-  }
-  // ORACLE of eq.(svm_oracle): w = V/||V||, V = P mu - Q gamma.
-  const double *AP = comb, *AQ = comb + d;
-  double p = 0.0, pu = 0.0;
-  const bool both = T1 > 0.0 && T2 > 0.0;
-  for (int c = tid; c < d; c += NT) {
-    const double V = AP[c] - AQ[c];
-    p += V * V;
-    if (both) {
-      const double U = AP[c] / T1 - AQ[c] / T2;
-      pu += U * U;
-    }
-  }
-  const double nV = sqrt(block_sum<NT>(p, s_red));
-  const double ub = both ? sqrt(block_sum<NT>(pu, s_red)) : INFINITY;
-  const double alpha = st->alpha, D = st->D;
-  const double s1 = (T1 <= T2) ? D : alpha - D;
-  const double s2 = alpha - s1;
-  const double obj = nV - T1 * s1 - T2 * s2;
-  const double scale = nV + T1 * fabs(s1) + T2 * fabs(s2);
-  const bool bad = !isfinite(obj) || !(T1 + T2 > 0.0);
-  const bool separated = obj < -st->tau * scale;
-  if (tid == 0) {
-    const double M = -st->kscale * (double)st->t * st->shift_bound;
-    st->value = obj / (T1 + T2);
-    st->scale = scale / (T1 + T2);
-    st->log_trace = M + log(T1 + T2);
-    st->degenerate = !(nV > 0.0);
-    st->bound = fmin(st->bound, ub);
-    st->s1_last = s1;
-    st->s2_last = s2;
-  }
-  double w[(kMaxD + NT - 1) / NT];
-#pragma unroll
-  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
-    const int c = tid + j * NT;
-    w[j] = 0.0;
-    if (c < d) {
-      w[j] = nV > 0.0 ? (AP[c] - AQ[c]) / nV : 0.0;
-      last[c] = w[j];
-    }
-  }
-  if (bad || separated) {
-    if (tid == 0) {
-      st->status = bad ? kNumeric : kSeparated;
-      st->t_end = k;
-    }
-    return;
-  }
-  double dl = 0.0, wn = 0.0;
-#pragma unroll
-  for (int j = 0; j < (kMaxD + NT - 1) / NT; ++j) {
-    const int c = tid + j * NT;
-    if (c < d) {
-      const double s = Sv[c] + w[j];
-      Sv[c] = s;
-      const double yn = s / (double)k;
-      const double dd = yn - wbar[c];
-      dl += dd * dd;
-      wn += yn * yn;
-      wbar[c] = yn;
-    }
-  }
-  const double Dw = sqrt(block_sum<NT>(dl, s_red));
-  const double nwb = sqrt(block_sum<NT>(wn, s_red));
-  if (tid == 0) {
-    st->S1 += s1;
-    st->S2 += s2;
-    const double n1 = st->S1 / (double)k, n2 = st->S2 / (double)k;
-    const double ds = fmax(fabs(n1 - st->s1bar), fabs(n2 - st->s2bar));
-    st->s1bar = n1;
-    st->s2bar = n2;
-    st->wbar_norm = nwb;
-    // slack_i(k) >= slack_i(k-1) - ||x_i|| ||dwbar|| - |dsbar_c|, ||x_i|| <= D
-    st->shift_bound = slmin - D * Dw - ds;
-    st->t = k;
-  }
-}
-
 template <typename T, int EPL, int VEC>
 __global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
 void svm_pass_kernel(PassArgs a) {
@@ -614,11 +428,13 @@ void svm_pass_kernel(PassArgs a) {
   __shared__ double s_wa[kPassWaves][B];
   __shared__ double s_vec[kPassWaves][kG * EPL];
   __shared__ double s_sc[kPassWaves][8];
+  __shared__ double s_ctr[kG * EPL];  // the candidate (ubar or wbar), zero-padded
 
   DevState *st = a.st;
-  if (st->status != kRunning) return;
+  const int32_t status0 = st->status;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, cl = lane & 15;
   const int64_t n = a.n, ld = a.ld, n_pos = a.n_pos;
   const int d = (int)a.d;
@@ -628,12 +444,7 @@ void svm_pass_kernel(PassArgs a) {
   const double s1b = st->s1bar, s2b = st->s2bar;
   const double *wbar = a.vec + kVecMean * d;
 
-  double wb[EPL];
-#pragma unroll
-  for (int k = 0; k < EPL; ++k) {
-    const int c = cl * EPL + k;
-    wb[k] = c < d ? wbar[c] : 0.0;
-  }
+  for (int c = tid; c < kG * EPL; c += kPassBlock) s_ctr[c] = c < d ? wbar[c] : 0.0;
   double accP[EPL], accQ[EPL];
 #pragma unroll
   for (int k = 0; k < EPL; ++k) accP[k] = accQ[k] = 0.0;
@@ -641,24 +452,50 @@ void svm_pass_kernel(PassArgs a) {
 
   const int64_t nb = (n + B - 1) / B;
   const int64_t GW = (int64_t)gridDim.x * kPassWaves;
-  for (int64_t b = (int64_t)blockIdx.x * kPassWaves + wave; b < nb; b += GW) {
+  using R = typename RegT<T>::type;
+  R xv[SB][EPL];
+  // lane offsets (bytes) of the lane's column chunks within its row of a
+  // load step; chunks past column d get an offset beyond the buffer range
+  int32_t voff[EPL / VEC];
+#pragma unroll
+  for (int q = 0; q < EPL / VEC; ++q) {
+    const int c0 = cl * EPL + q * VEC;
+    voff[q] = c0 < d ? (int32_t)(((int64_t)g * ld + c0) * (int64_t)sizeof(T)) : kOffInvalid;
+  }
+  const int32_t step_bytes = (int32_t)(kRowsPerStep * ld * (int64_t)sizeof(T));
+  // rows of batch b into registers (rows >= n read as zeros)
+  auto load_batch = [&](int64_t b) {
     const int64_t r0 = b * B;
-    using R = typename RegT<T>::type;
-    R xv[SB][EPL];
+    const __amdgpu_buffer_rsrc_t rs = rows_rsrc<T>(X, r0, n - r0 < B ? n - r0 : B, ld, d);
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
-      VecT<T, VEC> raw[EPL / VEC];
-      load_row<T, EPL, VEC>(X, r0 + s * kRowsPerStep + g, n, d, ld, cl, raw);
 #pragma unroll
-      for (int q = 0; q < EPL / VEC; ++q)
+      for (int q = 0; q < EPL / VEC; ++q) {
+        const VecT<T, VEC> raw = buf_load<T, VEC>(rs, voff[q], s * step_bytes);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) xv[s][q * VEC + e] = to_reg(raw[q].v[e]);
+        for (int e = 0; e < VEC; ++e) xv[s][q * VEC + e] = to_reg(raw.v[e]);
+      }
     }
+  };
+  const int64_t b0 = (int64_t)blockIdx.x * kPassWaves + wave;
+  // status0 is the same for the whole grid: either every wave returns below
+  // (after this barrier) or none does
+  __syncthreads();
+  for (int64_t b = b0; b < nb; b += GW) {
+    const int64_t r0 = b * B;
+    load_batch(b);
+    // the first batch's loads go out before the state word is waited on
+    if (b == b0 && status0 != kRunning) return;
+    // re-read the candidate each batch: it stays out of registers in phases 2-3
+    asm volatile("" ::: "memory");
+    double ub[EPL];
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) ub[k] = s_ctr[cl * EPL + k];
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       double dot = 0.0;
 #pragma unroll
-      for (int k = 0; k < EPL; ++k) dot = fma((double)xv[s][k], wb[k], dot);
+      for (int k = 0; k < EPL; ++k) dot = fma((double)xv[s][k], ub[k], dot);
       s_part[wave][s * kRowsPerStep + g][cl] = dot;
     }
     wave_lds_sync();
@@ -710,6 +547,7 @@ void svm_pass_kernel(PassArgs a) {
     }
     wave_lds_sync();
   }
+  if (status0 != kRunning) return;
 
 #pragma unroll
   for (int k = 0; k < EPL; ++k) {
@@ -718,7 +556,7 @@ void svm_pass_kernel(PassArgs a) {
     accQ[k] += __shfl_xor(accQ[k], 16);
     accQ[k] += __shfl_xor(accQ[k], 32);
   }
-  const int pw = partial_width(d);
+  const int pw = rec_width(d);
   if (g == 0)
 #pragma unroll
     for (int k = 0; k < EPL; ++k) s_vec[wave][cl * EPL + k] = accP[k];
@@ -736,13 +574,14 @@ void svm_pass_kernel(PassArgs a) {
   }
   __syncthreads();
   double *rec = a.partials + (int64_t)blockIdx.x * pw;
+  const int dp = rec_dp(d);
   for (int c = tid; c < d; c += kPassBlock) rec[c] = sum_waves(s_vec, c);
   __syncthreads();
   if (g == 0)
 #pragma unroll
     for (int k = 0; k < EPL; ++k) s_vec[wave][cl * EPL + k] = accQ[k];
   __syncthreads();
-  for (int c = tid; c < d; c += kPassBlock) rec[d + c] = sum_waves(s_vec, c);
+  for (int c = tid; c < d; c += kPassBlock) rec[dp + 8 + c] = sum_waves(s_vec, c);
   if (tid < 8) {
     double v;
     if (tid < 2)
@@ -753,55 +592,303 @@ void svm_pass_kernel(PassArgs a) {
       v = max_waves(s_sc, tid);
     else
       v = -INFINITY;
-    rec[2 * d + tid] = v;
+    rec[dp + tid] = v;
   }
 }
 
 // ===================================================== combine + epilogue
-// One workgroup: sums the per-workgroup records of the pass that just ran
-// (fixed order: a transposed pass over record pairs, then over the row
-// groups) and runs the FP64 epilogue of the iteration.  The kernel boundary
-// after the pass makes every record visible; no fences are needed.
+// Section 5 monitor for the mean evaluated by pass k (iteration k-1 >= 1),
+// on the LDS copy of the state; one lane.  Returns the new status.
+__device__ inline int monitor_rules(DevState &S, int64_t k, double f, bool better, bool beat,
+                                    int *copy_best) {
+  int status = kRunning;
+  S.f_last = f;
+  if (!isfinite(f)) return kNumeric;
+  if (better) {
+    S.f_best = f;
+    S.t_best = k - 1;
+    *copy_best = 1;
+  }
+  if (S.early) {
+    if (beat) {
+      status = kBeat;
+    } else {
+      if (S.f_prev >= 0.0) {  // a previous monitored iteration exists
+        if (S.f_prev > 0.0 && fabs(f - S.f_prev) / S.f_prev < S.delta)
+          S.cnt += 1;
+        else
+          S.cnt = 0;
+      }
+      S.f_prev = f;
+      if (S.cnt >= S.patience) status = kStabilized;
+    }
+  }
+  if (status == kRunning && k - 1 >= S.T) status = kTReached;
+  return status;
+}
+
+constexpr int kPerLane = kMaxD / kWave;  // columns per lane in the one-wave epilogue
+
+// SES epilogue of pass k, one wave: ORACLE of eq.(ses_oracle), separation
+// test, running mean and the bound for the next pass's exponent shift.
+// S, y (mean), Sv (running sum), v1 are LDS copies; results go to global.
+__device__ inline void ses_epilogue(const PassArgs &a, DevState &S, const double *y, const double *Sv,
+                                    const double *v1, const double *comb, bool cert) {
+  const int d = (int)a.d, lane = threadIdx.x & 63;
+  const double *sc = comb + rec_dp(d);
+  const int64_t k = S.t + 1;
+  const double Bsum = sc[0], Esum = sc[1], Gsum = sc[2], BD2 = sc[3], Asum = sc[4];
+  const double gmax = sc[5], fall = sc[6];
+  int status = kRunning, copy = 0;
+  if (lane == 0 && k >= 2) status = monitor_rules(S, k, fall, fall < S.f_best, fall < S.alpha, &copy);
+  status = __shfl(status, 0);
+  copy = __shfl(copy, 0);
+  wave_lds_sync();
+  if (copy)
+    for (int c = lane; c < d; c += kWave) a.vec[kVecBest * d + c] = y[c];
+  if (status != kRunning) {
+    if (lane == 0) {
+      S.status = status;
+      S.t_end = k - 1;
+    }
+    return;
+  }
+  // W = sum_i a_i (v_i - ubar) = sum a_i v_i - (sum a_i) ubar
+  double Wr[kPerLane], u[kPerLane];
+  double p = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPerLane; ++j) {
+    const int c = lane + j * kWave;
+    Wr[j] = c < d ? comb[c] - Asum * y[c] : 0.0;
+    p += Wr[j] * Wr[j];
+  }
+  const double nW = sqrt(wave_sum(p));
+  const double alpha = S.alpha, g1 = S.gamma1;
+  double q = 0.0;
+#pragma unroll
+  for (int j = 0; j < kPerLane; ++j) {
+    const int c = lane + j * kWave;
+    u[j] = 0.0;
+    if (c < d) {
+      u[j] = nW > 0.0 ? v1[c] + (alpha - g1) * (Wr[j] / nW) : v1[c];
+      q += (u[j] - y[c]) * Wr[j];
+    }
+  }
+  // sum_i (u - v_i).w_i + (alpha - gamma_i) s_i, scaled by sqrt2 C e^{-M}:
+  // (u - ubar).W - sum (e+ - e-) d_i + alpha sum b_i - sum gamma_i b_i.
+  const double obj = wave_sum(q) - Esum + alpha * Bsum - Gsum;
+  const double scale = alpha * (nW + Bsum);
+  double lb2 = 0.0;
+  if (cert) {
+    double cc = 0.0;
+    const double *cx = comb + rec_dp(d) + 8;
+    for (int c = lane; c < d; c += kWave) {
+      const double cv = cx[c] - Bsum * y[c];  // sum_i b_i (v_i - ubar)
+      cc += cv * cv;
+    }
+    lb2 = BD2 / Bsum - wave_sum(cc) / (Bsum * Bsum);
+  }
+  const bool bad = !isfinite(obj) || !(Bsum > 0.0) || !isfinite(nW);
+  const bool separated = obj < -S.tau * scale;
+#pragma unroll
+  for (int j = 0; j < kPerLane; ++j) {
+    const int c = lane + j * kWave;
+    if (c < d) a.vec[kVecLast * d + c] = u[j];
+  }
+  double dl = 0.0;
+  if (!bad && !separated) {
+#pragma unroll
+    for (int j = 0; j < kPerLane; ++j) {
+      const int c = lane + j * kWave;
+      if (c < d) {
+        const double sm = Sv[c] + u[j];
+        const double yn = sm / (double)k;
+        const double dd = yn - y[c];
+        dl += dd * dd;
+        a.vec[kVecS * d + c] = sm;
+        a.vec[kVecMean * d + c] = yn;
+      }
+    }
+  }
+  const double Delta = sqrt(wave_sum(dl));
+  if (lane == 0) {
+    const double M = S.kscale * (double)S.t * (S.shift_bound - alpha);
+    S.value = obj / (M_SQRT2 * Bsum);
+    S.scale = scale / (M_SQRT2 * Bsum);
+    S.log_trace = M + log(Bsum);
+    S.degenerate = !(nW > 0.0);
+    S.cert = cert ? 1 : 0;
+    if (cert && a.radii == nullptr) S.bound = fmax(S.bound, sqrt(fmax(lb2, 0.0)));
+    if (bad || separated) {
+      S.status = bad ? kNumeric : kSeparated;
+      S.t_end = k;
+    } else {
+      // ||v_i - ubar(k)|| <= ||v_i - ubar(k-1)|| + ||ubar(k) - ubar(k-1)||
+      S.shift_bound = gmax + Delta;
+      S.t = k;
+    }
+  }
+}
+
+// SVM epilogue of pass k, one wave: ORACLE of eq.(svm_oracle), separation
+// test, the polytope-distance certificate, running means, next slack bound.
+__device__ inline void svm_epilogue(const PassArgs &a, DevState &S, const double *wb, const double *Sv,
+                                    const double *comb) {
+  const int d = (int)a.d, lane = threadIdx.x & 63;
+  const double *sc = comb + rec_dp(d);
+  const double *AP = comb, *AQ = comb + rec_dp(d) + 8;
+  const int64_t k = S.t + 1;
+  const double T1 = sc[0], T2 = sc[1];
+  const double minP = -sc[4], maxQ = sc[5], slmin = -sc[6];
+  int status = kRunning, copy = 0;
+  if (lane == 0 && k >= 2) {
+    const double nw = S.wbar_norm;
+    const double f = nw > 0.0 ? fmax((minP - maxQ) / nw, 0.0) : 0.0;
+    status = monitor_rules(S, k, f, f > S.f_best, f > S.alpha, &copy);
+  }
+  status = __shfl(status, 0);
+  copy = __shfl(copy, 0);
+  wave_lds_sync();
+  if (copy)
+    for (int c = lane; c < d; c += kWave) a.vec[kVecBest * d + c] = wb[c];
+  if (status != kRunning) {
+    if (lane == 0) {
+      S.status = status;
+      S.t_end = k - 1;
+    }
+    return;
+  }
+  const bool both = T1 > 0.0 && T2 > 0.0;
+  double p = 0.0, pu = 0.0;
+  for (int c = lane; c < d; c += kWave) {
+    const double V = AP[c] - AQ[c];
+    p += V * V;
+    if (both) {
+      const double U = AP[c] / T1 - AQ[c] / T2;
+      pu += U * U;
+    }
+  }
+  const double nV = sqrt(wave_sum(p));
+  const double ub = both ? sqrt(wave_sum(pu)) : INFINITY;
+  const double alpha = S.alpha, D = S.D;
+  const double s1 = (T1 <= T2) ? D : alpha - D;
+  const double s2 = alpha - s1;
+  const double obj = nV - T1 * s1 - T2 * s2;
+  const double scale = nV + T1 * fabs(s1) + T2 * fabs(s2);
+  const bool bad = !isfinite(obj) || !(T1 + T2 > 0.0);
+  const bool separated = obj < -S.tau * scale;
+  double w[kPerLane];
+#pragma unroll
+  for (int j = 0; j < kPerLane; ++j) {
+    const int c = lane + j * kWave;
+    w[j] = 0.0;
+    if (c < d) {
+      w[j] = nV > 0.0 ? (AP[c] - AQ[c]) / nV : 0.0;
+      a.vec[kVecLast * d + c] = w[j];
+    }
+  }
+  double dl = 0.0, wn = 0.0;
+  if (!bad && !separated) {
+#pragma unroll
+    for (int j = 0; j < kPerLane; ++j) {
+      const int c = lane + j * kWave;
+      if (c < d) {
+        const double sm = Sv[c] + w[j];
+        const double yn = sm / (double)k;
+        const double dd = yn - wb[c];
+        dl += dd * dd;
+        wn += yn * yn;
+        a.vec[kVecS * d + c] = sm;
+        a.vec[kVecMean * d + c] = yn;
+      }
+    }
+  }
+  const double Dw = sqrt(wave_sum(dl));
+  const double nwb = sqrt(wave_sum(wn));
+  if (lane == 0) {
+    const double M = -S.kscale * (double)S.t * S.shift_bound;
+    S.value = obj / (T1 + T2);
+    S.scale = scale / (T1 + T2);
+    S.log_trace = M + log(T1 + T2);
+    S.degenerate = !(nV > 0.0);
+    S.bound = fmin(S.bound, ub);
+    S.s1_last = s1;
+    S.s2_last = s2;
+    if (bad || separated) {
+      S.status = bad ? kNumeric : kSeparated;
+      S.t_end = k;
+    } else {
+      S.S1 += s1;
+      S.S2 += s2;
+      const double n1 = S.S1 / (double)k, n2 = S.S2 / (double)k;
+      const double ds = fmax(fabs(n1 - S.s1bar), fabs(n2 - S.s2bar));
+      S.s1bar = n1;
+      S.s2bar = n2;
+      S.wbar_norm = nwb;
+      // slack_i(k) >= slack_i(k-1) - ||x_i|| ||dwbar|| - |dsbar_c|, ||x_i|| <= D
+      S.shift_bound = slmin - D * Dw - ds;
+      S.t = k;
+    }
+  }
+}
+
+static_assert(sizeof(DevState) % 8 == 0, "DevState is copied as 8-byte words");
+constexpr int kStateWords = (int)(sizeof(DevState) / 8);
+
+// One workgroup per iteration: every global read (records of the pass that
+// just ran, the state, the mean, the running sum, row v1) is issued at once
+// into LDS; the records are summed in a fixed transposed order; one wave then
+// runs the FP64 epilogue on the LDS copies and writes the state back.  The
+// kernel boundary after the pass makes every record visible: no fences.
 template <typename T, int PROB, bool CERT>
 __global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P) {
   __shared__ double s_acc[2 * kCombBlock];
   __shared__ double s_comb[2 * kMaxD + 8];
-  __shared__ double s_red[kCombBlock / 64];
-  __shared__ int s_int[4];
-  DevState *st = a.st;
-  if (st->status != kRunning) return;
+  __shared__ double s_y[kMaxD], s_S[kMaxD], s_v1[kMaxD];
+  __shared__ DevState s_st;
   const int d = (int)a.d;
-  const int pw = partial_width(d);
-  const int nsum = PROB == kSES ? 2 * d + 5 : 2 * d + 4;
-  const int npairs = pw / 2;
-  const int groups = kCombBlock / npairs;
   const int tid = threadIdx.x;
+  const int dp = rec_dp(d), pw = rec_width(d);
+  const int ncols = (PROB == kSES && !CERT) ? dp + 8 : pw;  // the certificate half is not read
+  const int nsc = PROB == kSES ? 5 : 4;                      // summed scalars
+  const int npairs = ncols / 2;
+  const int groups = kCombBlock / npairs;
+  // state, mean, running sum, row v1
+  if (tid < kStateWords) reinterpret_cast<double *>(&s_st)[tid] = reinterpret_cast<const double *>(a.st)[tid];
+  for (int c = tid; c < d; c += kCombBlock) {
+    s_y[c] = a.vec[kVecMean * d + c];
+    s_S[c] = a.vec[kVecS * d + c];
+    if (PROB == kSES) s_v1[c] = to_f64(reinterpret_cast<const T *>(a.X)[a.v1 * a.ld + c]);
+  }
   const int j = tid % npairs, grp = tid / npairs;
   if (grp < groups) {
     const int c0 = 2 * j;
-    const bool s0 = c0 < nsum, s1 = c0 + 1 < nsum;
-    double acc0 = s0 ? 0.0 : -INFINITY, acc1 = s1 ? 0.0 : -INFINITY;
-#pragma unroll 8
+    const bool m0 = c0 >= dp + nsc && c0 < dp + 8, m1 = c0 + 1 >= dp + nsc && c0 + 1 < dp + 8;
+    double acc0 = m0 ? -INFINITY : 0.0, acc1 = m1 ? -INFINITY : 0.0;
+#pragma unroll 16
     for (int b = grp; b < P; b += groups) {
       const double2 v = *reinterpret_cast<const double2 *>(a.partials + (int64_t)b * pw + c0);
-      acc0 = s0 ? acc0 + v.x : fmax(acc0, v.x);
-      acc1 = s1 ? acc1 + v.y : fmax(acc1, v.y);
+      acc0 = m0 ? fmax(acc0, v.x) : acc0 + v.x;
+      acc1 = m1 ? fmax(acc1, v.y) : acc1 + v.y;
     }
-    s_acc[grp * pw + c0] = acc0;
-    s_acc[grp * pw + c0 + 1] = acc1;
+    s_acc[grp * ncols + c0] = acc0;
+    s_acc[grp * ncols + c0 + 1] = acc1;
   }
   __syncthreads();
-  for (int c = tid; c < pw; c += kCombBlock) {
-    const bool sm = c < nsum;
-    double r = sm ? 0.0 : -INFINITY;
-    for (int g = 0; g < groups; ++g) r = sm ? r + s_acc[g * pw + c] : fmax(r, s_acc[g * pw + c]);
+  for (int c = tid; c < ncols; c += kCombBlock) {
+    const bool mx = c >= dp + nsc && c < dp + 8;
+    double r = mx ? -INFINITY : 0.0;
+    for (int g = 0; g < groups; ++g) r = mx ? fmax(r, s_acc[g * ncols + c]) : r + s_acc[g * ncols + c];
     s_comb[c] = r;
   }
   __syncthreads();
+  if (tid >= kWave || s_st.status != kRunning) return;
   if (PROB == kSES)
-    ses_epilogue<T, kCombBlock>(a, s_comb, CERT, s_red, s_int);
+    ses_epilogue(a, s_st, s_y, s_S, s_v1, s_comb, CERT);
   else
-    svm_epilogue<T, kCombBlock>(a, s_comb, s_red, s_int);
+    svm_epilogue(a, s_st, s_y, s_S, s_comb);
+  wave_lds_sync();
+  if (tid < kStateWords) reinterpret_cast<double *>(a.st)[tid] = reinterpret_cast<const double *>(&s_st)[tid];
 }
 
 // ========================================================== monitor pass

@@ -308,6 +308,8 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   const int64_t ld = desc->ld ? desc->ld : desc->d;
   if (ld < desc->d) return bad("ld < d");
   if ((uintptr_t)desc->points % elem_size(desc->dtype)) return bad("points misaligned");
+  // a batch of 32 rows is addressed with 32-bit byte offsets
+  if (ld * (int64_t)elem_size(desc->dtype) * 32 >= (int64_t)1 << 30) return bad("row stride too large");
   if (desc->problem == SCP_MWU_PROBLEM_SVM) {
     if (desc->n_pos < 1 || desc->n_pos > desc->n - 1) return bad("n_pos outside [1, n-1]");
     if (desc->radii) return bad("radii given for SVM");
