@@ -1,0 +1,82 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (default grid, one workgroup per compute unit).
+
+The FP64 oracle takes a few seconds per iteration at these sizes, so each
+test runs the GPU for a number of iterations, reads its state (the running
+sums), and compares the next iteration against one oracle step from that
+same state: the ORACLE output, its objective, ln of the trace, and the
+monitor value f of the mean -- every output of the iteration.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ses as oses
+from oracle import svm as osvm
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = 1e-9
+
+
+def _ses_case(V32, Vref64, storage, alpha_fn):
+    import torch
+    import paper_2405_09157_amd as scp
+    P = oses.setup(Vref64)
+    alpha = alpha_fn(P)
+    T = 20000
+    eta = math.sqrt(math.log(P.r) / T)
+    m = scp.MWU(torch.from_numpy(V32).cuda(), "ses", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP,
+                storage=storage, chunk=64)
+    assert abs(m.D - P.D) <= 1e-12 * P.D
+    m.step(alpha, T, 37)
+    sums, t = m.get_state()
+    assert t == 37
+    info = m.step(alpha, T, 1)
+    u_gpu = np.array(m.vector(2))
+    m.close()
+    st = oses.step(P, np.array(sums), t, alpha, eta)
+    assert np.linalg.norm(u_gpu - st["u"]) / alpha <= TIGHT
+    assert abs(info["value"] - st["value"]) / st["scale"] <= TIGHT
+    assert abs(info["log_trace"] - st["logC"]) / abs(st["logC"]) <= TIGHT
+    assert abs(info["f_last"] - st["f_prev"]) / st["f_prev"] <= TIGHT
+    assert (info["outcome_name"] == "separated") == st["separated"]
+
+
+def test_ses_1m_d100_f32_fullsize():
+    V = synth.ses_gaussian_outliers(1_000_000, 100, 0, dtype=np.float32)
+    _ses_case(V, V.astype(np.float64), None, lambda P: 0.8 * P.D)
+
+
+def test_ses_1m_d100_bf16_fullsize():
+    V = synth.ses_gaussian_outliers(1_000_000, 100, 0, dtype=np.float32)
+    Vq = synth.bf16_to_f32(synth.bf16_round(V)).astype(np.float64)
+    _ses_case(V, Vq, "bf16", lambda P: 0.8 * P.D)
+
+
+def test_svm_500k_d256_f32_fullsize():
+    import torch
+    import paper_2405_09157_amd as scp
+    X, _ = synth.svm_planted(250_000, 250_000, 256, 0, dtype=np.float32)
+    X64 = X.astype(np.float64)
+    Pb = osvm.setup(X64, 250_000)
+    alpha, T = 0.12, 20000            # near the planted margin
+    eta = math.sqrt(math.log(Pb.r) / T)
+    m = scp.MWU(torch.from_numpy(X).cuda(), "svm", n_pos=250_000,
+                flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP, chunk=64)
+    assert abs(m.D - Pb.D) <= 1e-12 * Pb.D
+    m.step(alpha, T, 29)
+    sums, t = m.get_state()
+    info = m.step(alpha, T, 1)
+    y = np.array(m.vector(2))
+    m.close()
+    sums = np.array(sums)
+    st = osvm.step(Pb, sums[:256], sums[256], sums[257], t, alpha, eta)
+    assert np.linalg.norm(y[:256] - st["w"]) <= TIGHT
+    assert abs(y[256] - st["s1"]) <= TIGHT * Pb.D and abs(y[257] - st["s2"]) <= TIGHT * Pb.D
+    assert abs(info["value"] - st["value"]) / st["scale"] <= TIGHT
+    assert abs(info["log_trace"] - st["logC"]) / max(1.0, abs(st["logC"])) <= TIGHT
+    if st["f_prev"] > 0:
+        assert abs(info["f_last"] - st["f_prev"]) / st["f_prev"] <= TIGHT
