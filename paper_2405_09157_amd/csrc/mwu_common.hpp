@@ -106,6 +106,7 @@ struct LaunchCfg {
   int epl;     // columns per lane: 16 * epl >= d
   int vec;     // elements per vector load (1 = scalar loads)
   bool cert;   // SES weight certificate accumulators
+  bool pf;     // two register batches, the next one loading (prefetch)
 };
 
 #define SCPMWU_DECLARE_TYPED(name)                                                              \

@@ -30,12 +30,12 @@
 //            the row weight goes back to LDS;
 //   phase 3  lanes over columns: weighted accumulation of the rows still held
 //            in registers (one FMA per element).
-// Workgroup partials are reduced by a two-level, fixed-order combine (the
-// last finisher of each group of kGroup workgroups, then the last group),
-// whose final workgroup runs the FP64 epilogue: ORACLE closed form, the
-// separation test, the running mean and the early-exit rules.  All
-// arithmetic on point data is binary64; results are bitwise reproducible for
-// a fixed grid.
+// Each workgroup writes one record of partial sums and maxima; the pass has
+// no inter-workgroup synchronisation.  The one-workgroup kernel launched
+// after it sums the records in a fixed order and one wave runs the FP64
+// epilogue: ORACLE closed form, the separation test, the running mean and the
+// early-exit rules.  All arithmetic on point data is
+// binary64; results are bitwise reproducible for a fixed grid.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -99,26 +99,72 @@ __device__ __forceinline__ double to_reg<double>(double x) {
 #define SCPMWU_PASS_WAVES 2
 #endif
 
-// Batch shape: SB load steps of 4 rows; the batch's row data (SB * EPL
-// elements per lane, 64 VGPRs) stays in registers through the three phases.
-template <int EPL, int ESZ, int PROB = kSES>
-struct Shape {
-  // SVM keeps two binary64 class accumulators per column: half the batch.
-  static constexpr int LIM = (ESZ == 8 ? 32 : 64) / (PROB == kSVM ? 2 : 1);
-  static constexpr int SB = (LIM / EPL) < 8 ? ((LIM / EPL) > 0 ? LIM / EPL : 1) : 8;
-  static constexpr int B = SB * kRowsPerStep;  // rows per batch (<= 32)
+// Register image of one batch: SB load steps x EPL elements of the lane.
+// F32 and F64 elements are held in their own type (binary32 holds F32 and
+// BF16 values exactly at half the registers of binary64); with PACK, BF16
+// keeps its raw pairs, two elements per 32-bit register, widened on use.
+template <typename T, int SB, int EPL, bool PACK>
+struct Batch {
+  using R = typename RegT<T>::type;
+  R x[SB][EPL];
+  double gi;  // SES: radius of the batch row of this lane (lanes < B)
+  __device__ __forceinline__ double get(int s, int k) const { return (double)x[s][k]; }
+  template <int VEC>
+  __device__ __forceinline__ void put(int s, int q, const VecT<T, VEC> &raw) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) x[s][q * VEC + e] = to_reg(raw.v[e]);
+  }
+  // keeps the elements in their narrow type across the per-row phase
+  // instead of caching binary64 conversions (which would double the live
+  // registers)
+  __device__ __forceinline__ void pin() {
+#pragma unroll
+    for (int s = 0; s < SB; ++s)
+#pragma unroll
+      for (int k = 0; k < EPL; ++k) asm volatile("" : "+v"(x[s][k]));
+  }
+};
+template <int SB, int EPL>
+struct Batch<uint16_t, SB, EPL, true> {
+  static_assert(EPL % 2 == 0, "packed BF16 needs an even number of columns per lane");
+  uint32_t w[SB][EPL / 2];
+  double gi;
+  __device__ __forceinline__ double get(int s, int k) const {
+    const uint32_t u = w[s][k >> 1];
+    return (double)__uint_as_float((k & 1) ? (u & 0xffff0000u) : (u << 16));
+  }
+  template <int VEC>
+  __device__ __forceinline__ void put(int s, int q, const VecT<uint16_t, VEC> &raw) {
+    if constexpr (VEC >= 2) {
+      __builtin_memcpy(&w[s][q * VEC / 2], &raw, VEC * 2);
+    } else {
+      const uint32_t h = raw.v[0];
+      w[s][q >> 1] = (q & 1) ? (w[s][q >> 1] | (h << 16)) : h;
+    }
+  }
+  __device__ __forceinline__ void pin() {
+#pragma unroll
+    for (int s = 0; s < SB; ++s)
+#pragma unroll
+      for (int k = 0; k < EPL / 2; ++k) asm volatile("" : "+v"(w[s][k]));
+  }
 };
 
-// Forces the compiler to keep x in its (narrow) register type across the
-// per-row phase instead of caching its binary64 conversion: the widened copy
-// of a whole batch would double the live registers.
-template <typename R, int SB, int EPL>
-__device__ __forceinline__ void opaque(R (&x)[SB][EPL]) {
-#pragma unroll
-  for (int s = 0; s < SB; ++s)
-#pragma unroll
-    for (int k = 0; k < EPL; ++k) asm volatile("" : "+v"(x[s][k]));
-}
+// Batch shape: SB load steps of 4 rows (B = 4 SB <= 32 rows).  The batch
+// registers get a budget of 64 VGPRs: one batch, or with PF (prefetch) two
+// of half the size, the next batch loading while the current one is
+// processed.  SVM keeps two binary64 class accumulators per column and halves
+// the budget.  With PF, BF16 batches are packed (same rows, half the
+// registers).
+template <typename T, int EPL, int PROB, bool PF>
+struct PassShape {
+  static constexpr bool PACK = PF && sizeof(T) == 2 && EPL % 2 == 0;
+  static constexpr int ESZ = (int)sizeof(typename RegT<T>::type);
+  static constexpr int LIM = (ESZ == 8 ? 32 : (PACK ? 128 : 64)) / (PROB == kSVM ? 2 : 1) / (PF ? 2 : 1);
+  static constexpr int SB = (LIM / EPL) < 8 ? ((LIM / EPL) > 0 ? LIM / EPL : 1) : 8;
+  static constexpr int B = SB * kRowsPerStep;
+  using Regs = Batch<T, SB, EPL, PACK>;
+};
 
 // Lanes of one wavefront exchange data through LDS only: DS instructions of a
 // wave execute in order, so a compiler barrier is all that is needed.
@@ -132,6 +178,24 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
   return v;
+}
+// Several wave sums in one butterfly, so their shuffle latencies overlap.
+__device__ __forceinline__ void wave_sum2(double &a, double &b) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double x = __shfl_xor(a, m), y = __shfl_xor(b, m);
+    a += x;
+    b += y;
+  }
+}
+__device__ __forceinline__ void wave_sum3(double &a, double &b, double &c) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double x = __shfl_xor(a, m), y = __shfl_xor(b, m), z = __shfl_xor(c, m);
+    a += x;
+    b += y;
+    c += z;
+  }
 }
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -172,15 +236,39 @@ __device__ __forceinline__ double block_sum(double v, double *s_red) {
 // ------------------------------------------------------------ buffer loads
 // Rows [r0, r0 + rows) of X as a raw buffer resource: bytes past the last
 // valid element of the last valid row read as zero (hardware range check),
-// so a batch needs no per-row branch, zero fill or 64-bit address update.
+// so a batch needs no per-row branch or zero fill.  The range check covers
+// the lane (VGPR) offset and the immediate offset but not the SGPR offset,
+// so the whole offset of a load (row step and column) goes in the lane
+// offset.
 constexpr int32_t kBufWord3 = 0x00020000;  // raw buffer, gfx9 family
 constexpr int32_t kOffInvalid = 0x40000000;  // a lane offset beyond any batch
 
+// r0 and rows are wave-uniform; they are read from the first lane so that the
+// resource is built in scalar registers (a resource the compiler cannot prove
+// uniform makes it loop over lanes around every load).
 template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const T *X, int64_t r0, int64_t rows, int64_t ld,
                                                           int d) {
   const int32_t num = rows > 0 ? (int32_t)(((rows - 1) * ld + d) * (int64_t)sizeof(T)) : 0;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(X + r0 * ld), (short)0, num, kBufWord3);
+  const uint64_t base = reinterpret_cast<uint64_t>(X + r0 * ld);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<T *>(((uint64_t)hi << 32) | lo), (short)0,
+                                           __builtin_amdgcn_readfirstlane(num), kBufWord3);
+}
+
+// Radii of rows [r0, r0 + rows) (none: an empty resource, every load reads 0).
+__device__ __forceinline__ double radius_load(const double *radii, int64_t r0, int64_t rows, int lane) {
+  const int32_t num = (radii != nullptr && rows > 0) ? (int32_t)(rows * 8) : 0;
+  const uint64_t base = radii != nullptr ? reinterpret_cast<uint64_t>(radii + r0) : 0;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<void *>(((uint64_t)hi << 32) | lo), (short)0, __builtin_amdgcn_readfirstlane(num), kBufWord3);
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, lane * 8, 0, 0);
+  double g;
+  __builtin_memcpy(&g, &v, 8);
+  return g;
 }
 
 template <typename T, int VEC>
@@ -231,11 +319,12 @@ __host__ __device__ inline int rec_dp(int d) { return (d + 1) & ~1; }
 __host__ __device__ inline int rec_width(int d) { return partial_width(d); }
 
 // =========================================================== SES pass
-template <typename T, int EPL, int VEC, bool CERT>
+template <typename T, int EPL, int VEC, bool CERT, bool PF>
 __global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
 void ses_pass_kernel(PassArgs a) {
-  using Sh = Shape<EPL, (int)sizeof(typename RegT<T>::type)>;
+  using Sh = PassShape<T, EPL, kSES, PF>;
   constexpr int SB = Sh::SB, B = Sh::B;
+  using Regs = typename Sh::Regs;
   __shared__ double s_part[kPassWaves][B][kG + 1];
   __shared__ double s_wa[kPassWaves][B];
   __shared__ double s_wb[kPassWaves][CERT ? B : 1];
@@ -244,7 +333,7 @@ void ses_pass_kernel(PassArgs a) {
   __shared__ double s_ctr[kG * EPL];  // the candidate (ubar or wbar), zero-padded
 
   DevState *st = a.st;
-  const int32_t status0 = st->status;
+  const int32_t status0 = __builtin_amdgcn_readfirstlane(st->status);  // grid-uniform
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -268,8 +357,6 @@ void ses_pass_kernel(PassArgs a) {
 
   const int64_t nb = (n + B - 1) / B;
   const int64_t GW = (int64_t)gridDim.x * kPassWaves;
-  using R = typename RegT<T>::type;
-  R xs[SB][EPL];
   // lane offsets (bytes) of the lane's column chunks within its row of a
   // load step; chunks past column d get an offset beyond the buffer range
   int32_t voff[EPL / VEC];
@@ -280,28 +367,20 @@ void ses_pass_kernel(PassArgs a) {
   }
   const int32_t step_bytes = (int32_t)(kRowsPerStep * ld * (int64_t)sizeof(T));
   // rows of batch b into registers (rows >= n read as zeros)
-  auto load_batch = [&](int64_t b) {
+  auto load_batch = [&](Regs &xs, int64_t b) {
     const int64_t r0 = b * B;
-    const __amdgpu_buffer_rsrc_t rs = rows_rsrc<T>(X, r0, n - r0 < B ? n - r0 : B, ld, d);
+    const int64_t rows = n - r0 < B ? n - r0 : B;
+    const __amdgpu_buffer_rsrc_t rs = rows_rsrc<T>(X, r0, rows, ld, d);
 #pragma unroll
-    for (int s = 0; s < SB; ++s) {
+    for (int s = 0; s < SB; ++s)
 #pragma unroll
-      for (int q = 0; q < EPL / VEC; ++q) {
-        const VecT<T, VEC> raw = buf_load<T, VEC>(rs, voff[q], s * step_bytes);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) xs[s][q * VEC + e] = to_reg(raw.v[e]);
-      }
-    }
+      for (int q = 0; q < EPL / VEC; ++q)
+        xs.template put<VEC>(s, q, buf_load<T, VEC>(rs, voff[q] + s * step_bytes, 0));
+    xs.gi = radius_load(radii, r0, rows, lane);
   };
-  const int64_t b0 = (int64_t)blockIdx.x * kPassWaves + wave;
-  // status0 is the same for the whole grid: either every wave returns below
-  // (after this barrier) or none does
-  __syncthreads();
-  for (int64_t b = b0; b < nb; b += GW) {
+  // phases 1-3 on the batch b held in xs
+  auto process = [&](Regs &xs, int64_t b) {
     const int64_t r0 = b * B;
-    load_batch(b);
-    // the first batch's loads go out before the state word is waited on
-    if (b == b0 && status0 != kRunning) return;
     // re-read the candidate each batch: it stays out of registers in phases 2-3
     asm volatile("" ::: "memory");
     double ub[EPL];
@@ -312,7 +391,7 @@ void ses_pass_kernel(PassArgs a) {
       double dsq = 0.0;
 #pragma unroll
       for (int k = 0; k < EPL; ++k) {
-        const double df = (double)xs[s][k] - ub[k];
+        const double df = xs.get(s, k) - ub[k];
         dsq = fma(df, df, dsq);
       }
       s_part[wave][s * kRowsPerStep + g][cl] = dsq;
@@ -326,7 +405,7 @@ void ses_pass_kernel(PassArgs a) {
       const bool valid = row < n;
       const bool incl = valid && row != v1;
       const double di = sqrt(dsq);
-      const double gi = (valid && radii != nullptr) ? radii[row] : 0.0;
+      const double gi = xs.gi;  // 0 past n or without radii
       const double h = di + gi;
       // shifted lambda_+ = kappa (h - alpha) - kappa (G - alpha) <= ~0
       const double ep = exp(kappa * (h - Gb));
@@ -346,20 +425,53 @@ void ses_pass_kernel(PassArgs a) {
       if (CERT) s_wb[wave][lane] = bw;
     }
     wave_lds_sync();
-    opaque(xs);
+    xs.pin();
     // sum_i a_i x_i (and sum_i b_i x_i); the epilogue subtracts (sum a_i) ubar
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       const double ar = s_wa[wave][s * kRowsPerStep + g];
 #pragma unroll
-      for (int k = 0; k < EPL; ++k) wacc[k] = fma(ar, (double)xs[s][k], wacc[k]);
+      for (int k = 0; k < EPL; ++k) wacc[k] = fma(ar, xs.get(s, k), wacc[k]);
       if (CERT) {
         const double br = s_wb[wave][s * kRowsPerStep + g];
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) cacc[k] = fma(br, (double)xs[s][k], cacc[k]);
+        for (int k = 0; k < EPL; ++k) cacc[k] = fma(br, xs.get(s, k), cacc[k]);
       }
     }
     wave_lds_sync();
+  };
+  const int64_t b0 = (int64_t)blockIdx.x * kPassWaves + wave;
+  // status0 is the same for the whole grid: either every wave returns below
+  // (after this barrier) or none does
+  __syncthreads();
+  if constexpr (PF) {
+    // two register batches, unrolled by two so that neither is copied: the
+    // loads of the next batch are in flight while the current one is
+    // processed.  The loads are unconditional (a batch past the end has an
+    // empty resource and reads zeros without touching memory), so that the
+    // waits for the current batch never include the next one's loads.
+    Regs xa, xb;
+    int64_t b = b0;
+    load_batch(xa, b);
+    if (status0 != kRunning) return;
+    while (b < nb) {
+      const int64_t b1 = b + GW;
+      load_batch(xb, b1);
+      process(xa, b);
+      if (b1 >= nb) break;
+      const int64_t b2 = b1 + GW;
+      load_batch(xa, b2);
+      process(xb, b1);
+      b = b2;
+    }
+  } else {
+    Regs xs;
+    for (int64_t b = b0; b < nb; b += GW) {
+      load_batch(xs, b);
+      // the first batch's loads go out before the state word is waited on
+      if (b == b0 && status0 != kRunning) return;
+      process(xs, b);
+    }
   }
   if (status0 != kRunning) return;
 
@@ -419,11 +531,12 @@ void ses_pass_kernel(PassArgs a) {
 }
 
 // =========================================================== SVM pass
-template <typename T, int EPL, int VEC>
+template <typename T, int EPL, int VEC, bool PF>
 __global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
 void svm_pass_kernel(PassArgs a) {
-  using Sh = Shape<EPL, (int)sizeof(typename RegT<T>::type), kSVM>;
+  using Sh = PassShape<T, EPL, kSVM, PF>;
   constexpr int SB = Sh::SB, B = Sh::B;
+  using Regs = typename Sh::Regs;
   __shared__ double s_part[kPassWaves][B][kG + 1];
   __shared__ double s_wa[kPassWaves][B];
   __shared__ double s_vec[kPassWaves][kG * EPL];
@@ -431,7 +544,7 @@ void svm_pass_kernel(PassArgs a) {
   __shared__ double s_ctr[kG * EPL];  // the candidate (ubar or wbar), zero-padded
 
   DevState *st = a.st;
-  const int32_t status0 = st->status;
+  const int32_t status0 = __builtin_amdgcn_readfirstlane(st->status);  // grid-uniform
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -452,8 +565,6 @@ void svm_pass_kernel(PassArgs a) {
 
   const int64_t nb = (n + B - 1) / B;
   const int64_t GW = (int64_t)gridDim.x * kPassWaves;
-  using R = typename RegT<T>::type;
-  R xv[SB][EPL];
   // lane offsets (bytes) of the lane's column chunks within its row of a
   // load step; chunks past column d get an offset beyond the buffer range
   int32_t voff[EPL / VEC];
@@ -464,28 +575,18 @@ void svm_pass_kernel(PassArgs a) {
   }
   const int32_t step_bytes = (int32_t)(kRowsPerStep * ld * (int64_t)sizeof(T));
   // rows of batch b into registers (rows >= n read as zeros)
-  auto load_batch = [&](int64_t b) {
+  auto load_batch = [&](Regs &xv, int64_t b) {
     const int64_t r0 = b * B;
     const __amdgpu_buffer_rsrc_t rs = rows_rsrc<T>(X, r0, n - r0 < B ? n - r0 : B, ld, d);
 #pragma unroll
-    for (int s = 0; s < SB; ++s) {
+    for (int s = 0; s < SB; ++s)
 #pragma unroll
-      for (int q = 0; q < EPL / VEC; ++q) {
-        const VecT<T, VEC> raw = buf_load<T, VEC>(rs, voff[q], s * step_bytes);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) xv[s][q * VEC + e] = to_reg(raw.v[e]);
-      }
-    }
+      for (int q = 0; q < EPL / VEC; ++q)
+        xv.template put<VEC>(s, q, buf_load<T, VEC>(rs, voff[q] + s * step_bytes, 0));
   };
-  const int64_t b0 = (int64_t)blockIdx.x * kPassWaves + wave;
-  // status0 is the same for the whole grid: either every wave returns below
-  // (after this barrier) or none does
-  __syncthreads();
-  for (int64_t b = b0; b < nb; b += GW) {
+  // phases 1-3 on the batch b held in xv
+  auto process = [&](Regs &xv, int64_t b) {
     const int64_t r0 = b * B;
-    load_batch(b);
-    // the first batch's loads go out before the state word is waited on
-    if (b == b0 && status0 != kRunning) return;
     // re-read the candidate each batch: it stays out of registers in phases 2-3
     asm volatile("" ::: "memory");
     double ub[EPL];
@@ -495,7 +596,7 @@ void svm_pass_kernel(PassArgs a) {
     for (int s = 0; s < SB; ++s) {
       double dot = 0.0;
 #pragma unroll
-      for (int k = 0; k < EPL; ++k) dot = fma((double)xv[s][k], ub[k], dot);
+      for (int k = 0; k < EPL; ++k) dot = fma(xv.get(s, k), ub[k], dot);
       s_part[wave][s * kRowsPerStep + g][cl] = dot;
     }
     wave_lds_sync();
@@ -517,20 +618,20 @@ void svm_pass_kernel(PassArgs a) {
       s_wa[wave][lane] = e;
     }
     wave_lds_sync();
-    opaque(xv);
+    xv.pin();
     if (r0 + B <= n_pos) {
 #pragma unroll
       for (int s = 0; s < SB; ++s) {
         const double er = s_wa[wave][s * kRowsPerStep + g];
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) accP[k] = fma(er, (double)xv[s][k], accP[k]);
+        for (int k = 0; k < EPL; ++k) accP[k] = fma(er, xv.get(s, k), accP[k]);
       }
     } else if (r0 >= n_pos) {
 #pragma unroll
       for (int s = 0; s < SB; ++s) {
         const double er = s_wa[wave][s * kRowsPerStep + g];
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) accQ[k] = fma(er, (double)xv[s][k], accQ[k]);
+        for (int k = 0; k < EPL; ++k) accQ[k] = fma(er, xv.get(s, k), accQ[k]);
       }
     } else {
 #pragma unroll
@@ -540,12 +641,40 @@ void svm_pass_kernel(PassArgs a) {
         const double eP = rp ? er : 0.0, eQ = rp ? 0.0 : er;
 #pragma unroll
         for (int k = 0; k < EPL; ++k) {
-          accP[k] = fma(eP, (double)xv[s][k], accP[k]);
-          accQ[k] = fma(eQ, (double)xv[s][k], accQ[k]);
+          accP[k] = fma(eP, xv.get(s, k), accP[k]);
+          accQ[k] = fma(eQ, xv.get(s, k), accQ[k]);
         }
       }
     }
     wave_lds_sync();
+  };
+  const int64_t b0 = (int64_t)blockIdx.x * kPassWaves + wave;
+  // status0 is the same for the whole grid: either every wave returns below
+  // (after this barrier) or none does
+  __syncthreads();
+  if constexpr (PF) {
+    Regs xa, xb;
+    int64_t b = b0;
+    load_batch(xa, b);
+    if (status0 != kRunning) return;
+    while (b < nb) {
+      const int64_t b1 = b + GW;
+      load_batch(xb, b1);
+      process(xa, b);
+      if (b1 >= nb) break;
+      const int64_t b2 = b1 + GW;
+      load_batch(xa, b2);
+      process(xb, b1);
+      b = b2;
+    }
+  } else {
+    Regs xv;
+    for (int64_t b = b0; b < nb; b += GW) {
+      load_batch(xv, b);
+      // the first batch's loads go out before the state word is waited on
+      if (b == b0 && status0 != kRunning) return;
+      process(xv, b);
+    }
   }
   if (status0 != kRunning) return;
 
@@ -653,41 +782,43 @@ __device__ inline void ses_epilogue(const PassArgs &a, DevState &S, const double
     }
     return;
   }
-  // W = sum_i a_i (v_i - ubar) = sum a_i v_i - (sum a_i) ubar
+  // W = sum_i a_i (v_i - ubar) = sum a_i v_i - (sum a_i) ubar.  One
+  // butterfly sums ||W||^2, (v1 - ubar).W and, with a certificate,
+  // ||sum_i b_i (v_i - ubar)||^2.
   double Wr[kPerLane], u[kPerLane];
-  double p = 0.0;
+  double p = 0.0, r = 0.0, cc = 0.0;
 #pragma unroll
   for (int j = 0; j < kPerLane; ++j) {
     const int c = lane + j * kWave;
     Wr[j] = c < d ? comb[c] - Asum * y[c] : 0.0;
     p += Wr[j] * Wr[j];
+    if (c < d) r += (v1[c] - y[c]) * Wr[j];
   }
-  const double nW = sqrt(wave_sum(p));
+  if (cert) {
+    const double *cx = comb + rec_dp(d) + 8;
+    for (int c = lane; c < d; c += kWave) {
+      const double cv = cx[c] - Bsum * y[c];
+      cc += cv * cv;
+    }
+    wave_sum3(p, r, cc);
+  } else {
+    wave_sum2(p, r);
+  }
+  const double nW = sqrt(p);
   const double alpha = S.alpha, g1 = S.gamma1;
-  double q = 0.0;
 #pragma unroll
   for (int j = 0; j < kPerLane; ++j) {
     const int c = lane + j * kWave;
     u[j] = 0.0;
-    if (c < d) {
-      u[j] = nW > 0.0 ? v1[c] + (alpha - g1) * (Wr[j] / nW) : v1[c];
-      q += (u[j] - y[c]) * Wr[j];
-    }
+    if (c < d) u[j] = nW > 0.0 ? v1[c] + (alpha - g1) * (Wr[j] / nW) : v1[c];
   }
   // sum_i (u - v_i).w_i + (alpha - gamma_i) s_i, scaled by sqrt2 C e^{-M}:
-  // (u - ubar).W - sum (e+ - e-) d_i + alpha sum b_i - sum gamma_i b_i.
-  const double obj = wave_sum(q) - Esum + alpha * Bsum - Gsum;
+  // (u - ubar).W - sum (e+ - e-) d_i + alpha sum b_i - sum gamma_i b_i, where
+  // (u - ubar).W = (v1 - ubar).W + (alpha - gamma1) ||W||.
+  const double q = nW > 0.0 ? r + (alpha - g1) * nW : r;
+  const double obj = q - Esum + alpha * Bsum - Gsum;
   const double scale = alpha * (nW + Bsum);
-  double lb2 = 0.0;
-  if (cert) {
-    double cc = 0.0;
-    const double *cx = comb + rec_dp(d) + 8;
-    for (int c = lane; c < d; c += kWave) {
-      const double cv = cx[c] - Bsum * y[c];  // sum_i b_i (v_i - ubar)
-      cc += cv * cv;
-    }
-    lb2 = BD2 / Bsum - wave_sum(cc) / (Bsum * Bsum);
-  }
+  const double lb2 = cert ? BD2 / Bsum - cc / (Bsum * Bsum) : 0.0;
   const bool bad = !isfinite(obj) || !(Bsum > 0.0) || !isfinite(nW);
   const bool separated = obj < -S.tau * scale;
 #pragma unroll
@@ -768,8 +899,9 @@ __device__ inline void svm_epilogue(const PassArgs &a, DevState &S, const double
       pu += U * U;
     }
   }
-  const double nV = sqrt(wave_sum(p));
-  const double ub = both ? sqrt(wave_sum(pu)) : INFINITY;
+  wave_sum2(p, pu);
+  const double nV = sqrt(p);
+  const double ub = both ? sqrt(pu) : INFINITY;
   const double alpha = S.alpha, D = S.D;
   const double s1 = (T1 <= T2) ? D : alpha - D;
   const double s2 = alpha - s1;
@@ -803,8 +935,9 @@ __device__ inline void svm_epilogue(const PassArgs &a, DevState &S, const double
       }
     }
   }
-  const double Dw = sqrt(wave_sum(dl));
-  const double nwb = sqrt(wave_sum(wn));
+  wave_sum2(dl, wn);
+  const double Dw = sqrt(dl);
+  const double nwb = sqrt(wn);
   if (lane == 0) {
     const double M = -S.kscale * (double)S.t * S.shift_bound;
     S.value = obj / (T1 + T2);
@@ -994,17 +1127,23 @@ __global__ __launch_bounds__(kBlock) void ftp_init_kernel(PassArgs a, InitParams
 }
 
 // ============================================================== dispatch
-template <typename T, int EPL, int VEC>
-hipError_t launch_pass_t(int problem, bool cert, int grid, const PassArgs &a, hipStream_t s) {
+template <typename T, int EPL, int VEC, bool PF>
+hipError_t launch_pass_p(int problem, bool cert, int grid, const PassArgs &a, hipStream_t s) {
   if (problem == kSES) {
     if (cert)
-      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, true>), dim3(grid), dim3(kPassBlock), 0, s, a);
+      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, true, PF>), dim3(grid), dim3(kPassBlock), 0, s, a);
     else
-      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, false>), dim3(grid), dim3(kPassBlock), 0, s, a);
+      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, false, PF>), dim3(grid), dim3(kPassBlock), 0, s, a);
   } else {
-    hipLaunchKernelGGL((svm_pass_kernel<T, EPL, VEC>), dim3(grid), dim3(kPassBlock), 0, s, a);
+    hipLaunchKernelGGL((svm_pass_kernel<T, EPL, VEC, PF>), dim3(grid), dim3(kPassBlock), 0, s, a);
   }
   return hipGetLastError();
+}
+
+template <typename T, int EPL, int VEC>
+hipError_t launch_pass_t(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
+  return c.pf ? launch_pass_p<T, EPL, VEC, true>(problem, c.cert, c.grid, a, s)
+              : launch_pass_p<T, EPL, VEC, false>(problem, c.cert, c.grid, a, s);
 }
 
 template <typename T>
@@ -1023,12 +1162,12 @@ hipError_t launch_epilogue_typed(int problem, bool cert, int grid, const PassArg
 template <typename T, int EPL>
 hipError_t launch_pass_v(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
   constexpr int VF = (16 / (int)sizeof(T)) < EPL ? (16 / (int)sizeof(T)) : EPL;
-  if (c.vec == VF) return launch_pass_t<T, EPL, VF>(problem, c.cert, c.grid, a, s);
+  if (c.vec == VF) return launch_pass_t<T, EPL, VF>(problem, c, a, s);
   if constexpr (VF >= 4) {
-    if (c.vec == VF / 2) return launch_pass_t<T, EPL, VF / 2>(problem, c.cert, c.grid, a, s);
+    if (c.vec == VF / 2) return launch_pass_t<T, EPL, VF / 2>(problem, c, a, s);
   }
   if constexpr (VF > 1) {
-    if (c.vec == 1) return launch_pass_t<T, EPL, 1>(problem, c.cert, c.grid, a, s);
+    if (c.vec == 1) return launch_pass_t<T, EPL, 1>(problem, c, a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -11,6 +11,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <cstdlib>
 #include <vector>
 
 #include "../../include/scp_mwu.h"
@@ -377,8 +378,10 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   int grid = desc->grid > 0 ? desc->grid : cus;
   grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, (nb + kPassWaves - 1) / kPassWaves));
   c->grid = grid;
-  c->cfg = LaunchCfg{grid, epl, vec, false};
-  c->cfg_cert = LaunchCfg{grid, epl, vec, true};
+  const char *pfe = getenv("SCPMWU_PASS_PREFETCH");
+  const bool pf = pfe != nullptr && pfe[0] == '1';
+  c->cfg = LaunchCfg{grid, epl, vec, false, pf};
+  c->cfg_cert = LaunchCfg{grid, epl, vec, true, pf};
 
   const int pw = partial_width((int)c->d);
   if (hipMalloc(&c->st, sizeof(DevState)) != hipSuccess ||

@@ -306,3 +306,27 @@ def test_svm_end_to_end():
     assert abs(out["upper"] - ref.upper) / ref.upper <= NORTH_STAR_F32
     assert np.linalg.norm(np.array(out["w"]) - ref.w) <= NORTH_STAR_F32
     assert abs(out["s1"] + out["s2"] - ref.margin) / ref.margin <= NORTH_STAR_F32
+
+
+# -------------------------------------------------- rows past n are never read
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_rows_past_n_are_not_read(dt):
+    """The points are a view of the first n rows of a larger buffer whose
+    remaining rows hold NaN: a load that strays past row n - 1 (the last,
+    partial batch of each wave) would turn the sums into NaN."""
+    import torch
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    n, d = 1001, 36
+    V = synth.ses_gaussian_outliers(n, d, seed=21)
+    V = V.astype(np.float32).astype(np.float64)
+    buf = torch.full((n + 70, d), float("nan"), dtype=tdt)
+    buf[:n] = torch.from_numpy(V).to(tdt)
+    view = buf.cuda()[:n]
+    P = oses.setup(V)
+    ses_compare_steps(view, V, 0.8 * P.D, 3000, 12)
+    X, _ = synth.svm_planted(500, 501, d, seed=22)
+    X = X.astype(np.float32).astype(np.float64)
+    bufx = torch.full((1001 + 70, d), float("nan"), dtype=tdt)
+    bufx[:1001] = torch.from_numpy(X).to(tdt)
+    Pb = osvm.setup(X, 500)
+    svm_compare_steps(bufx.cuda()[:1001], X, 500, 0.5 * Pb.D, 2000, 12)
