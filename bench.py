@@ -11,14 +11,17 @@ device synchronisations; the reported value is MWU iterations per second.
 
 The same JSON line also carries
   roofline      bytes the pass must read (n d sizeof) over its mean HIP-event
-                duration, against the 8 TB/s HBM peak; HBM traffic from the
-                committed rocprofv3 counter summary when it matches the kernel;
+                duration, against the 8 TB/s HBM peak and against the
+                library's plain streaming-read kernel over the same number of
+                bytes; HBM traffic from the committed rocprofv3 counter
+                summary when it matches the kernel;
   bf16          the same measurement with BF16 storage (library-rounded copy);
   solve         eps = 1e-3 solves (FP32 and BF16 storage) with the paper's
                 Section 5 early stopping: wall time, iterations, tests,
                 certified bounds;
   cpu_baseline  the FP64 reference implementation timed on this host on a
-                bounded sample (a few iterations at the full size).
+                bounded sample (a few iterations at the full size), one
+                thread and all cores.
 """
 from __future__ import annotations
 
@@ -29,6 +32,8 @@ import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -84,26 +89,32 @@ def measure(X, storage, steps, warmup, alpha, T=20000):
 
 
 def copy_probe(X, reps=10):
-    """Plain streaming references on the same 400 MB: a read-only reduction
-    (torch sum) and a copy (torch copy_).  They give the achievable streaming
-    rate and the scale of the rocprofv3 FETCH_SIZE / WRITE_SIZE counters."""
+    """A plain copy of the same 400 MB (torch copy_): the kernel of known size
+    whose rocprofv3 FETCH_SIZE / WRITE_SIZE readings scale the counters."""
     import torch
     Y = torch.empty_like(X)
-    out = {}
-    for name, fn in (("read_sum", lambda: X.sum()), ("copy", lambda: Y.copy_(X))):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        moved = X.numel() * X.element_size() * (2 if name == "copy" else 1)
-        out[name] = dict(ms=round(ms, 5), GBs=round(moved / (ms * 1e-3) / 1e9, 1), bytes=moved)
+    Y.copy_(X)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        Y.copy_(X)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    moved = X.numel() * X.element_size() * 2
     del Y
-    return out
+    return dict(ms=round(ms, 5), GBs=round(moved / (ms * 1e-3) / 1e9, 1), bytes=moved)
+
+
+def read_reference(nbytes, X=None, reps=20):
+    """Achievable read bandwidth: the library's plain streaming-read kernel over
+    nbytes of device memory (the point matrix itself when given)."""
+    import torch
+    import paper_2405_09157_amd as scp
+    buf = X if X is not None else torch.empty(nbytes // 2, dtype=torch.int16, device="cuda")
+    ms = scp.scp_mwu_read_reference(buf.data_ptr(), nbytes, reps, torch.cuda.current_stream().cuda_stream)
+    return dict(ms=round(ms, 5), GBs=round(nbytes / (ms * 1e-3) / 1e9, 1), bytes=nbytes)
 
 
 def solve(X, storage):
@@ -121,31 +132,42 @@ def solve(X, storage):
                 cert_gap=(out["upper"] - out["lower"]) / out["lower"], converged=bool(out["converged"]))
 
 
-def cpu_baseline(V32, budget_s=20.0):
-    """FP64 oracle iterations at the full size on the host (bounded sample)."""
-    import numpy as np
+def _oracle_iters(V64, threads, warm, timed, budget_s):
+    """Median seconds per FP64 oracle iteration of the benchmarked alpha-test."""
     from threadpoolctl import threadpool_limits
     from oracle import ses as oses
-    with threadpool_limits(1):
-        V64 = V32.astype(np.float64)
+    with threadpool_limits(threads):
         P = oses.setup(V64)
         alpha, T = 0.8 * P.D, 20000
         eta = math.sqrt(math.log(P.r) / T)
         S = np.zeros(V64.shape[1])
-        t_prev = 0
-        times = []
+        t_prev, times = 0, []
         t_start = time.perf_counter()
-        while True:
+        while len(times) < warm + timed:
             t0 = time.perf_counter()
             st = oses.step(P, S, t_prev, alpha, eta)
             times.append(time.perf_counter() - t0)
             S, t_prev = st["S"], t_prev + 1
-            if time.perf_counter() - t_start > budget_s or len(times) >= 30:
+            if time.perf_counter() - t_start > budget_s and len(times) > warm:
                 break
-    per = sorted(times[1:] if len(times) > 2 else times)[len(times[1:] if len(times) > 2 else times) // 2]
-    return dict(value=1.0 / per, unit="iters/s", cores=1, kind="oracle",
-                sample=f"{len(times)} FP64 oracle iterations of the same n=1e6, d=100 test "
-                       f"(median of the last {max(len(times) - 1, 1)}), numpy single thread")
+    tt = sorted(times[warm:]) if len(times) > warm else sorted(times)
+    return tt[len(tt) // 2], len(times) - min(warm, len(times) - 1)
+
+
+def cpu_baseline(V32):
+    """The FP64 reference implementation (numpy) on the host at the full size,
+    on a bounded sample: a few iterations of the same alpha-test, one thread,
+    then with every core available to its BLAS calls."""
+    V64 = V32.astype(np.float64)
+    one, n1 = _oracle_iters(V64, 1, 1, 2, 15.0)
+    ncpu = os.cpu_count() or 1
+    allc, n2 = _oracle_iters(V64, ncpu, 1, 2, 12.0)
+    return dict(value=round(1.0 / one, 4), unit="iters/s", cores=1, kind="oracle",
+                sample=f"median of {n1} FP64 oracle iterations (after 1 warm-up) of the same "
+                       f"n=1e6, d=100 alpha-test, numpy on one thread",
+                all_cores=dict(value=round(1.0 / allc, 4), cores=ncpu,
+                               note=f"median of {n2} iterations with {ncpu} threads allowed "
+                                    f"(only the BLAS calls are threaded)"))
 
 
 def main(argv=None):
@@ -157,7 +179,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also time torch read/copy kernels on the same matrix")
+                    help="also time a plain copy of the matrix (counter calibration)")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -180,9 +202,13 @@ def main(argv=None):
     bf16 = None if a.no_bf16 else measure(X, "bf16", a.steps, a.warmup, alpha)
     if bf16:
         print(f"# bf16: {bf16}", file=sys.stderr, flush=True)
+    rref = dict(f32=read_reference(w["n"] * w["d"] * 4, X))
+    if bf16:
+        rref["bf16"] = read_reference(w["n"] * w["d"] * 2)
+    print(f"# read reference: {rref}", file=sys.stderr, flush=True)
     probe = copy_probe(X) if a.copy_probe else None
     if probe:
-        print(f"# streaming references: {probe}", file=sys.stderr, flush=True)
+        print(f"# copy: {probe}", file=sys.stderr, flush=True)
     sol = {}
     if not a.no_solve:
         sol["f32"] = solve(X, None)
@@ -201,8 +227,9 @@ def main(argv=None):
     ach = algo_bytes / (f32["kernel_ms"] * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_for("f32"),
-                kernel="ses_pass_kernel<float,8,4,false>", kernel_ms=round(f32["kernel_ms"], 5),
-                bytes_per_launch=algo_bytes)
+                kernel="ses_pass_kernel<float,8,4,false,false>", kernel_ms=round(f32["kernel_ms"], 5),
+                bytes_per_launch=algo_bytes, read_reference_GBs=rref["f32"]["GBs"],
+                frac_of_read_reference=round(ach / rref["f32"]["GBs"], 4))
     line = dict(metric=METRIC, value=round(1e3 / f32["ms_per_step"], 1), unit="iters/s", n_gpus=1,
                 steps=a.steps, warmup=a.warmup, ms_per_step=round(f32["ms_per_step"], 5),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
@@ -219,13 +246,14 @@ def main(argv=None):
                             roofline=dict(bound="hbm", achieved=round(b_ach, 1), peak=HBM_PEAK_GBS,
                                           unit="GB/s", frac=round(b_ach / HBM_PEAK_GBS, 4),
                                           traffic=traffic_for("bf16"),
-                                          kernel="ses_pass_kernel<uint16_t,8,4,false>",
-                                          kernel_ms=round(bf16["kernel_ms"], 5), bytes_per_launch=b_bytes))
+                                          kernel="ses_pass_kernel<uint16_t,8,4,false,false>",
+                                          kernel_ms=round(bf16["kernel_ms"], 5), bytes_per_launch=b_bytes,
+                                          read_reference_GBs=rref["bf16"]["GBs"],
+                                          frac_of_read_reference=round(b_ach / rref["bf16"]["GBs"], 4)))
     if sol:
         line["solve"] = sol
     if probe:
-        line["streaming_reference"] = probe
-        line["roofline"]["frac_of_read_reference"] = round(ach / probe["read_sum"]["GBs"], 4)
+        line["copy_reference"] = probe
     print(json.dumps(line), flush=True)
     return 0
 

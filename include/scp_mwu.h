@@ -279,6 +279,17 @@ const char *scp_mwu_strerror(int code);
  */
 int scp_mwu_cast_bf16(const float *src, uint16_t *dst, int64_t n, void *stream);
 
+/*
+ * Measurement helper: the achievable read bandwidth the streaming pass is
+ * held to.  Times reps >= 1 launches of a plain streaming read of the bytes
+ * bytes at buf (device, 16-byte aligned, only read; no arithmetic on the data)
+ * on the stream (a hipStream_t; NULL = default), after one untimed launch,
+ * and returns the mean milliseconds per launch in *ms (host).  Allocates and
+ * frees a 64-byte device buffer.  E_INVAL (NULL, bytes <= 0, reps < 1,
+ * misaligned buf), E_NOMEM, E_HIP.
+ */
+int scp_mwu_read_reference(const void *buf, int64_t bytes, int32_t reps, void *stream, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

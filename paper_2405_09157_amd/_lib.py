@@ -30,7 +30,7 @@ OUTCOME_NAMES = {0: "running", 1: "separated", 2: "beat_alpha", 3: "stabilized",
 EXPORTS = ("scp_mwu_init", "scp_mwu_step", "scp_mwu_solve", "scp_mwu_backward",
            "scp_mwu_get_state", "scp_mwu_set_state", "scp_mwu_get_vector", "scp_mwu_get_D",
            "scp_mwu_destroy", "scp_mwu_last_error", "scp_mwu_strerror", "scp_mwu_cast_bf16",
-           "scp_mwu_time_passes")
+           "scp_mwu_time_passes", "scp_mwu_read_reference")
 
 
 class scp_mwu_desc(ctypes.Structure):
@@ -119,6 +119,7 @@ def load() -> ctypes.CDLL:
         "scp_mwu_strerror": (ctypes.c_char_p, [i32]),
         "scp_mwu_cast_bf16": (i32, [vp, vp, i64, vp]),
         "scp_mwu_time_passes": (i32, [vp, i32, P(f64), P(f64)]),
+        "scp_mwu_read_reference": (i32, [vp, i64, i32, vp, P(f64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -205,6 +206,13 @@ def scp_mwu_time_passes(ctx, k: int):
     mp, mi = ctypes.c_double(), ctypes.c_double()
     _check(load().scp_mwu_time_passes(ctx, k, ctypes.byref(mp), ctypes.byref(mi)), ctx)
     return mp.value, mi.value
+
+
+def scp_mwu_read_reference(ptr: int, nbytes: int, reps: int = 20, stream: int = 0) -> float:
+    """Mean ms of a plain streaming read of nbytes at device address ptr."""
+    ms = ctypes.c_double()
+    _check(load().scp_mwu_read_reference(ptr, nbytes, reps, stream, ctypes.byref(ms)))
+    return ms.value
 
 
 def scp_mwu_strerror(code: int) -> str:

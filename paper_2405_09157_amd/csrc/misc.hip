@@ -1,5 +1,6 @@
-// Small non-iterative kernels: resuming a test from given running sums and
-// the FP32 -> BF16 storage conversion.
+// Small non-iterative kernels: resuming a test from given running sums, the
+// FP32 -> BF16 storage conversion, and a plain streaming read of a buffer
+// (the achievable-read-bandwidth reference the streaming pass is held to).
 #include <algorithm>
 
 #include "mwu_kernels.hpp"
@@ -48,6 +49,55 @@ __global__ __launch_bounds__(kBlock) void cast_bf16_kernel(const float *src, uin
       h = (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
     dst[r * ld_dst + c] = (uint16_t)h;
   }
+}
+
+// Streaming read, no arithmetic on the data: each wave moves chunks of
+// kReadChunk bytes into a two-stage LDS ring with buffer-to-LDS loads (16 B
+// per lane), the next chunk in flight while the previous one is consumed.
+// A resource per chunk bounds it (its tail reads zeros); nothing is written
+// unless an impossible sum appears, so the loads cannot be elided.
+constexpr int kReadU = 4;                      // 1 KB loads per chunk
+constexpr int kReadChunk = kReadU * 1024;      // bytes per wave per stage
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+__global__ __launch_bounds__(kPassBlock) void read_reference_kernel(const char *buf, int64_t bytes, float *sink) {
+  __shared__ __attribute__((aligned(16))) float4 ring[kPassWaves * 2 * kReadU * 64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t nchunks = (bytes + kReadChunk - 1) / kReadChunk;
+  const int64_t gw = (int64_t)gridDim.x * kPassWaves;
+  float4 *mine = ring + wave * 2 * kReadU * 64;
+  auto issue = [&](int64_t c, int stage) {
+    const int64_t base = c * kReadChunk;
+    const int64_t left = bytes - base;
+    const __amdgpu_buffer_rsrc_t r = uniform_rsrc(buf + base, (int32_t)(left < kReadChunk ? left : kReadChunk));
+#pragma unroll
+    for (int u = 0; u < kReadU; ++u)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t *)(mine + (stage * kReadU + u) * 64), 16,
+                                               (unsigned)(lane * 16 + u * 1024), 0, 0, 0);
+  };
+  float acc = 0.f;
+  int stage = 0;
+  int64_t c = (int64_t)blockIdx.x * kPassWaves + wave;
+  if (c < nchunks) issue(c, 0);
+  for (; c < nchunks; c += gw) {
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's chunk is in LDS
+    __builtin_amdgcn_wave_barrier();
+    float4 v[kReadU];
+#pragma unroll
+    for (int u = 0; u < kReadU; ++u) v[u] = mine[(stage * kReadU + u) * 64 + lane];
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the stage is free again
+    if (c + gw < nchunks) issue(c + gw, stage ^ 1);
+#pragma unroll
+    for (int u = 0; u < kReadU; ++u) acc += v[u].x + v[u].y + v[u].z + v[u].w;
+    stage ^= 1;
+  }
+  if (acc == 1.2345e-30f) sink[blockIdx.x & 15] = acc;
+}
+
+hipError_t launch_read_reference(const void *buf, int64_t bytes, int grid, float *sink, hipStream_t s) {
+  hipLaunchKernelGGL(read_reference_kernel, dim3(grid), dim3(kPassBlock), 0, s, reinterpret_cast<const char *>(buf),
+                     bytes, sink);
+  return hipGetLastError();
 }
 
 hipError_t launch_set_state_k(const PassArgs &a, int problem, int64_t t, double S1, double S2,

@@ -109,6 +109,8 @@ struct LaunchCfg {
   bool pf;     // two register batches, the next one loading (prefetch)
 };
 
+hipError_t launch_read_reference(const void *buf, int64_t bytes, int grid, float *sink, hipStream_t s);
+
 #define SCPMWU_DECLARE_TYPED(name)                                                              \
   hipError_t launch_pass_##name(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s); \
   hipError_t launch_epilogue_##name(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s); \

@@ -243,28 +243,32 @@ __device__ __forceinline__ double block_sum(double v, double *s_red) {
 constexpr int32_t kBufWord3 = 0x00020000;  // raw buffer, gfx9 family
 constexpr int32_t kOffInvalid = 0x40000000;  // a lane offset beyond any batch
 
-// r0 and rows are wave-uniform; they are read from the first lane so that the
-// resource is built in scalar registers (a resource the compiler cannot prove
-// uniform makes it loop over lanes around every load).
+// A raw buffer resource over [base, base + num bytes) built from the first
+// lane's values (the caller guarantees they are wave-uniform), so that it
+// lives in scalar registers: a resource the compiler cannot prove uniform
+// makes it loop over lanes around every load.  readfirstlane returns a signed
+// int: both address halves go through uint32_t so that the low half is
+// zero-extended.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void *base, int32_t num) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(((uint64_t)hi << 32) | (uint64_t)lo), (short)0,
+                                           __builtin_amdgcn_readfirstlane(num), kBufWord3);
+}
+
+// Rows [r0, r0 + rows) of X (r0, rows wave-uniform).
 template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const T *X, int64_t r0, int64_t rows, int64_t ld,
                                                           int d) {
   const int32_t num = rows > 0 ? (int32_t)(((rows - 1) * ld + d) * (int64_t)sizeof(T)) : 0;
-  const uint64_t base = reinterpret_cast<uint64_t>(X + r0 * ld);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<T *>(((uint64_t)hi << 32) | lo), (short)0,
-                                           __builtin_amdgcn_readfirstlane(num), kBufWord3);
+  return uniform_rsrc(X + r0 * ld, num);
 }
 
 // Radii of rows [r0, r0 + rows) (none: an empty resource, every load reads 0).
 __device__ __forceinline__ double radius_load(const double *radii, int64_t r0, int64_t rows, int lane) {
   const int32_t num = (radii != nullptr && rows > 0) ? (int32_t)(rows * 8) : 0;
-  const uint64_t base = radii != nullptr ? reinterpret_cast<uint64_t>(radii + r0) : 0;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-      reinterpret_cast<void *>(((uint64_t)hi << 32) | lo), (short)0, __builtin_amdgcn_readfirstlane(num), kBufWord3);
+  const __amdgpu_buffer_rsrc_t r = uniform_rsrc(radii != nullptr ? radii + r0 : nullptr, num);
   const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, lane * 8, 0, 0);
   double g;
   __builtin_memcpy(&g, &v, 8);

@@ -696,6 +696,34 @@ int scp_mwu_solve(scp_mwu_ctx *c, scp_mwu_result *res, double *y) {
   return converged ? SCP_MWU_OK : SCP_MWU_STOPPED;
 }
 
+int scp_mwu_read_reference(const void *buf, int64_t bytes, int32_t reps, void *stream, double *ms) {
+  if (!buf || !ms || bytes <= 0 || reps < 1 || (reinterpret_cast<uintptr_t>(buf) & 15u) != 0)
+    return SCP_MWU_E_INVAL;
+  const hipStream_t s = (hipStream_t)stream;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return SCP_MWU_E_HIP;
+  float *sink = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = SCP_MWU_OK;
+  if (hipMalloc(&sink, 64) != hipSuccess) return SCP_MWU_E_NOMEM;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = SCP_MWU_E_HIP;
+  // one launch to warm up, then reps timed launches
+  if (!rc && launch_read_reference(buf, bytes, cus, sink, s) != hipSuccess) rc = SCP_MWU_E_HIP;
+  if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = SCP_MWU_E_HIP;
+  for (int32_t i = 0; i < reps && !rc; ++i)
+    if (launch_read_reference(buf, bytes, cus, sink, s) != hipSuccess) rc = SCP_MWU_E_HIP;
+  if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)) rc = SCP_MWU_E_HIP;
+  float t = 0.f;
+  if (!rc && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = SCP_MWU_E_HIP;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(sink);
+  if (!rc) *ms = (double)t / reps;
+  return rc;
+}
+
 int scp_mwu_cast_bf16(const float *src, uint16_t *dst, int64_t n, void *stream) {
   if (!src || !dst || n < 0) return SCP_MWU_E_INVAL;
   if (n == 0) return SCP_MWU_OK;

@@ -330,3 +330,18 @@ def test_rows_past_n_are_not_read(dt):
     bufx[:1001] = torch.from_numpy(X).to(tdt)
     Pb = osvm.setup(X, 500)
     svm_compare_steps(bufx.cuda()[:1001], X, 500, 0.5 * Pb.D, 2000, 12)
+
+
+# ------------------------------------------------------ measurement helpers
+def test_read_reference_entry_point():
+    """The streaming-read reference times a read of the given bytes (a ragged
+    size included) and rejects misaligned or empty buffers."""
+    import torch
+    import paper_2405_09157_amd as scp
+    buf = torch.zeros(1 << 22, dtype=torch.float32, device="cuda")
+    for nbytes in (buf.numel() * 4, 12345 * 16 + 8, 16):
+        ms = scp.scp_mwu_read_reference(buf.data_ptr(), nbytes, 3)
+        assert 0.0 < ms < 100.0
+    for bad in ((buf.data_ptr() + 4, 1024), (buf.data_ptr(), 0)):
+        with pytest.raises(scp.ScpMwuError):
+            scp.scp_mwu_read_reference(bad[0], bad[1], 1)
