@@ -29,6 +29,26 @@ inline __host__ __device__ int partial_width(int d) { return 2 * ((d + 1) & ~1) 
 
 enum Problem : int32_t { kSES = 1, kSVM = 2 };
 enum DType : int32_t { kF32 = 1, kBF16 = 2, kF64 = 3 };
+
+// Load steps per batch of the streaming pass (B = 4 * steps rows, B <= 64),
+// shared by the kernels and the host's grid sizing.  A batch's elements stay
+// in registers through its three phases, within a budget of 64 VGPRs:
+// binary32 registers for F32 and BF16 values, binary64 for F64; SES with BF16
+// storage and an even number (at most 16) of columns per lane keeps the raw
+// pairs (two elements per register, widened on use), which doubles the rows
+// per batch.  SVM keeps two binary64 class accumulators per column and halves
+// the budget; with prefetch two batches share it.  At most 8 steps (16 for
+// packed BF16, whose per-row phase then fills the wave).
+inline __host__ __device__ constexpr bool pass_packed(int storage_size, int epl, int problem) {
+  return storage_size == 2 && epl % 2 == 0 && epl <= 16 && problem == kSES;
+}
+inline __host__ __device__ constexpr int pass_steps(int storage_size, int epl, int problem, bool pf) {
+  const bool pack = pass_packed(storage_size, epl, problem);
+  const int lim = (storage_size == 8 ? 32 : (pack ? 128 : 64)) / (problem == kSVM ? 2 : 1) / (pf ? 2 : 1);
+  const int cap = pack ? 16 : 8;
+  return lim / epl < 1 ? 1 : (lim / epl > cap ? cap : lim / epl);
+}
+
 enum Status : int32_t {
   kRunning = 0,
   kSeparated = 1,

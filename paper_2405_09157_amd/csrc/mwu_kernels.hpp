@@ -150,19 +150,13 @@ struct Batch<uint16_t, SB, EPL, true> {
   }
 };
 
-// Batch shape: SB load steps of 4 rows (B = 4 SB <= 32 rows).  The batch
-// registers get a budget of 64 VGPRs: one batch, or with PF (prefetch) two
-// of half the size, the next batch loading while the current one is
-// processed.  SVM keeps two binary64 class accumulators per column and halves
-// the budget.  With PF, BF16 batches are packed (same rows, half the
-// registers).
+// Batch shape of the streaming pass (pass_steps): SB load steps of 4 rows.
 template <typename T, int EPL, int PROB, bool PF>
 struct PassShape {
-  static constexpr bool PACK = PF && sizeof(T) == 2 && EPL % 2 == 0;
-  static constexpr int ESZ = (int)sizeof(typename RegT<T>::type);
-  static constexpr int LIM = (ESZ == 8 ? 32 : (PACK ? 128 : 64)) / (PROB == kSVM ? 2 : 1) / (PF ? 2 : 1);
-  static constexpr int SB = (LIM / EPL) < 8 ? ((LIM / EPL) > 0 ? LIM / EPL : 1) : 8;
+  static constexpr bool PACK = pass_packed((int)sizeof(T), EPL, PROB);
+  static constexpr int SB = pass_steps((int)sizeof(T), EPL, PROB, PF);
   static constexpr int B = SB * kRowsPerStep;
+  static_assert(B <= kWave, "the per-row phase holds one row per lane");
   using Regs = Batch<T, SB, EPL, PACK>;
 };
 

@@ -372,14 +372,13 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
       break;
     }
   }
-  const int lim = (c->dtype == kF64 ? 32 : 64) / (c->problem == kSVM ? 2 : 1);
-  const int B = std::max(1, std::min(8, lim / epl)) * kRowsPerStep;
+  const char *pfe = getenv("SCPMWU_PASS_PREFETCH");
+  const bool pf = pfe != nullptr && pfe[0] == '1';
+  const int B = pass_steps(es, epl, c->problem, pf) * kRowsPerStep;
   const int64_t nb = (c->n + B - 1) / B;
   int grid = desc->grid > 0 ? desc->grid : cus;
   grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, (nb + kPassWaves - 1) / kPassWaves));
   c->grid = grid;
-  const char *pfe = getenv("SCPMWU_PASS_PREFETCH");
-  const bool pf = pfe != nullptr && pfe[0] == '1';
   c->cfg = LaunchCfg{grid, epl, vec, false, pf};
   c->cfg_cert = LaunchCfg{grid, epl, vec, true, pf};
 

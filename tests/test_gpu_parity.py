@@ -131,6 +131,20 @@ def test_ses_bf16_step_parity_on_stored_values():
     ses_compare_steps(dev(V, torch.float32), Vq, 0.8 * P.D, 3000, 10, storage="bf16")
 
 
+@pytest.mark.parametrize("n,d", [(1001, 3), (517, 20), (2049, 64), (777, 100), (1500, 200), (63, 32)])
+def test_ses_bf16_step_parity_shapes(n, d):
+    """BF16 storage at every column layout (1, 2, 4, 8, 16 columns per lane:
+    raw BF16 pairs are kept packed for an even count, with batches of up to
+    64 rows), ragged n with a partial last batch, at the 1e-9 bar on the
+    stored values."""
+    import torch
+    V = synth.ses_gaussian_outliers(n, d, seed=n + d).astype(np.float32)
+    h, Vq = bf16_points(V)
+    Vb = torch.from_numpy(h.view(np.int16)).cuda().view(torch.bfloat16)
+    P = oses.setup(Vq)
+    ses_compare_steps(Vb, Vq, 0.8 * P.D, 3000, 12)
+
+
 def test_bf16_cast_bit_exact():
     import torch
     import paper_2405_09157_amd as scp
