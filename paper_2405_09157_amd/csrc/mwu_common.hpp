@@ -42,9 +42,13 @@ enum DType : int32_t { kF32 = 1, kBF16 = 2, kF64 = 3 };
 inline __host__ __device__ constexpr bool pass_packed(int storage_size, int epl, int problem) {
   return storage_size == 2 && epl % 2 == 0 && epl <= 16 && problem == kSES;
 }
-inline __host__ __device__ constexpr int pass_steps(int storage_size, int epl, int problem, bool pf) {
+// Prefetch modes of the streaming pass: none, or two register batches (the
+// next one loading while the current one is processed).
+enum Prefetch : int32_t { kPrefetchNone = 0, kPrefetchRegs = 1 };
+inline __host__ __device__ constexpr int pass_steps(int storage_size, int epl, int problem, int pfm) {
   const bool pack = pass_packed(storage_size, epl, problem);
-  const int lim = (storage_size == 8 ? 32 : (pack ? 128 : 64)) / (problem == kSVM ? 2 : 1) / (pf ? 2 : 1);
+  const int lim = (storage_size == 8 ? 32 : (pack ? 128 : 64)) / (problem == kSVM ? 2 : 1) /
+                  (pfm == kPrefetchRegs ? 2 : 1);
   const int cap = pack ? 16 : 8;
   return lim / epl < 1 ? 1 : (lim / epl > cap ? cap : lim / epl);
 }
@@ -126,7 +130,7 @@ struct LaunchCfg {
   int epl;     // columns per lane: 16 * epl >= d
   int vec;     // elements per vector load (1 = scalar loads)
   bool cert;   // SES weight certificate accumulators
-  bool pf;     // two register batches, the next one loading (prefetch)
+  int pfm;     // Prefetch mode
 };
 
 hipError_t launch_read_reference(const void *buf, int64_t bytes, int grid, float *sink, hipStream_t s);

@@ -151,10 +151,10 @@ struct Batch<uint16_t, SB, EPL, true> {
 };
 
 // Batch shape of the streaming pass (pass_steps): SB load steps of 4 rows.
-template <typename T, int EPL, int PROB, bool PF>
+template <typename T, int EPL, int PROB, int PFM>
 struct PassShape {
   static constexpr bool PACK = pass_packed((int)sizeof(T), EPL, PROB);
-  static constexpr int SB = pass_steps((int)sizeof(T), EPL, PROB, PF);
+  static constexpr int SB = pass_steps((int)sizeof(T), EPL, PROB, PFM);
   static constexpr int B = SB * kRowsPerStep;
   static_assert(B <= kWave, "the per-row phase holds one row per lane");
   using Regs = Batch<T, SB, EPL, PACK>;
@@ -317,10 +317,18 @@ __host__ __device__ inline int rec_dp(int d) { return (d + 1) & ~1; }
 __host__ __device__ inline int rec_width(int d) { return partial_width(d); }
 
 // =========================================================== SES pass
-template <typename T, int EPL, int VEC, bool CERT, bool PF>
+// Column of element k (chunk k / VEC) of lane cl: chunk q of the 16 lanes of
+// a row covers VEC * 16 contiguous columns, so every load instruction reads
+// whole lines.
+template <int VEC>
+__device__ __forceinline__ int lane_col(int cl, int k) {
+  return ((k / VEC) * kG + cl) * VEC + (k % VEC);
+}
+
+template <typename T, int EPL, int VEC, bool CERT, int PFM>
 __global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
 void ses_pass_kernel(PassArgs a) {
-  using Sh = PassShape<T, EPL, kSES, PF>;
+  using Sh = PassShape<T, EPL, kSES, PFM>;
   constexpr int SB = Sh::SB, B = Sh::B;
   using Regs = typename Sh::Regs;
   __shared__ double s_part[kPassWaves][B][kG + 1];
@@ -360,7 +368,7 @@ void ses_pass_kernel(PassArgs a) {
   int32_t voff[EPL / VEC];
 #pragma unroll
   for (int q = 0; q < EPL / VEC; ++q) {
-    const int c0 = cl * EPL + q * VEC;
+    const int c0 = lane_col<VEC>(cl, q * VEC);
     voff[q] = c0 < d ? (int32_t)(((int64_t)g * ld + c0) * (int64_t)sizeof(T)) : kOffInvalid;
   }
   const int32_t step_bytes = (int32_t)(kRowsPerStep * ld * (int64_t)sizeof(T));
@@ -383,7 +391,7 @@ void ses_pass_kernel(PassArgs a) {
     asm volatile("" ::: "memory");
     double ub[EPL];
 #pragma unroll
-    for (int k = 0; k < EPL; ++k) ub[k] = s_ctr[cl * EPL + k];
+    for (int k = 0; k < EPL; ++k) ub[k] = s_ctr[lane_col<VEC>(cl, k)];
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       double dsq = 0.0;
@@ -442,7 +450,7 @@ void ses_pass_kernel(PassArgs a) {
   // status0 is the same for the whole grid: either every wave returns below
   // (after this barrier) or none does
   __syncthreads();
-  if constexpr (PF) {
+  if constexpr (PFM == kPrefetchRegs) {
     // two register batches, unrolled by two so that neither is copied: the
     // loads of the next batch are in flight while the current one is
     // processed.  The loads are unconditional (a batch past the end has an
@@ -482,7 +490,7 @@ void ses_pass_kernel(PassArgs a) {
   const int pw = rec_width(d);
   if (g == 0)
 #pragma unroll
-    for (int k = 0; k < EPL; ++k) s_vec[wave][cl * EPL + k] = wacc[k];
+    for (int k = 0; k < EPL; ++k) s_vec[wave][lane_col<VEC>(cl, k)] = wacc[k];
   asum = wave_sum(asum);
   bsum = wave_sum(bsum);
   esum = wave_sum(esum);
@@ -512,7 +520,7 @@ void ses_pass_kernel(PassArgs a) {
     }
     if (g == 0)
 #pragma unroll
-      for (int k = 0; k < EPL; ++k) s_vec[wave][cl * EPL + k] = cacc[k];
+      for (int k = 0; k < EPL; ++k) s_vec[wave][lane_col<VEC>(cl, k)] = cacc[k];
     __syncthreads();
     for (int c = tid; c < d; c += kPassBlock) rec[dp + 8 + c] = sum_waves(s_vec, c);
   }
@@ -529,10 +537,10 @@ void ses_pass_kernel(PassArgs a) {
 }
 
 // =========================================================== SVM pass
-template <typename T, int EPL, int VEC, bool PF>
+template <typename T, int EPL, int VEC, int PFM>
 __global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
 void svm_pass_kernel(PassArgs a) {
-  using Sh = PassShape<T, EPL, kSVM, PF>;
+  using Sh = PassShape<T, EPL, kSVM, PFM>;
   constexpr int SB = Sh::SB, B = Sh::B;
   using Regs = typename Sh::Regs;
   __shared__ double s_part[kPassWaves][B][kG + 1];
@@ -650,7 +658,7 @@ void svm_pass_kernel(PassArgs a) {
   // status0 is the same for the whole grid: either every wave returns below
   // (after this barrier) or none does
   __syncthreads();
-  if constexpr (PF) {
+  if constexpr (PFM == kPrefetchRegs) {
     Regs xa, xb;
     int64_t b = b0;
     load_batch(xa, b);
@@ -1125,23 +1133,23 @@ __global__ __launch_bounds__(kBlock) void ftp_init_kernel(PassArgs a, InitParams
 }
 
 // ============================================================== dispatch
-template <typename T, int EPL, int VEC, bool PF>
+template <typename T, int EPL, int VEC, int PFM>
 hipError_t launch_pass_p(int problem, bool cert, int grid, const PassArgs &a, hipStream_t s) {
   if (problem == kSES) {
     if (cert)
-      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, true, PF>), dim3(grid), dim3(kPassBlock), 0, s, a);
+      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, true, PFM>), dim3(grid), dim3(kPassBlock), 0, s, a);
     else
-      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, false, PF>), dim3(grid), dim3(kPassBlock), 0, s, a);
+      hipLaunchKernelGGL((ses_pass_kernel<T, EPL, VEC, false, PFM>), dim3(grid), dim3(kPassBlock), 0, s, a);
   } else {
-    hipLaunchKernelGGL((svm_pass_kernel<T, EPL, VEC, PF>), dim3(grid), dim3(kPassBlock), 0, s, a);
+    hipLaunchKernelGGL((svm_pass_kernel<T, EPL, VEC, PFM>), dim3(grid), dim3(kPassBlock), 0, s, a);
   }
   return hipGetLastError();
 }
 
 template <typename T, int EPL, int VEC>
 hipError_t launch_pass_t(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
-  return c.pf ? launch_pass_p<T, EPL, VEC, true>(problem, c.cert, c.grid, a, s)
-              : launch_pass_p<T, EPL, VEC, false>(problem, c.cert, c.grid, a, s);
+  return c.pfm == kPrefetchRegs ? launch_pass_p<T, EPL, VEC, kPrefetchRegs>(problem, c.cert, c.grid, a, s)
+                                : launch_pass_p<T, EPL, VEC, kPrefetchNone>(problem, c.cert, c.grid, a, s);
 }
 
 template <typename T>

@@ -372,15 +372,18 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
       break;
     }
   }
-  const char *pfe = getenv("SCPMWU_PASS_PREFETCH");
-  const bool pf = pfe != nullptr && pfe[0] == '1';
-  const int B = pass_steps(es, epl, c->problem, pf) * kRowsPerStep;
+  // prefetch mode: none (measured fastest); SCPMWU_PASS_PREFETCH=1 selects two
+  // register batches
+  int pfm = kPrefetchNone;
+  if (const char *pfe = getenv("SCPMWU_PASS_PREFETCH"))
+    if (pfe[0] == '1') pfm = kPrefetchRegs;
+  const int B = pass_steps(es, epl, c->problem, pfm) * kRowsPerStep;
   const int64_t nb = (c->n + B - 1) / B;
   int grid = desc->grid > 0 ? desc->grid : cus;
   grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, (nb + kPassWaves - 1) / kPassWaves));
   c->grid = grid;
-  c->cfg = LaunchCfg{grid, epl, vec, false, pf};
-  c->cfg_cert = LaunchCfg{grid, epl, vec, true, pf};
+  c->cfg = LaunchCfg{grid, epl, vec, false, pfm};
+  c->cfg_cert = LaunchCfg{grid, epl, vec, true, pfm};
 
   const int pw = partial_width((int)c->d);
   if (hipMalloc(&c->st, sizeof(DevState)) != hipSuccess ||

@@ -359,3 +359,18 @@ def test_read_reference_entry_point():
     for bad in ((buf.data_ptr() + 4, 1024), (buf.data_ptr(), 0)):
         with pytest.raises(scp.ScpMwuError):
             scp.scp_mwu_read_reference(bad[0], bad[1], 1)
+
+
+# ------------------------------------------------------------- prefetch modes
+@pytest.mark.parametrize("mode", ["0", "1"])
+def test_ses_prefetch_modes(mode, monkeypatch):
+    """Both loop schedules of the pass (one register batch; two, the next one
+    loading) at the 1e-9 bar: F32 and F64 storage, ragged n, several column
+    layouts."""
+    import torch
+    monkeypatch.setenv("SCPMWU_PASS_PREFETCH", mode)
+    for n, d, tdt in ((3001, 100, torch.float32), (2049, 64, torch.float32), (1100, 200, torch.float32),
+                      (999, 33, torch.float32), (777, 48, torch.float64)):
+        V = synth.ses_gaussian_outliers(n, d, seed=n).astype(np.float32).astype(np.float64)
+        P = oses.setup(V)
+        ses_compare_steps(dev(V, tdt), V, 0.8 * P.D, 3000, 8)
