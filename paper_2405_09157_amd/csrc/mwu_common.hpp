@@ -27,6 +27,19 @@ constexpr int kMaxD = 512;
 // length) around 8 scalars, so that pairs of entries are 16-byte aligned.
 inline __host__ __device__ int partial_width(int d) { return 2 * ((d + 1) & ~1) + 8; }
 
+// Records are summed by the one-workgroup epilogue kernel, whose loads are
+// bound by one compute unit; when the records it would read exceed
+// kRecSingleBytes, a first kernel of ceil(grid / kRecGroup) workgroups sums
+// groups of kRecGroup records (the extra kernel boundary costs a few us, the
+// single unit reads ~40 KB/us).  The record buffer holds grid + that many
+// records.
+constexpr int kRecGroup = 16;
+constexpr int64_t kRecSingleBytes = 384 * 1024;
+inline __host__ __device__ int rec_groups(int grid) { return (grid + kRecGroup - 1) / kRecGroup; }
+inline __host__ __device__ bool rec_two_level(int grid, int read_cols) {
+  return rec_groups(grid) > 1 && (int64_t)grid * read_cols * 8 > kRecSingleBytes;
+}
+
 enum Problem : int32_t { kSES = 1, kSVM = 2 };
 enum DType : int32_t { kF32 = 1, kBF16 = 2, kF64 = 3 };
 

@@ -971,6 +971,36 @@ __device__ inline void svm_epilogue(const PassArgs &a, DevState &S, const double
   }
 }
 
+// Columns of a record the epilogue reads: SES without a certificate skips the
+// second vector.
+template <int PROB, bool CERT>
+__host__ __device__ inline int rec_read_cols(int d) {
+  return (PROB == kSES && !CERT) ? rec_dp(d) + 8 : rec_width(d);
+}
+
+// First level of the record combine (large records only): workgroup g sums
+// records [g * kRecGroup, (g + 1) * kRecGroup) column by column in record
+// order (the maximum slots by max) into record g of `out`.
+template <int PROB, bool CERT>
+__global__ __launch_bounds__(kBlock) void record_combine_kernel(const double *__restrict__ in, int P, int d,
+                                                                double *__restrict__ out) {
+  const int dp = rec_dp(d), pw = rec_width(d);
+  const int ncols = rec_read_cols<PROB, CERT>(d);
+  const int nsc = PROB == kSES ? 5 : 4;
+  const int b0 = blockIdx.x * kRecGroup;
+  const int b1 = b0 + kRecGroup < P ? b0 + kRecGroup : P;
+  for (int c = threadIdx.x; c < ncols; c += kBlock) {
+    const bool mx = c >= dp + nsc && c < dp + 8;
+    double acc = mx ? -INFINITY : 0.0;
+#pragma unroll 16
+    for (int b = b0; b < b1; ++b) {
+      const double v = in[(int64_t)b * pw + c];
+      acc = mx ? fmax(acc, v) : acc + v;
+    }
+    out[(int64_t)blockIdx.x * pw + c] = acc;
+  }
+}
+
 static_assert(sizeof(DevState) % 8 == 0, "DevState is copied as 8-byte words");
 constexpr int kStateWords = (int)(sizeof(DevState) / 8);
 
@@ -988,7 +1018,7 @@ __global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P)
   const int d = (int)a.d;
   const int tid = threadIdx.x;
   const int dp = rec_dp(d), pw = rec_width(d);
-  const int ncols = (PROB == kSES && !CERT) ? dp + 8 : pw;  // the certificate half is not read
+  const int ncols = rec_read_cols<PROB, CERT>(d);  // the certificate half is read only with one
   const int nsc = PROB == kSES ? 5 : 4;                      // summed scalars
   const int npairs = ncols / 2;
   const int groups = kCombBlock / npairs;
@@ -1152,17 +1182,28 @@ hipError_t launch_pass_t(int problem, const LaunchCfg &c, const PassArgs &a, hip
                                 : launch_pass_p<T, EPL, VEC, kPrefetchNone>(problem, c.cert, c.grid, a, s);
 }
 
+template <typename T, int PROB, bool CERT>
+hipError_t launch_epilogue_p(int grid, const PassArgs &a, hipStream_t s) {
+  // records of the pass: a.partials[0 .. grid); group sums after them
+  PassArgs e = a;
+  int P = grid;
+  const int d = (int)a.d;
+  if (rec_two_level(grid, rec_read_cols<PROB, CERT>(d))) {
+    double *l1 = a.partials + (int64_t)grid * rec_width(d);
+    hipLaunchKernelGGL((record_combine_kernel<PROB, CERT>), dim3(rec_groups(grid)), dim3(kBlock), 0, s, a.partials,
+                       grid, d, l1);
+    e.partials = l1;
+    P = rec_groups(grid);
+  }
+  hipLaunchKernelGGL((epilogue_kernel<T, PROB, CERT>), dim3(1), dim3(kCombBlock), 0, s, e, P);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_epilogue_typed(int problem, bool cert, int grid, const PassArgs &a, hipStream_t s) {
-  if (problem == kSES) {
-    if (cert)
-      hipLaunchKernelGGL((epilogue_kernel<T, kSES, true>), dim3(1), dim3(kCombBlock), 0, s, a, grid);
-    else
-      hipLaunchKernelGGL((epilogue_kernel<T, kSES, false>), dim3(1), dim3(kCombBlock), 0, s, a, grid);
-  } else {
-    hipLaunchKernelGGL((epilogue_kernel<T, kSVM, false>), dim3(1), dim3(kCombBlock), 0, s, a, grid);
-  }
-  return hipGetLastError();
+  if (problem == kSES)
+    return cert ? launch_epilogue_p<T, kSES, true>(grid, a, s) : launch_epilogue_p<T, kSES, false>(grid, a, s);
+  return launch_epilogue_p<T, kSVM, false>(grid, a, s);
 }
 
 template <typename T, int EPL>

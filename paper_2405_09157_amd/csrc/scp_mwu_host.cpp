@@ -388,7 +388,7 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   const int pw = partial_width((int)c->d);
   if (hipMalloc(&c->st, sizeof(DevState)) != hipSuccess ||
       hipMalloc(&c->vec, sizeof(double) * kNumVec * c->d) != hipSuccess ||
-      hipMalloc(&c->partials, sizeof(double) * (size_t)grid * pw) != hipSuccess ||
+      hipMalloc(&c->partials, sizeof(double) * (size_t)(grid + rec_groups(grid)) * pw) != hipSuccess ||
       hipMalloc(&c->mon, sizeof(double) * (size_t)grid * 4) != hipSuccess ||
       hipHostMalloc((void **)&c->host_st, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
     return fail(SCP_MWU_E_NOMEM, "workspace allocation");
