@@ -168,33 +168,47 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-  return v;
+// Wave reductions without LDS round trips: DPP moves within each 16-lane row
+// (pairs, quads, then rotations by 4 and 8 lanes), then the four row values
+// read from lanes 0, 16, 32, 48 and combined in that fixed order.  Every lane
+// returns the same value; the order is fixed, so results are reproducible.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
-// Several wave sums in one butterfly, so their shuffle latencies overlap.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l), __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+constexpr int kDppPairs = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kDppQuads = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int kDppRor4 = 0x124;  // row_ror:4
+constexpr int kDppRor8 = 0x128;  // row_ror:8
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<kDppPairs>(v);
+  v += dpp_f64<kDppQuads>(v);
+  v += dpp_f64<kDppRor4>(v);
+  v += dpp_f64<kDppRor8>(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+// Several wave sums, independent so that their latencies overlap.
 __device__ __forceinline__ void wave_sum2(double &a, double &b) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const double x = __shfl_xor(a, m), y = __shfl_xor(b, m);
-    a += x;
-    b += y;
-  }
+  a = wave_sum(a);
+  b = wave_sum(b);
 }
 __device__ __forceinline__ void wave_sum3(double &a, double &b, double &c) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const double x = __shfl_xor(a, m), y = __shfl_xor(b, m), z = __shfl_xor(c, m);
-    a += x;
-    b += y;
-    c += z;
-  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
-  return v;
+  v = fmax(v, dpp_f64<kDppPairs>(v));
+  v = fmax(v, dpp_f64<kDppQuads>(v));
+  v = fmax(v, dpp_f64<kDppRor4>(v));
+  v = fmax(v, dpp_f64<kDppRor8>(v));
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
 // Fixed-order sum / max over the waves of a pass workgroup.
@@ -776,8 +790,8 @@ __device__ inline void ses_epilogue(const PassArgs &a, DevState &S, const double
   const double gmax = sc[5], fall = sc[6];
   int status = kRunning, copy = 0;
   if (lane == 0 && k >= 2) status = monitor_rules(S, k, fall, fall < S.f_best, fall < S.alpha, &copy);
-  status = __shfl(status, 0);
-  copy = __shfl(copy, 0);
+  status = __builtin_amdgcn_readfirstlane(status);  // lane 0's decision
+  copy = __builtin_amdgcn_readfirstlane(copy);
   wave_lds_sync();
   if (copy)
     for (int c = lane; c < d; c += kWave) a.vec[kVecBest * d + c] = y[c];
@@ -883,8 +897,8 @@ __device__ inline void svm_epilogue(const PassArgs &a, DevState &S, const double
     const double f = nw > 0.0 ? fmax((minP - maxQ) / nw, 0.0) : 0.0;
     status = monitor_rules(S, k, f, f > S.f_best, f > S.alpha, &copy);
   }
-  status = __shfl(status, 0);
-  copy = __shfl(copy, 0);
+  status = __builtin_amdgcn_readfirstlane(status);  // lane 0's decision
+  copy = __builtin_amdgcn_readfirstlane(copy);
   wave_lds_sync();
   if (copy)
     for (int c = lane; c < d; c += kWave) a.vec[kVecBest * d + c] = wb[c];
