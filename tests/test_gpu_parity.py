@@ -374,3 +374,42 @@ def test_ses_prefetch_modes(mode, monkeypatch):
         V = synth.ses_gaussian_outliers(n, d, seed=n).astype(np.float32).astype(np.float64)
         P = oses.setup(V)
         ses_compare_steps(dev(V, tdt), V, 0.8 * P.D, 3000, 8)
+
+
+# ------------------------------------------- two-level record combine
+def test_ses_certificate_passes_two_level():
+    """Certificate passes at n = 100k, d = 100 (256 workgroups: their records,
+    with the second vector, exceed what one workgroup sums, so a first kernel
+    sums groups of 16): step parity, and the reported lower bound equals the
+    running maximum of the weighted-spread certificate computed from the
+    oracle's own trace weights."""
+    import torch
+    import paper_2405_09157_amd as scp
+    from oracle import certify
+    V = synth.ses_gaussian_outliers(100_000, 100, seed=31).astype(np.float32).astype(np.float64)
+    P = oses.setup(V)
+    alpha, T = 0.8 * P.D, 3000
+    eta = math.sqrt(math.log(P.r) / T)
+    m = mwu(dev(V, torch.float32), "ses",
+            flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP | scp.SCP_MWU_FLAG_CERTIFICATES)
+    S, lb_max = np.zeros(V.shape[1]), 0.0
+    for t in range(1, 7):
+        st = oses.step(P, S, t - 1, alpha, eta)
+        info = m.step(alpha, T, 1)
+        assert np.linalg.norm(np.array(m.vector(2)) - st["u"]) / alpha <= TIGHT
+        assert abs(info["value"] - st["value"]) / st["scale"] <= TIGHT
+        lb_max = max(lb_max, certify.ses_lower(V[P.F], st["s"]))
+        assert abs(info["bound"] - lb_max) / lb_max <= 1e-9, (t, info["bound"], lb_max)
+        assert info["bound"] <= certify.ses_upper(V, None, np.array(m.vector(0))) + 1e-9
+        S = st["S"]
+    m.close()
+
+
+def test_svm_two_level_partial_group():
+    """SVM at d = 256 on a 100-workgroup grid: the records go through the
+    group kernel with a partial last group of 4."""
+    import torch
+    X, _ = synth.svm_planted(3200, 3200, 256, seed=41)
+    X = X.astype(np.float32).astype(np.float64)
+    Pb = osvm.setup(X, 3200)
+    svm_compare_steps(dev(X, torch.float32), X, 3200, 0.5 * Pb.D, 2000, 10)
