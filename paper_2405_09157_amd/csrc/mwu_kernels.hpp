@@ -1111,12 +1111,16 @@ __global__ __launch_bounds__(kBlock) void monitor_kernel(PassArgs a, const doubl
     acc += __shfl_xor(acc, 2, 16);
     acc += __shfl_xor(acc, 1, 16);
     if (row < n) {
+      // a non-finite input value must not vanish in fmax (which drops NaN):
+      // it turns the maxima into +inf, which the host rejects
       if (mode == 0) {
-        const double h = sqrt(acc) + (a.radii ? a.radii[row] : 0.0);
+        double h = sqrt(acc) + (a.radii ? a.radii[row] : 0.0);
+        if (!isfinite(h)) h = INFINITY;
         if (row != exclude) r0 = fmax(r0, h);
         r1 = fmax(r1, h);
       } else {
-        if (row < a.n_pos) r2 = fmax(r2, -acc); else r3 = fmax(r3, acc);
+        const double v = isfinite(acc) ? acc : INFINITY;
+        if (row < a.n_pos) r2 = fmax(r2, isfinite(acc) ? -acc : INFINITY); else r3 = fmax(r3, v);
       }
     }
   }

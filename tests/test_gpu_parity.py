@@ -243,10 +243,17 @@ def test_invalid_descriptors_raise():
     X = dev(np.random.default_rng(0).standard_normal((10, 3)).astype(np.float32), torch.float32)
     with pytest.raises(scp.ScpMwuError):
         mwu(X, "svm", n_pos=0)
-    Xn = np.ones((10, 3), np.float32)
-    Xn[3, 1] = np.nan
-    with pytest.raises(scp.ScpMwuError):
-        mwu(dev(Xn, torch.float32), "ses")
+    # a non-finite coordinate in an otherwise ordinary point set: E_NUMERIC at init
+    for bad in (np.nan, np.inf):
+        Xn = np.random.default_rng(1).standard_normal((1000, 7)).astype(np.float32)
+        Xn[517, 3] = bad
+        for kw in (dict(), dict(storage="bf16")):
+            with pytest.raises(scp.ScpMwuError) as e:
+                mwu(dev(Xn, torch.float32), "ses", **kw)
+            assert e.value.code == scp.SCP_MWU_E_NUMERIC
+        with pytest.raises(scp.ScpMwuError) as e:
+            mwu(dev(Xn, torch.float32), "svm", n_pos=500)
+        assert e.value.code == scp.SCP_MWU_E_NUMERIC
     m = mwu(X, "ses")
     with pytest.raises(scp.ScpMwuError):
         m.step(-1.0, 10, 1)
