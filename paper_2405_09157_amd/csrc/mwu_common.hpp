@@ -7,9 +7,9 @@
 
 namespace scpmwu {
 
-// Launch geometry of the streaming pass.  A wavefront owns G = 16 lanes per
-// point row (one DPP row), so a wave covers 4 rows per load step; a
-// workgroup holds 4 waves.
+// Launch geometry.  In the streaming pass a wavefront owns G = 16 lanes per
+// point row (one DPP row), so a wave covers 4 rows per load step.  The small
+// kernels (monitor, init, state, cast, record groups) use kBlock threads.
 constexpr int kWave = 64;
 constexpr int kG = 16;
 constexpr int kRowsPerStep = kWave / kG;

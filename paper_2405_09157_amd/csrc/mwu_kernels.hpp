@@ -32,10 +32,11 @@
 //            in registers (one FMA per element).
 // Each workgroup writes one record of partial sums and maxima; the pass has
 // no inter-workgroup synchronisation.  The one-workgroup kernel launched
-// after it sums the records in a fixed order and one wave runs the FP64
+// after it (preceded, when the records are large, by a kernel that sums
+// groups of 16) sums the records in a fixed order, and one wave runs the FP64
 // epilogue: ORACLE closed form, the separation test, the running mean and the
-// early-exit rules.  All arithmetic on point data is
-// binary64; results are bitwise reproducible for a fixed grid.
+// early-exit rules.  All arithmetic on point data is binary64; results are
+// bitwise reproducible for a fixed grid.
 #pragma once
 
 #include <hip/hip_runtime.h>
