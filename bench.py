@@ -227,7 +227,7 @@ def main(argv=None):
     ach = algo_bytes / (f32["kernel_ms"] * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_for("f32"),
-                kernel="ses_pass_kernel<float,8,4,false,false>", kernel_ms=round(f32["kernel_ms"], 5),
+                kernel="ses_pass_kernel<float,8,4,false,0>", kernel_ms=round(f32["kernel_ms"], 5),
                 bytes_per_launch=algo_bytes, read_reference_GBs=rref["f32"]["GBs"],
                 frac_of_read_reference=round(ach / rref["f32"]["GBs"], 4))
     line = dict(metric=METRIC, value=round(1e3 / f32["ms_per_step"], 1), unit="iters/s", n_gpus=1,
@@ -246,7 +246,7 @@ def main(argv=None):
                             roofline=dict(bound="hbm", achieved=round(b_ach, 1), peak=HBM_PEAK_GBS,
                                           unit="GB/s", frac=round(b_ach / HBM_PEAK_GBS, 4),
                                           traffic=traffic_for("bf16"),
-                                          kernel="ses_pass_kernel<uint16_t,8,4,false,false>",
+                                          kernel="ses_pass_kernel<uint16_t,8,4,false,0>",
                                           kernel_ms=round(bf16["kernel_ms"], 5), bytes_per_launch=b_bytes,
                                           read_reference_GBs=rref["bf16"]["GBs"],
                                           frac_of_read_reference=round(b_ach / rref["bf16"]["GBs"], 4)))
