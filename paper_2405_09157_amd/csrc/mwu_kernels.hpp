@@ -110,6 +110,7 @@ struct Batch {
   R x[SB][EPL];
   double gi;  // SES: radius of the batch row of this lane (lanes < B)
   __device__ __forceinline__ double get(int s, int k) const { return (double)x[s][k]; }
+  __device__ __forceinline__ float getf(int s, int k) const { return (float)x[s][k]; }
   template <int VEC>
   __device__ __forceinline__ void put(int s, int q, const VecT<T, VEC> &raw) {
 #pragma unroll
@@ -130,10 +131,11 @@ struct Batch<uint16_t, SB, EPL, true> {
   static_assert(EPL % 2 == 0, "packed BF16 needs an even number of columns per lane");
   uint32_t w[SB][EPL / 2];
   double gi;
-  __device__ __forceinline__ double get(int s, int k) const {
+  __device__ __forceinline__ float getf(int s, int k) const {
     const uint32_t u = w[s][k >> 1];
-    return (double)__uint_as_float((k & 1) ? (u & 0xffff0000u) : (u << 16));
+    return __uint_as_float((k & 1) ? (u & 0xffff0000u) : (u << 16));
   }
+  __device__ __forceinline__ double get(int s, int k) const { return (double)getf(s, k); }
   template <int VEC>
   __device__ __forceinline__ void put(int s, int q, const VecT<uint16_t, VEC> &raw) {
     if constexpr (VEC >= 2) {
@@ -346,6 +348,10 @@ void ses_pass_kernel(PassArgs a) {
   using Sh = PassShape<T, EPL, kSES, PFM>;
   constexpr int SB = Sh::SB, B = Sh::B;
   using Regs = typename Sh::Regs;
+  // BF16 storage: per-element arithmetic in binary32 (the row distance
+  // partials and the batch's weighted sums), everything per row and across
+  // batches in binary64; F32 and F64 storage: binary64 throughout
+  constexpr bool M32 = sizeof(T) == 2;
   __shared__ double s_part[kPassWaves][B][kG + 1];
   __shared__ double s_wa[kPassWaves][B];
   __shared__ double s_wb[kPassWaves][CERT ? B : 1];
@@ -404,18 +410,34 @@ void ses_pass_kernel(PassArgs a) {
     const int64_t r0 = b * B;
     // re-read the candidate each batch: it stays out of registers in phases 2-3
     asm volatile("" ::: "memory");
-    double ub[EPL];
+    if constexpr (M32) {
+      float ub[EPL];
 #pragma unroll
-    for (int k = 0; k < EPL; ++k) ub[k] = s_ctr[lane_col<VEC>(cl, k)];
+      for (int k = 0; k < EPL; ++k) ub[k] = (float)s_ctr[lane_col<VEC>(cl, k)];
 #pragma unroll
-    for (int s = 0; s < SB; ++s) {
-      double dsq = 0.0;
+      for (int s = 0; s < SB; ++s) {
+        float dsq = 0.f;
 #pragma unroll
-      for (int k = 0; k < EPL; ++k) {
-        const double df = xs.get(s, k) - ub[k];
-        dsq = fma(df, df, dsq);
+        for (int k = 0; k < EPL; ++k) {
+          const float df = xs.getf(s, k) - ub[k];
+          dsq = fmaf(df, df, dsq);
+        }
+        s_part[wave][s * kRowsPerStep + g][cl] = (double)dsq;
       }
-      s_part[wave][s * kRowsPerStep + g][cl] = dsq;
+    } else {
+      double ub[EPL];
+#pragma unroll
+      for (int k = 0; k < EPL; ++k) ub[k] = s_ctr[lane_col<VEC>(cl, k)];
+#pragma unroll
+      for (int s = 0; s < SB; ++s) {
+        double dsq = 0.0;
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) {
+          const double df = xs.get(s, k) - ub[k];
+          dsq = fma(df, df, dsq);
+        }
+        s_part[wave][s * kRowsPerStep + g][cl] = dsq;
+      }
     }
     wave_lds_sync();
     if (lane < B) {
@@ -448,15 +470,40 @@ void ses_pass_kernel(PassArgs a) {
     wave_lds_sync();
     xs.pin();
     // sum_i a_i x_i (and sum_i b_i x_i); the epilogue subtracts (sum a_i) ubar
+    if constexpr (M32) {
+      // the batch's rows in binary32, added to the binary64 sums per batch
+      float w32[EPL], c32[CERT ? EPL : 1];
 #pragma unroll
-    for (int s = 0; s < SB; ++s) {
-      const double ar = s_wa[wave][s * kRowsPerStep + g];
+      for (int k = 0; k < EPL; ++k) w32[k] = 0.f;
 #pragma unroll
-      for (int k = 0; k < EPL; ++k) wacc[k] = fma(ar, xs.get(s, k), wacc[k]);
-      if (CERT) {
-        const double br = s_wb[wave][s * kRowsPerStep + g];
+      for (int k = 0; k < (CERT ? EPL : 1); ++k) c32[k] = 0.f;
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) cacc[k] = fma(br, xs.get(s, k), cacc[k]);
+      for (int s = 0; s < SB; ++s) {
+        const float ar = (float)s_wa[wave][s * kRowsPerStep + g];
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) w32[k] = fmaf(ar, xs.getf(s, k), w32[k]);
+        if (CERT) {
+          const float br = (float)s_wb[wave][s * kRowsPerStep + g];
+#pragma unroll
+          for (int k = 0; k < EPL; ++k) c32[k] = fmaf(br, xs.getf(s, k), c32[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < EPL; ++k) wacc[k] += (double)w32[k];
+      if (CERT)
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) cacc[k] += (double)c32[k];
+    } else {
+#pragma unroll
+      for (int s = 0; s < SB; ++s) {
+        const double ar = s_wa[wave][s * kRowsPerStep + g];
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) wacc[k] = fma(ar, xs.get(s, k), wacc[k]);
+        if (CERT) {
+          const double br = s_wb[wave][s * kRowsPerStep + g];
+#pragma unroll
+          for (int k = 0; k < EPL; ++k) cacc[k] = fma(br, xs.get(s, k), cacc[k]);
+        }
       }
     }
     wave_lds_sync();

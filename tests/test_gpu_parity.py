@@ -1,14 +1,25 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Tolerances.  The kernels compute every point-data operation in binary64
-(distances, dot products, exponentials, weighted sums), so the only
-difference from the oracle is the order of floating-point summation.  The
-bars written below are the spec bars (1e-6 relative for F32 storage,
-1e-3 for BF16 storage against the original points) and, where noted, the
-tighter bound the arithmetic gives: summation-order error of an n-term FP64
-sum is below n * 2^-53 relative to the sum of magnitudes, times the
-cancellation ratio of the weighted sum W; 1e-9 covers n <= 1e6 with a
-cancellation ratio up to 1e2.
+Tolerances.  With F32 and F64 storage the kernels compute every point-data
+operation in binary64 (distances, dot products, exponentials, weighted
+sums), so the only difference from the oracle is the order of
+floating-point summation.  The bars written below are the spec bars
+(1e-6 relative for F32 storage, 1e-3 for BF16 storage against the original
+points) and, where noted, the tighter bound the arithmetic gives:
+summation-order error of an n-term FP64 sum is below n * 2^-53 relative to
+the sum of magnitudes, times the cancellation ratio of the weighted sum W;
+1e-9 covers n <= 1e6 with a cancellation ratio up to 1e2.
+
+With BF16 storage the per-element arithmetic of the SES pass is binary32
+(row distance partials over a lane's <= 16 columns, and the weighted sums of
+one batch, <= 16 rows per lane); rows, exponentials and all sums across
+batches stay binary64.  A distance then carries a relative error below
+17 * 2^-24 ~ 1e-6 plus the binary32 rounding of the mean (2^-24 |ubar|), so
+an exponent kappa * d_i moves by at most ~1e-6 * kappa * max(d_i, |ubar|) <=
+1.5e-4 for the largest exponent scale kappa * D ~ 150 of the 1e6 x 100
+workload at T = 20000 (far less in the tests below); the batch sums add
+16 * 2^-24 relative.  BF16_STEP = 2e-4 bounds the resulting relative
+change of every step output against the oracle on the stored values.
 """
 import math
 
@@ -24,6 +35,7 @@ pytestmark = pytest.mark.gpu
 TIGHT = 1e-9
 NORTH_STAR_F32 = 1e-6
 NORTH_STAR_BF16 = 1e-3
+BF16_STEP = 2e-4
 
 
 def dev(x, dtype):
@@ -126,23 +138,23 @@ def test_ses_bf16_step_parity_on_stored_values():
     h, Vq = bf16_points(V)
     Vb = torch.from_numpy(h.view(np.int16)).cuda().view(torch.bfloat16)
     P = oses.setup(Vq)
-    ses_compare_steps(Vb, Vq, 0.8 * P.D, 3000, 30)
+    ses_compare_steps(Vb, Vq, 0.8 * P.D, 3000, 30, tol=BF16_STEP)
     # the library's own F32 -> BF16 conversion feeds the same values
-    ses_compare_steps(dev(V, torch.float32), Vq, 0.8 * P.D, 3000, 10, storage="bf16")
+    ses_compare_steps(dev(V, torch.float32), Vq, 0.8 * P.D, 3000, 10, tol=BF16_STEP, storage="bf16")
 
 
 @pytest.mark.parametrize("n,d", [(1001, 3), (517, 20), (2049, 64), (777, 100), (1500, 200), (63, 32)])
 def test_ses_bf16_step_parity_shapes(n, d):
     """BF16 storage at every column layout (1, 2, 4, 8, 16 columns per lane:
     raw BF16 pairs are kept packed for an even count, with batches of up to
-    64 rows), ragged n with a partial last batch, at the 1e-9 bar on the
+    64 rows), ragged n with a partial last batch, at the BF16_STEP bar on the
     stored values."""
     import torch
     V = synth.ses_gaussian_outliers(n, d, seed=n + d).astype(np.float32)
     h, Vq = bf16_points(V)
     Vb = torch.from_numpy(h.view(np.int16)).cuda().view(torch.bfloat16)
     P = oses.setup(Vq)
-    ses_compare_steps(Vb, Vq, 0.8 * P.D, 3000, 12)
+    ses_compare_steps(Vb, Vq, 0.8 * P.D, 3000, 12, tol=BF16_STEP)
 
 
 def test_bf16_cast_bit_exact():
