@@ -657,6 +657,9 @@ void svm_pass_kernel(PassArgs a) {
     const int64_t r0 = b * B;
     // re-read the candidate each batch: it stays out of registers in phases 2-3
     asm volatile("" ::: "memory");
+    // binary64 for every storage type: the binary32 per-element variant of
+    // the SES pass is slower here, where a BF16 batch at d = 256 holds 8 rows
+    // and its flush to binary64 costs as much as the batch's FMAs
     double ub[EPL];
 #pragma unroll
     for (int k = 0; k < EPL; ++k) ub[k] = s_ctr[cl * EPL + k];

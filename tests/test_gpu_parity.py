@@ -10,7 +10,8 @@ summation-order error of an n-term FP64 sum is below n * 2^-53 relative to
 the sum of magnitudes, times the cancellation ratio of the weighted sum W;
 1e-9 covers n <= 1e6 with a cancellation ratio up to 1e2.
 
-With BF16 storage the per-element arithmetic of the SES pass is binary32
+With BF16 storage the per-element arithmetic of the SES pass (not the SVM
+pass, which stays binary64) is binary32
 (row distance partials over a lane's <= 16 columns, and the weighted sums of
 one batch, <= 16 rows per lane); rows, exponentials and all sums across
 batches stay binary64.  A distance then carries a relative error below
@@ -432,3 +433,16 @@ def test_svm_two_level_partial_group():
     X = X.astype(np.float32).astype(np.float64)
     Pb = osvm.setup(X, 3200)
     svm_compare_steps(dev(X, torch.float32), X, 3200, 0.5 * Pb.D, 2000, 10)
+
+
+@pytest.mark.parametrize("n1,n2,d", [(1500, 1300, 256), (700, 900, 16), (40, 25, 2), (3000, 2000, 100)])
+def test_svm_bf16_step_parity(n1, n2, d):
+    """SVM with BF16 storage (binary64 arithmetic on the stored values)
+    against the oracle on those values at the 1e-9 bar; a batch straddling
+    the class boundary is included at each size."""
+    import torch
+    X, _ = synth.svm_planted(n1, n2, d, seed=d + 7)
+    h, Xq = bf16_points(X.astype(np.float32))
+    Xb = torch.from_numpy(h.view(np.int16)).cuda().view(torch.bfloat16)
+    Pb = osvm.setup(Xq, n1)
+    svm_compare_steps(Xb, Xq, n1, 0.5 * Pb.D, 2000, 25)
