@@ -126,6 +126,68 @@ def bf16_to_f32(h: np.ndarray) -> np.ndarray:
     return (np.asarray(h, dtype=np.uint16).astype(np.uint32) << np.uint32(16)).view(np.float32)
 
 
+FP8_E4M3_MAX = 448.0
+
+
+def fp8_e4m3_decode(codes: np.ndarray) -> np.ndarray:
+    """FP8 E4M3 codes (uint8: sign, 4 exponent bits with bias 7, 3 mantissa
+    bits; no infinities; S.1111.111 is NaN) -> the FP32 values they encode
+    (exactly)."""
+    c = np.asarray(codes, dtype=np.uint8).astype(np.int32)
+    sign = np.where(c & 0x80, -1.0, 1.0)
+    e = (c >> 3) & 0xF
+    m = c & 0x7
+    mag = np.where(e == 0, m * 2.0 ** -9, (8 + m) * np.exp2(e.astype(np.float64) - 10))
+    mag = np.where((e == 0xF) & (m == 0x7), np.nan, mag)
+    return (sign * mag).astype(np.float32)
+
+
+def fp8_e4m3_encode(v32: np.ndarray) -> np.ndarray:
+    """FP32 values -> FP8 E4M3 codes, round to nearest, ties to even,
+    magnitudes from 464 (the tie above 448) up saturated to 448; NaN -> 0x7F
+    (with the sign)."""
+    v = np.ascontiguousarray(v32, dtype=np.float32)
+    b = v.view(np.uint32)
+    sign = ((b >> np.uint32(31)) & np.uint32(1)).astype(np.int32) << 7
+    a = np.abs(v)
+    ab = a.view(np.uint32).astype(np.int64)
+    e = (ab >> 23) - 127
+    # normals of the target (|a| >= 2^-6): 3 of the 23 mantissa bits, to nearest even
+    m = ab & 0x7FFFFF
+    m3 = m >> 20
+    rem = m & 0xFFFFF
+    up = (rem > 0x80000) | ((rem == 0x80000) & ((m3 & 1) == 1))
+    m3 = m3 + up
+    e = e + (m3 >> 3)
+    m3 = m3 & 0x7
+    normal = ((e + 7) << 3) | m3
+    # subnormals of the target (|a| < 2^-6): multiples of 2^-9, to nearest even
+    sub = np.rint(a.astype(np.float64) * 512.0).astype(np.int64)
+    code = np.where(a < 2.0 ** -6, sub, normal)
+    code = np.where(a >= 464.0, 0x7E, np.minimum(code, 0x7E))
+    code = np.where(np.isnan(v), 0x7F, code)
+    return (code | sign).astype(np.uint8)
+
+
+def fp8_rows(x32: np.ndarray):
+    """Per-row scaled FP8 storage of a row-major matrix: scale s_r = max_c
+    |x_rc| / 448 in FP32 (1 for an all-zero row) and codes of x_rc / s_r
+    (FP32 quotient).  Returns (codes uint8 n x d, scales float32 n); the
+    stored value of entry (r, c) is s_r * decode(code), exact in FP64."""
+    x = np.ascontiguousarray(x32, dtype=np.float32)
+    amax = np.max(np.abs(x), axis=1)
+    s = (amax / np.float32(FP8_E4M3_MAX)).astype(np.float32)
+    s = np.where(amax > 0, s, np.float32(1.0)).astype(np.float32)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        q = (x / s[:, None]).astype(np.float32)
+    return fp8_e4m3_encode(q), s
+
+
+def fp8_values(codes: np.ndarray, scales: np.ndarray) -> np.ndarray:
+    """The FP64 values held by per-row scaled FP8 storage."""
+    return fp8_e4m3_decode(codes).astype(np.float64) * np.asarray(scales, dtype=np.float64)[:, None]
+
+
 # The five measured workloads, by name.  Sizes, distributions and tolerances
 # are what the tests and the benchmark use.
 CONFIGS = {
