@@ -60,7 +60,9 @@ enum {
 enum {
   SCP_MWU_F32 = 1,  /* IEEE binary32 */
   SCP_MWU_BF16 = 2, /* bfloat16 (upper half of a binary32), stored as uint16 */
-  SCP_MWU_F64 = 3   /* IEEE binary64 */
+  SCP_MWU_F64 = 3,  /* IEEE binary64 */
+  SCP_MWU_FP8 = 4   /* storage only: FP8 E4M3 codes (uint8) with one binary32
+                       scale per row, made by init from binary32 points */
 };
 
 /* return codes */
@@ -110,7 +112,12 @@ typedef struct scp_mwu_desc {
   int32_t storage;      /* element type the iteration streams: 0 = dtype;
                            SCP_MWU_BF16 with dtype SCP_MWU_F32 makes init round
                            the points once (nearest, ties to even) into a
-                           library-owned BF16 copy */
+                           library-owned BF16 copy; SCP_MWU_FP8 with dtype
+                           SCP_MWU_F32 makes init quantize them once into
+                           library-owned per-row scaled FP8 codes (see
+                           scp_mwu_quantize_fp8).  With BF16 or FP8 storage
+                           the SES pass computes per element in binary32
+                           (rows and all sums across rows in binary64). */
   int64_t n;            /* number of points (SES: >= 2; SVM: n_pos + n_neg) */
   int64_t d;            /* dimension, 1 <= d <= 512 */
   int64_t ld;           /* row stride of `points` in elements, >= d (0 = d) */
@@ -278,6 +285,22 @@ const char *scp_mwu_strerror(int code);
  * E_INVAL on NULL pointers or n < 0, E_HIP.
  */
 int scp_mwu_cast_bf16(const float *src, uint16_t *dst, int64_t n, void *stream);
+
+/*
+ * Per-row scaled FP8 storage of an n x d binary32 matrix src (device, row
+ * stride ld >= d elements): scales[r] = max_c |src[r][c]| / 448 (binary32
+ * division; 1 for an all-zero row) and codes[r * d + c] = the FP8 E4M3 code
+ * of src[r][c] / scales[r] (binary32 division), rounded to nearest with ties
+ * to even and saturated at 448; E4M3 is sign, 4 exponent bits with bias 7,
+ * 3 mantissa bits, no infinities.  The stored value is scales[r] times the
+ * decoded code.  codes (device, n * d bytes) and scales (device, n floats)
+ * are caller-owned; a NaN element gives a NaN code.  The conversion init uses
+ * for SCP_MWU_FP8 storage; exported so callers can inspect it.  Enqueued on
+ * stream (a hipStream_t; NULL = default).  E_INVAL (NULL pointers, n < 0,
+ * d < 1, ld < d), E_HIP.
+ */
+int scp_mwu_quantize_fp8(const float *src, int64_t n, int64_t d, int64_t ld, uint8_t *codes, float *scales,
+                         void *stream);
 
 /*
  * Measurement helper: the achievable read bandwidth the streaming pass is

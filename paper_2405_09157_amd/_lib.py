@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(PKG, "libscpmwu.so")
 # ---- constants (mirror include/scp_mwu.h)
 SCP_MWU_ABI_VERSION = 1
 SCP_MWU_PROBLEM_SES, SCP_MWU_PROBLEM_SVM = 1, 2
-SCP_MWU_F32, SCP_MWU_BF16, SCP_MWU_F64 = 1, 2, 3
+SCP_MWU_F32, SCP_MWU_BF16, SCP_MWU_F64, SCP_MWU_FP8 = 1, 2, 3, 4
 SCP_MWU_OK, SCP_MWU_STOPPED = 0, 1
 SCP_MWU_E_INVAL, SCP_MWU_E_NOMEM, SCP_MWU_E_HIP, SCP_MWU_E_STATE = -1, -2, -3, -4
 SCP_MWU_E_NUMERIC, SCP_MWU_E_INFEASIBLE, SCP_MWU_E_UNSUPPORTED = -5, -6, -7
@@ -30,7 +30,7 @@ OUTCOME_NAMES = {0: "running", 1: "separated", 2: "beat_alpha", 3: "stabilized",
 EXPORTS = ("scp_mwu_init", "scp_mwu_step", "scp_mwu_solve", "scp_mwu_backward",
            "scp_mwu_get_state", "scp_mwu_set_state", "scp_mwu_get_vector", "scp_mwu_get_D",
            "scp_mwu_destroy", "scp_mwu_last_error", "scp_mwu_strerror", "scp_mwu_cast_bf16",
-           "scp_mwu_time_passes", "scp_mwu_read_reference")
+           "scp_mwu_time_passes", "scp_mwu_read_reference", "scp_mwu_quantize_fp8")
 
 
 class scp_mwu_desc(ctypes.Structure):
@@ -120,6 +120,7 @@ def load() -> ctypes.CDLL:
         "scp_mwu_cast_bf16": (i32, [vp, vp, i64, vp]),
         "scp_mwu_time_passes": (i32, [vp, i32, P(f64), P(f64)]),
         "scp_mwu_read_reference": (i32, [vp, i64, i32, vp, P(f64)]),
+        "scp_mwu_quantize_fp8": (i32, [vp, i64, i64, i64, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -206,6 +207,11 @@ def scp_mwu_time_passes(ctx, k: int):
     mp, mi = ctypes.c_double(), ctypes.c_double()
     _check(load().scp_mwu_time_passes(ctx, k, ctypes.byref(mp), ctypes.byref(mi)), ctx)
     return mp.value, mi.value
+
+
+def scp_mwu_quantize_fp8(src_ptr: int, n: int, d: int, ld: int, codes_ptr: int, scales_ptr: int,
+                         stream: int = 0) -> None:
+    _check(load().scp_mwu_quantize_fp8(src_ptr, n, d, ld, codes_ptr, scales_ptr, stream))
 
 
 def scp_mwu_read_reference(ptr: int, nbytes: int, reps: int = 20, stream: int = 0) -> float:

@@ -28,8 +28,9 @@ class MWU:
 
     points   device tensor n x d (row stride >= d, unit column stride); SVM rows
              [0, n_pos) are class +1 and the rest class -1.
-    storage  None (stream the points as given) or "bf16" (round FP32 points
-             once into a library-owned BF16 copy).
+    storage  None (stream the points as given), "bf16" (round FP32 points
+             once into a library-owned BF16 copy) or "fp8" (quantize FP32
+             points once into library-owned per-row scaled FP8 E4M3 codes).
     """
 
     def __init__(self, points, problem: str = "ses", *, n_pos: int | None = None, radii=None,
@@ -54,7 +55,7 @@ class MWU:
         desc.struct_size = __import__("ctypes").sizeof(L.scp_mwu_desc)
         desc.problem = L.SCP_MWU_PROBLEM_SVM if self.svm else L.SCP_MWU_PROBLEM_SES
         desc.dtype = _dtype_code(points)
-        desc.storage = {None: 0, "bf16": L.SCP_MWU_BF16}[storage]
+        desc.storage = {None: 0, "bf16": L.SCP_MWU_BF16, "fp8": L.SCP_MWU_FP8}[storage]
         desc.n, desc.d, desc.ld = self.n, self.d, points.stride(0)
         desc.points = points.data_ptr()
         if radii is not None:

@@ -1,6 +1,7 @@
 // Small non-iterative kernels: resuming a test from given running sums, the
-// FP32 -> BF16 storage conversion, and a plain streaming read of a buffer
-// (the achievable-read-bandwidth reference the streaming pass is held to).
+// FP32 -> BF16 and FP32 -> FP8 (per-row scaled) storage conversions, and a
+// plain streaming read of a buffer (the achievable-read-bandwidth reference
+// the streaming pass is held to).
 #include <algorithm>
 
 #include "mwu_kernels.hpp"
@@ -97,6 +98,64 @@ __global__ __launch_bounds__(kPassBlock) void read_reference_kernel(const char *
 hipError_t launch_read_reference(const void *buf, int64_t bytes, int grid, float *sink, hipStream_t s) {
   hipLaunchKernelGGL(read_reference_kernel, dim3(grid), dim3(kPassBlock), 0, s, reinterpret_cast<const char *>(buf),
                      bytes, sink);
+  return hipGetLastError();
+}
+
+// FP32 -> FP8 E4M3 code (sign, 4 exponent bits with bias 7, 3 mantissa
+// bits, no infinities): round to nearest, ties to even; magnitudes from 464
+// (the tie above the largest finite value 448) up saturate to 448; NaN gives
+// 0x7F with its sign.
+__device__ inline uint32_t fp8_encode(float v) {
+  const uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
+  const float a = fabsf(v);
+  uint32_t code;
+  if (!(a == a)) {
+    code = 0x7Fu;
+  } else if (a >= 464.f) {
+    code = 0x7Eu;
+  } else if (a < 0.015625f) {
+    // below the smallest normal 2^-6: multiples of 2^-9 (the scaling is exact)
+    code = (uint32_t)rintf(a * 512.f);
+  } else {
+    const uint32_t ab = __float_as_uint(a);
+    int e = (int)(ab >> 23) - 127;
+    uint32_t m3 = (ab >> 20) & 7u;
+    const uint32_t rem = ab & 0xFFFFFu;
+    if (rem > 0x80000u || (rem == 0x80000u && (m3 & 1u))) ++m3;
+    if (m3 == 8u) {
+      m3 = 0u;
+      ++e;
+    }
+    code = ((uint32_t)(e + 7) << 3) | m3;
+    if (code > 0x7Eu) code = 0x7Eu;
+  }
+  return code | sign;
+}
+
+// Per-row scaled FP8 storage: one wave per row; the scale is the row's
+// largest magnitude over 448 (binary32 division; 1 for an all-zero row), the
+// codes encode x / scale (binary32 division).  Codes are stored with row
+// stride d.
+__global__ __launch_bounds__(kBlock) void quantize_fp8_kernel(const float *__restrict__ src, int64_t n, int64_t d,
+                                                             int64_t ld, uint8_t *__restrict__ codes,
+                                                             float *__restrict__ scales) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t r = (int64_t)blockIdx.x * kWavesPerBlock + wave; r < n; r += (int64_t)gridDim.x * kWavesPerBlock) {
+    const float *row = src + r * ld;
+    float m = 0.f;
+    for (int64_t c = lane; c < d; c += kWave) m = fmaxf(m, fabsf(row[c]));
+    m = (float)wave_max((double)m);
+    const float sc = m > 0.f ? m / 448.f : 1.f;
+    for (int64_t c = lane; c < d; c += kWave) codes[r * d + c] = (uint8_t)fp8_encode(row[c] / sc);
+    if (lane == 0) scales[r] = sc;
+  }
+}
+
+hipError_t launch_quantize_fp8(const float *src, int64_t n, int64_t d, int64_t ld, uint8_t *codes, float *scales,
+                               hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>((n + kWavesPerBlock - 1) / kWavesPerBlock, 65536);
+  hipLaunchKernelGGL(quantize_fp8_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kBlock), 0, s, src, n,
+                     d, ld, codes, scales);
   return hipGetLastError();
 }
 

@@ -41,27 +41,29 @@ inline __host__ __device__ bool rec_two_level(int grid, int read_cols) {
 }
 
 enum Problem : int32_t { kSES = 1, kSVM = 2 };
-enum DType : int32_t { kF32 = 1, kBF16 = 2, kF64 = 3 };
+enum DType : int32_t { kF32 = 1, kBF16 = 2, kF64 = 3, kFP8 = 4 };
 
 // Load steps per batch of the streaming pass (B = 4 * steps rows, B <= 64),
 // shared by the kernels and the host's grid sizing.  A batch's elements stay
 // in registers through its three phases, within a budget of 64 VGPRs:
-// binary32 registers for F32 and BF16 values, binary64 for F64; SES with BF16
-// storage and an even number (at most 16) of columns per lane keeps the raw
-// pairs (two elements per register, widened on use), which doubles the rows
-// per batch.  SVM keeps two binary64 class accumulators per column and halves
-// the budget; with prefetch two batches share it.  At most 8 steps (16 for
-// packed BF16, whose per-row phase then fills the wave).
+// binary32 registers for F32, BF16 and FP8 values, binary64 for F64.  Raw
+// codes stay packed (widened on use) where the columns per lane allow it:
+// BF16 pairs for SES with an even count (at most 16), FP8 quadruples for a
+// count that is a multiple of 4 (at most 16); packing multiplies the rows per
+// batch.  SVM keeps two binary64 class accumulators per column and halves the
+// budget; with prefetch two batches share it.  At most 8 steps (16 packed,
+// where the per-row phase then fills the wave).
 inline __host__ __device__ constexpr bool pass_packed(int storage_size, int epl, int problem) {
-  return storage_size == 2 && epl % 2 == 0 && epl <= 16 && problem == kSES;
+  return (storage_size == 2 && epl % 2 == 0 && epl <= 16 && problem == kSES) ||
+         (storage_size == 1 && epl % 4 == 0 && epl <= 16);
 }
 // Prefetch modes of the streaming pass: none, or two register batches (the
 // next one loading while the current one is processed).
 enum Prefetch : int32_t { kPrefetchNone = 0, kPrefetchRegs = 1 };
 inline __host__ __device__ constexpr int pass_steps(int storage_size, int epl, int problem, int pfm) {
   const bool pack = pass_packed(storage_size, epl, problem);
-  const int lim = (storage_size == 8 ? 32 : (pack ? 128 : 64)) / (problem == kSVM ? 2 : 1) /
-                  (pfm == kPrefetchRegs ? 2 : 1);
+  const int lim = (storage_size == 8 ? 32 : (pack ? 128 : 64)) /
+                  (problem == kSVM ? 2 : 1) / (pfm == kPrefetchRegs ? 2 : 1);
   const int cap = pack ? 16 : 8;
   return lim / epl < 1 ? 1 : (lim / epl > cap ? cap : lim / epl);
 }
@@ -128,6 +130,7 @@ struct PassArgs {
   DevState *st;
   double *vec;            // kNumVec * d
   double *partials;       // gridDim.x * partial_width(d), 16-byte aligned
+  const float *scales;    // FP8 storage: one binary32 scale per row; else nullptr
 };
 
 // Parameters of a new alpha-feasibility test (written by the init kernel).
@@ -147,6 +150,8 @@ struct LaunchCfg {
 };
 
 hipError_t launch_read_reference(const void *buf, int64_t bytes, int grid, float *sink, hipStream_t s);
+hipError_t launch_quantize_fp8(const float *src, int64_t n, int64_t d, int64_t ld, uint8_t *codes, float *scales,
+                               hipStream_t s);
 
 #define SCPMWU_DECLARE_TYPED(name)                                                              \
   hipError_t launch_pass_##name(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s); \
@@ -157,6 +162,7 @@ hipError_t launch_read_reference(const void *buf, int64_t bytes, int grid, float
 SCPMWU_DECLARE_TYPED(f32)
 SCPMWU_DECLARE_TYPED(bf16)
 SCPMWU_DECLARE_TYPED(f64)
+SCPMWU_DECLARE_TYPED(fp8)
 #undef SCPMWU_DECLARE_TYPED
 hipError_t launch_set_state_k(const PassArgs &a, int problem, int64_t t, double S1, double S2,
                               hipStream_t s);

@@ -62,6 +62,13 @@ template <>
 __device__ __forceinline__ double to_f64<double>(double x) {
   return x;
 }
+// FP8 E4M3 code (the low byte of c) -> its value, exactly (hardware decode;
+// the scale of the row is applied separately)
+__device__ __forceinline__ float fp8_value(uint32_t c) { return __builtin_amdgcn_cvt_f32_fp8(c, 0); }
+template <>
+__device__ __forceinline__ double to_f64<uint8_t>(uint8_t c) {
+  return (double)fp8_value(c);
+}
 
 template <typename T, int V>
 struct alignas(sizeof(T) * V) VecT {
@@ -92,6 +99,10 @@ template <>
 __device__ __forceinline__ double to_reg<double>(double x) {
   return x;
 }
+template <>
+__device__ __forceinline__ float to_reg<uint8_t>(uint8_t c) {
+  return fp8_value(c);
+}
 
 // Occupancy target of the streaming pass (waves per SIMD): caps the
 // register budget at 512 / target VGPRs so that enough waves are resident
@@ -109,6 +120,7 @@ struct Batch {
   using R = typename RegT<T>::type;
   R x[SB][EPL];
   double gi;  // SES: radius of the batch row of this lane (lanes < B)
+  float sc;   // FP8: scale of the batch row of this lane (lanes < B)
   __device__ __forceinline__ double get(int s, int k) const { return (double)x[s][k]; }
   __device__ __forceinline__ float getf(int s, int k) const { return (float)x[s][k]; }
   template <int VEC>
@@ -131,6 +143,7 @@ struct Batch<uint16_t, SB, EPL, true> {
   static_assert(EPL % 2 == 0, "packed BF16 needs an even number of columns per lane");
   uint32_t w[SB][EPL / 2];
   double gi;
+  float sc;
   __device__ __forceinline__ float getf(int s, int k) const {
     const uint32_t u = w[s][k >> 1];
     return __uint_as_float((k & 1) ? (u & 0xffff0000u) : (u << 16));
@@ -150,6 +163,41 @@ struct Batch<uint16_t, SB, EPL, true> {
     for (int s = 0; s < SB; ++s)
 #pragma unroll
       for (int k = 0; k < EPL / 2; ++k) asm volatile("" : "+v"(w[s][k]));
+  }
+};
+
+// FP8 E4M3 codes kept packed, four per 32-bit register, decoded on use.
+template <int SB, int EPL>
+struct Batch<uint8_t, SB, EPL, true> {
+  static_assert(EPL % 4 == 0, "packed FP8 needs a multiple of 4 columns per lane");
+  uint32_t w[SB][EPL / 4];
+  double gi;
+  float sc;
+  __device__ __forceinline__ float getf(int s, int k) const {
+    // the pair conversion decodes the low two bytes of its operand; the high
+    // pair is shifted down (k is a constant once unrolled, and the two
+    // elements of a pair share one conversion)
+    const uint32_t u = w[s][k >> 2];
+    const auto p = __builtin_amdgcn_cvt_pk_f32_fp8((int)((k & 2) ? (u >> 16) : u), false);
+    return (k & 1) ? p[1] : p[0];
+  }
+  __device__ __forceinline__ double get(int s, int k) const { return (double)getf(s, k); }
+  template <int VEC>
+  __device__ __forceinline__ void put(int s, int q, const VecT<uint8_t, VEC> &raw) {
+    if constexpr (VEC % 4 == 0) {
+      __builtin_memcpy(&w[s][q * VEC / 4], &raw, VEC);
+    } else {
+      uint32_t bits = 0;
+      __builtin_memcpy(&bits, &raw, VEC);
+      const int byte = (q * VEC) & 3;
+      w[s][(q * VEC) >> 2] = byte == 0 ? bits : (w[s][(q * VEC) >> 2] | (bits << (8 * byte)));
+    }
+  }
+  __device__ __forceinline__ void pin() {
+#pragma unroll
+    for (int s = 0; s < SB; ++s)
+#pragma unroll
+      for (int k = 0; k < EPL / 4; ++k) asm volatile("" : "+v"(w[s][k]));
   }
 };
 
@@ -286,6 +334,25 @@ __device__ __forceinline__ double radius_load(const double *radii, int64_t r0, i
   return g;
 }
 
+// FP8 scales of rows [r0, r0 + rows) (none: every load reads 0).
+__device__ __forceinline__ float scale_load(const float *scales, int64_t r0, int64_t rows, int lane) {
+  const int32_t num = (scales != nullptr && rows > 0) ? (int32_t)(rows * 4) : 0;
+  const __amdgpu_buffer_rsrc_t r = uniform_rsrc(scales != nullptr ? scales + r0 : nullptr, num);
+  const auto v = __builtin_amdgcn_raw_buffer_load_b32(r, lane * 4, 0, 0);
+  float f;
+  __builtin_memcpy(&f, &v, 4);
+  return f;
+}
+
+// Element (row, c) of the stored points as the value the method works on:
+// FP8 codes times their row's scale (exact in binary64).
+template <typename T>
+__device__ __forceinline__ double row_value(const PassArgs &a, int64_t row, int64_t c) {
+  const double v = to_f64(reinterpret_cast<const T *>(a.X)[row * a.ld + c]);
+  if constexpr (sizeof(T) == 1) return v * (double)a.scales[row];
+  return v;
+}
+
 template <typename T, int VEC>
 __device__ __forceinline__ VecT<T, VEC> buf_load(__amdgpu_buffer_rsrc_t r, int32_t voff, int32_t soff) {
   VecT<T, VEC> v;
@@ -299,28 +366,15 @@ __device__ __forceinline__ VecT<T, VEC> buf_load(__amdgpu_buffer_rsrc_t r, int32
   } else if constexpr (BYTES == 4) {
     const auto x = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
     __builtin_memcpy(&v, &x, 4);
-  } else {
-    static_assert(BYTES == 2, "load width");
+  } else if constexpr (BYTES == 2) {
     const auto x = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
     __builtin_memcpy(&v, &x, 2);
+  } else {
+    static_assert(BYTES == 1, "load width");
+    const auto x = __builtin_amdgcn_raw_buffer_load_b8(r, voff, soff, 0);
+    __builtin_memcpy(&v, &x, 1);
   }
   return v;
-}
-
-// Load one row's EPL columns owned by lane `cl` (zeros outside [0,n) x [0,d)).
-template <typename T, int EPL, int VEC>
-__device__ __forceinline__ void load_row(const T *__restrict__ X, int64_t row, int64_t n, int d,
-                                         int64_t ld, int cl, VecT<T, VEC> (&raw)[EPL / VEC]) {
-  const bool rv = row < n;
-  const T *rp = X + row * ld + (int64_t)cl * EPL;
-#pragma unroll
-  for (int q = 0; q < EPL / VEC; ++q) {
-    VecT<T, VEC> v;
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) v.v[e] = T(0);
-    if (rv && (cl * EPL + q * VEC) < d) v = *reinterpret_cast<const VecT<T, VEC> *>(rp + q * VEC);
-    raw[q] = v;
-  }
 }
 
 // ------------------------------------------------------- workgroup records
@@ -351,10 +405,13 @@ void ses_pass_kernel(PassArgs a) {
   // BF16 storage: per-element arithmetic in binary32 (the row distance
   // partials and the batch's weighted sums), everything per row and across
   // batches in binary64; F32 and F64 storage: binary64 throughout
-  constexpr bool M32 = sizeof(T) == 2;
+  constexpr bool M32 = sizeof(T) <= 2;
+  // FP8 storage: codes times one binary32 scale per row
+  constexpr bool FP8 = sizeof(T) == 1;
   __shared__ double s_part[kPassWaves][B][kG + 1];
   __shared__ double s_wa[kPassWaves][B];
   __shared__ double s_wb[kPassWaves][CERT ? B : 1];
+  __shared__ float s_scl[kPassWaves][FP8 ? B : 1];
   __shared__ double s_vec[kPassWaves][kG * EPL];
   __shared__ double s_sc[kPassWaves][8];
   __shared__ double s_ctr[kG * EPL];  // the candidate (ubar or wbar), zero-padded
@@ -404,6 +461,7 @@ void ses_pass_kernel(PassArgs a) {
       for (int q = 0; q < EPL / VEC; ++q)
         xs.template put<VEC>(s, q, buf_load<T, VEC>(rs, voff[q] + s * step_bytes, 0));
     xs.gi = radius_load(radii, r0, rows, lane);
+    if constexpr (FP8) xs.sc = scale_load(a.scales, r0, rows, lane);
   };
   // phases 1-3 on the batch b held in xs
   auto process = [&](Regs &xs, int64_t b) {
@@ -411,15 +469,20 @@ void ses_pass_kernel(PassArgs a) {
     // re-read the candidate each batch: it stays out of registers in phases 2-3
     asm volatile("" ::: "memory");
     if constexpr (M32) {
+      if constexpr (FP8) {
+        if (lane < B) s_scl[wave][lane] = xs.sc;
+        wave_lds_sync();
+      }
       float ub[EPL];
 #pragma unroll
       for (int k = 0; k < EPL; ++k) ub[k] = (float)s_ctr[lane_col<VEC>(cl, k)];
 #pragma unroll
       for (int s = 0; s < SB; ++s) {
+        const float sr = FP8 ? s_scl[wave][s * kRowsPerStep + g] : 1.f;
         float dsq = 0.f;
 #pragma unroll
         for (int k = 0; k < EPL; ++k) {
-          const float df = xs.getf(s, k) - ub[k];
+          const float df = FP8 ? fmaf(sr, xs.getf(s, k), -ub[k]) : xs.getf(s, k) - ub[k];
           dsq = fmaf(df, df, dsq);
         }
         s_part[wave][s * kRowsPerStep + g][cl] = (double)dsq;
@@ -464,8 +527,10 @@ void ses_pass_kernel(PassArgs a) {
       if (CERT) bd2 += bw * dsq;
       if (incl) gmax = fmax(gmax, h);
       if (valid) fall = fmax(fall, h);
-      s_wa[wave][lane] = aw;
-      if (CERT) s_wb[wave][lane] = bw;
+      // the weights of the stored codes: a_i x_i = (a_i s_i) q_i for FP8
+      const double sc = FP8 ? (double)xs.sc : 1.0;
+      s_wa[wave][lane] = aw * sc;
+      if (CERT) s_wb[wave][lane] = bw * sc;
     }
     wave_lds_sync();
     xs.pin();
@@ -645,12 +710,14 @@ void svm_pass_kernel(PassArgs a) {
   // rows of batch b into registers (rows >= n read as zeros)
   auto load_batch = [&](Regs &xv, int64_t b) {
     const int64_t r0 = b * B;
-    const __amdgpu_buffer_rsrc_t rs = rows_rsrc<T>(X, r0, n - r0 < B ? n - r0 : B, ld, d);
+    const int64_t rows = n - r0 < B ? n - r0 : B;
+    const __amdgpu_buffer_rsrc_t rs = rows_rsrc<T>(X, r0, rows, ld, d);
 #pragma unroll
     for (int s = 0; s < SB; ++s)
 #pragma unroll
       for (int q = 0; q < EPL / VEC; ++q)
         xv.template put<VEC>(s, q, buf_load<T, VEC>(rs, voff[q] + s * step_bytes, 0));
+    if constexpr (sizeof(T) == 1) xv.sc = scale_load(a.scales, r0, rows, lane);
   };
   // phases 1-3 on the batch b held in xv
   auto process = [&](Regs &xv, int64_t b) {
@@ -678,6 +745,7 @@ void svm_pass_kernel(PassArgs a) {
       const int64_t row = r0 + lane;
       const bool valid = row < n;
       const bool isP = row < n_pos;
+      if constexpr (sizeof(T) == 1) dot *= (double)xv.sc;  // FP8: x_i = s_i q_i
       const double sl = (isP ? dot : -dot) - (isP ? s1b : s2b);
       // weight exp(-kappa' slack) shifted by the lower bound on the slack
       const double e = valid ? exp(-kappa * (sl - slb)) : 0.0;
@@ -686,7 +754,7 @@ void svm_pass_kernel(PassArgs a) {
         if (isP) nminP = fmax(nminP, -dot); else maxQ = fmax(maxQ, dot);
         nslmin = fmax(nslmin, -sl);
       }
-      s_wa[wave][lane] = e;
+      s_wa[wave][lane] = sizeof(T) == 1 ? e * (double)xv.sc : e;  // weight of the stored codes
     }
     wave_lds_sync();
     xv.pin();
@@ -1092,7 +1160,7 @@ __global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P)
   for (int c = tid; c < d; c += kCombBlock) {
     s_y[c] = a.vec[kVecMean * d + c];
     s_S[c] = a.vec[kVecS * d + c];
-    if (PROB == kSES) s_v1[c] = to_f64(reinterpret_cast<const T *>(a.X)[a.v1 * a.ld + c]);
+    if (PROB == kSES) s_v1[c] = row_value<T>(a, a.v1, c);
   }
   const int j = tid % npairs, grp = tid / npairs;
   if (grp < groups) {
@@ -1149,7 +1217,7 @@ __global__ __launch_bounds__(kBlock) void monitor_kernel(PassArgs a, const doubl
     double acc = 0.0;
     if (row < n)
       for (int c = cl; c < d; c += kG) {
-        const double x = to_f64(X[row * ld + c]);
+        const double x = row_value<T>(a, row, c);
         if (mode == 0) {
           const double df = x - center[c];
           acc = fma(df, df, acc);
@@ -1199,7 +1267,7 @@ __global__ __launch_bounds__(kBlock) void ftp_init_kernel(PassArgs a, InitParams
   const int tid = threadIdx.x;
   for (int c = tid; c < d; c += kBlock) {
     double y0 = 0.0;
-    if (problem == kSES) y0 = to_f64(reinterpret_cast<const T *>(a.X)[a.v1 * a.ld + c]);
+    if (problem == kSES) y0 = row_value<T>(a, a.v1, c);
     a.vec[kVecS * d + c] = 0.0;
     a.vec[kVecMean * d + c] = y0;  // SES: ubar(0) = v1 (only distances of pass 1 use it)
     a.vec[kVecBest * d + c] = y0;

@@ -1,0 +1,20 @@
+// Streaming-pass kernels instantiated for FP8 E4M3 codes (one scale per row).
+#include "mwu_kernels.hpp"
+
+namespace scpmwu {
+
+hipError_t launch_pass_fp8(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
+  return launch_pass_typed<uint8_t>(problem, c, a, s);
+}
+hipError_t launch_epilogue_fp8(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
+  return launch_epilogue_typed<uint8_t>(problem, c.cert, c.grid, a, s);
+}
+hipError_t launch_monitor_fp8(int grid, const PassArgs &a, const double *center, int64_t exclude,
+                               int mode, double *out, hipStream_t s) {
+  return launch_monitor_typed<uint8_t>(grid, a, center, exclude, mode, out, s);
+}
+hipError_t launch_init_fp8(const PassArgs &a, const InitParams &p, int problem, hipStream_t s) {
+  return launch_init_typed<uint8_t>(a, p, problem, s);
+}
+
+}  // namespace scpmwu

@@ -26,7 +26,7 @@ thread_local std::string g_init_error;
 
 constexpr double kTau = 1e-12;  // relative tie tolerance of the separation test
 
-size_t elem_size(int dt) { return dt == kBF16 ? 2 : (dt == kF32 ? 4 : 8); }
+size_t elem_size(int dt) { return dt == kFP8 ? 1 : (dt == kBF16 ? 2 : (dt == kF32 ? 4 : 8)); }
 
 }  // namespace
 
@@ -36,6 +36,7 @@ struct scp_mwu_ctx {
   int64_t n = 0, d = 0, ld = 0, n_pos = 0, v1 = 0;
   const void *X = nullptr;
   void *owned = nullptr;
+  float *owned_scales = nullptr;  // FP8 storage: one scale per row
   const double *radii = nullptr;
   double eps = 1e-3, delta = 1e-4;
   int32_t patience = 10, flags = 0, chunk = 32;
@@ -78,6 +79,7 @@ hipError_t pass_kernel(scp_mwu_ctx *c, bool cert, hipStream_t s) {
   switch (c->dtype) {
     case kF32: return launch_pass_f32(c->problem, cfg, c->args, s);
     case kBF16: return launch_pass_bf16(c->problem, cfg, c->args, s);
+    case kFP8: return launch_pass_fp8(c->problem, cfg, c->args, s);
     default: return launch_pass_f64(c->problem, cfg, c->args, s);
   }
 }
@@ -88,6 +90,7 @@ hipError_t epilogue_kernel(scp_mwu_ctx *c, bool cert, hipStream_t s) {
   switch (c->dtype) {
     case kF32: return launch_epilogue_f32(c->problem, cfg, c->args, s);
     case kBF16: return launch_epilogue_bf16(c->problem, cfg, c->args, s);
+    case kFP8: return launch_epilogue_fp8(c->problem, cfg, c->args, s);
     default: return launch_epilogue_f64(c->problem, cfg, c->args, s);
   }
 }
@@ -103,6 +106,7 @@ hipError_t monitor(scp_mwu_ctx *c, const double *center, int64_t exclude, int mo
   switch (c->dtype) {
     case kF32: return launch_monitor_f32(c->grid, c->args, center, exclude, mode, c->mon, c->stream);
     case kBF16: return launch_monitor_bf16(c->grid, c->args, center, exclude, mode, c->mon, c->stream);
+    case kFP8: return launch_monitor_fp8(c->grid, c->args, center, exclude, mode, c->mon, c->stream);
     default: return launch_monitor_f64(c->grid, c->args, center, exclude, mode, c->mon, c->stream);
   }
 }
@@ -144,6 +148,7 @@ int start_test(scp_mwu_ctx *c, double alpha, int64_t T, bool early) {
   switch (c->dtype) {
     case kF32: e = launch_init_f32(c->args, p, c->problem, c->stream); break;
     case kBF16: e = launch_init_bf16(c->args, p, c->problem, c->stream); break;
+    case kFP8: e = launch_init_fp8(c->args, p, c->problem, c->stream); break;
     default: e = launch_init_f64(c->args, p, c->problem, c->stream); break;
   }
   int rc = c->hip(e, "test init");
@@ -282,6 +287,7 @@ void scp_mwu_destroy(scp_mwu_ctx *c) {
   hipFree(c->partials);
   hipFree(c->mon);
   hipFree(c->owned);
+  hipFree(c->owned_scales);
   if (c->host_st) hipHostFree(c->host_st);
   delete c;
 }
@@ -300,9 +306,10 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
     return bad("unknown problem");
   if (desc->dtype < SCP_MWU_F32 || desc->dtype > SCP_MWU_F64) return bad("unknown dtype");
   const int storage = desc->storage ? desc->storage : desc->dtype;
-  if (storage < SCP_MWU_F32 || storage > SCP_MWU_F64) return bad("unknown storage type");
-  if (storage != desc->dtype && !(desc->dtype == SCP_MWU_F32 && storage == SCP_MWU_BF16))
-    return bad("storage conversion other than F32 -> BF16");
+  if (storage < SCP_MWU_F32 || storage > SCP_MWU_FP8) return bad("unknown storage type");
+  if (storage != desc->dtype &&
+      !(desc->dtype == SCP_MWU_F32 && (storage == SCP_MWU_BF16 || storage == SCP_MWU_FP8)))
+    return bad("storage conversion other than F32 -> BF16 or F32 -> FP8");
   if (!desc->points) return bad("points is NULL");
   if (desc->n < 2) return bad("n < 2");
   if (desc->d < 1 || desc->d > kMaxD) return bad("d outside [1, 512]");
@@ -348,16 +355,25 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return fail(SCP_MWU_E_HIP, "no HIP device");
 
-  // storage: borrowed, or a library-owned BF16 copy
+  // storage: borrowed, or a library-owned BF16 copy or FP8 codes and scales
   c->dtype = storage;
   c->X = desc->points;
-  if (storage != desc->dtype) {
+  if (storage == kBF16 && desc->dtype != kBF16) {
     const int64_t ldb = desc->d;
     if (hipMalloc(&c->owned, (size_t)c->n * ldb * 2) != hipSuccess) return fail(SCP_MWU_E_NOMEM, "BF16 copy");
     if (launch_cast((const float *)desc->points, (uint16_t *)c->owned, c->n, c->d, ld, ldb, c->stream) != hipSuccess)
       return fail(SCP_MWU_E_HIP, "BF16 cast launch");
     c->X = c->owned;
     c->ld = ldb;
+  } else if (storage == kFP8) {
+    if (hipMalloc(&c->owned, (size_t)c->n * c->d) != hipSuccess ||
+        hipMalloc(&c->owned_scales, sizeof(float) * (size_t)c->n) != hipSuccess)
+      return fail(SCP_MWU_E_NOMEM, "FP8 codes and scales");
+    if (launch_quantize_fp8((const float *)desc->points, c->n, c->d, ld, (uint8_t *)c->owned, c->owned_scales,
+                            c->stream) != hipSuccess)
+      return fail(SCP_MWU_E_HIP, "FP8 quantize launch");
+    c->X = c->owned;
+    c->ld = c->d;
   }
 
   // launch shape
@@ -405,6 +421,7 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   a.st = c->st;
   a.vec = c->vec;
   a.partials = c->partials;
+  a.scales = c->owned_scales;
 
   // D (one streaming pass): SES distance from v1, SVM largest norm.
   c->r = c->problem == kSES ? 2 * (c->n - 1) : c->n;
@@ -724,6 +741,14 @@ int scp_mwu_read_reference(const void *buf, int64_t bytes, int32_t reps, void *s
   (void)hipFree(sink);
   if (!rc) *ms = (double)t / reps;
   return rc;
+}
+
+int scp_mwu_quantize_fp8(const float *src, int64_t n, int64_t d, int64_t ld, uint8_t *codes, float *scales,
+                         void *stream) {
+  if (!src || !codes || !scales || n < 0 || d < 1 || ld < d) return SCP_MWU_E_INVAL;
+  if (n == 0) return SCP_MWU_OK;
+  const hipError_t e = launch_quantize_fp8(src, n, d, ld, codes, scales, (hipStream_t)stream);
+  return e == hipSuccess ? SCP_MWU_OK : SCP_MWU_E_HIP;
 }
 
 int scp_mwu_cast_bf16(const float *src, uint16_t *dst, int64_t n, void *stream) {

@@ -162,7 +162,7 @@ def fp8_e4m3_encode(v32: np.ndarray) -> np.ndarray:
     m3 = m3 & 0x7
     normal = ((e + 7) << 3) | m3
     # subnormals of the target (|a| < 2^-6): multiples of 2^-9, to nearest even
-    sub = np.rint(a.astype(np.float64) * 512.0).astype(np.int64)
+    sub = np.rint(np.where(a < 2.0 ** -6, a, 0.0).astype(np.float64) * 512.0).astype(np.int64)
     code = np.where(a < 2.0 ** -6, sub, normal)
     code = np.where(a >= 464.0, 0x7E, np.minimum(code, 0x7E))
     code = np.where(np.isnan(v), 0x7F, code)

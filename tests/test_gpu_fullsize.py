@@ -57,13 +57,25 @@ def test_ses_1m_d100_bf16_fullsize():
     _ses_case(V, Vq, "bf16", lambda P: 0.8 * P.D, tol=2e-4)
 
 
-@pytest.mark.parametrize("storage", [None, "bf16"])
+def test_ses_1m_d100_fp8_fullsize():
+    V = synth.ses_gaussian_outliers(1_000_000, 100, 0, dtype=np.float32)
+    codes, scales = synth.fp8_rows(V)
+    # binary32 per-element arithmetic, as with BF16 storage (same bound)
+    _ses_case(V, synth.fp8_values(codes, scales), "fp8", lambda P: 0.8 * P.D, tol=2e-4)
+
+
+@pytest.mark.parametrize("storage", [None, "bf16", "fp8"])
 def test_svm_500k_d256_fullsize(storage):
     import torch
     import paper_2405_09157_amd as scp
     X, _ = synth.svm_planted(250_000, 250_000, 256, 0, dtype=np.float32)
-    X64 = X.astype(np.float64) if storage is None else synth.bf16_to_f32(synth.bf16_round(X)).astype(np.float64)
-    tol = TIGHT  # the SVM pass is binary64 for both storage types
+    if storage is None:
+        X64 = X.astype(np.float64)
+    elif storage == "bf16":
+        X64 = synth.bf16_to_f32(synth.bf16_round(X)).astype(np.float64)
+    else:
+        X64 = synth.fp8_values(*synth.fp8_rows(X))
+    tol = TIGHT  # the SVM pass is binary64 for every storage type
     Pb = osvm.setup(X64, 250_000)
     alpha, T = 0.12, 20000            # near the planted margin
     eta = math.sqrt(math.log(Pb.r) / T)

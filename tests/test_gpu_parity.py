@@ -260,7 +260,7 @@ def test_invalid_descriptors_raise():
     for bad in (np.nan, np.inf):
         Xn = np.random.default_rng(1).standard_normal((1000, 7)).astype(np.float32)
         Xn[517, 3] = bad
-        for kw in (dict(), dict(storage="bf16")):
+        for kw in (dict(), dict(storage="bf16"), dict(storage="fp8")):
             with pytest.raises(scp.ScpMwuError) as e:
                 mwu(dev(Xn, torch.float32), "ses", **kw)
             assert e.value.code == scp.SCP_MWU_E_NUMERIC
@@ -446,3 +446,131 @@ def test_svm_bf16_step_parity(n1, n2, d):
     Xb = torch.from_numpy(h.view(np.int16)).cuda().view(torch.bfloat16)
     Pb = osvm.setup(Xq, n1)
     svm_compare_steps(Xb, Xq, n1, 0.5 * Pb.D, 2000, 25)
+
+
+# ------------------------------------------------------------- FP8 storage
+def fp8_points(X32):
+    """Per-row scaled FP8 storage of FP32 points, and the FP64 values it holds."""
+    codes, scales = synth.fp8_rows(X32.astype(np.float32))
+    return codes, scales, synth.fp8_values(codes, scales)
+
+
+def _fp8_quantize_input(n, ld, seed):
+    """Rows of widely varying magnitude, plus special rows: all zeros, a row
+    whose largest magnitude is 448 (scale exactly 1) holding the ties between
+    neighbouring E4M3 values (normal and subnormal), and a row with one large
+    entry so that most quotients fall in the subnormal range."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    x = (g.standard_normal((n, ld)) * np.exp(g.uniform(-20.0, 20.0, (n, 1)))).astype(np.float32)
+    if n > 1:
+        x[1] = 0.0
+    if n > 2:
+        ties = np.array([1.0625, 1.1875, 3.75 + 0.125, -0.5 - 0.03125, 2.0 ** -9 * 2.5, -(2.0 ** -9) * 0.5,
+                         2.0 ** -9 * 7.5, 2.0 ** -6 * (1 - 2.0 ** -5), 416.0, -240.0, 0.0], np.float32)
+        x[2] = g.standard_normal(ld).astype(np.float32)
+        x[2, 0] = 448.0
+        x[2, 1:1 + min(ld - 1, ties.size)] = ties[:max(ld - 1, 0)]
+    if n > 3:
+        x[3] = g.standard_normal(ld).astype(np.float32) * 1e-3
+        x[3, ld // 2] = 50.0
+    return x
+
+
+@pytest.mark.parametrize("n,d,ld", [(1000, 100, 100), (517, 3, 5), (300, 77, 80), (64, 512, 512), (5, 1, 1),
+                                    (4, 16, 20), (0, 8, 8)])
+def test_fp8_quantize_bit_exact(n, d, ld):
+    """The library's FP8 storage conversion against the host definition of
+    the format: every code and every scale bit-exact, strided input
+    included."""
+    import torch
+    import paper_2405_09157_amd as scp
+    x = _fp8_quantize_input(n, ld, seed=n + d)
+    src = torch.from_numpy(x).cuda() if n > 0 else torch.zeros(ld, dtype=torch.float32, device="cuda")
+    codes = torch.full((max(n * d, 1),), 0xAA, dtype=torch.uint8, device="cuda")
+    scales = torch.full((max(n, 1),), -1.0, dtype=torch.float32, device="cuda")
+    scp.scp_mwu_quantize_fp8(src.data_ptr(), n, d, ld, codes.data_ptr(), scales.data_ptr(),
+                             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    if n == 0:
+        assert codes.cpu().numpy()[0] == 0xAA and scales.cpu().numpy()[0] == -1.0  # nothing written
+        return
+    ref_codes, ref_scales = synth.fp8_rows(x[:, :d])
+    assert np.array_equal(scales.cpu().numpy().view(np.uint32), ref_scales.view(np.uint32))
+    assert np.array_equal(codes.cpu().numpy().reshape(n, d), ref_codes)
+
+
+def test_fp8_quantize_rejects_bad_arguments():
+    import torch
+    import paper_2405_09157_amd as scp
+    src = torch.zeros(64, dtype=torch.float32, device="cuda")
+    codes = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    scales = torch.zeros(8, dtype=torch.float32, device="cuda")
+    for n, d, ld in ((8, 8, 7), (-1, 8, 8), (8, 0, 8)):
+        with pytest.raises(scp.ScpMwuError):
+            scp.scp_mwu_quantize_fp8(src.data_ptr(), n, d, ld, codes.data_ptr(), scales.data_ptr())
+    with pytest.raises(scp.ScpMwuError):
+        scp.scp_mwu_quantize_fp8(0, 8, 8, 8, codes.data_ptr(), scales.data_ptr())
+
+
+@pytest.mark.parametrize("n,d", [(1001, 3), (517, 20), (2049, 64), (777, 100), (1500, 200), (63, 32), (400, 300),
+                                 (301, 12), (999, 34), (500, 35)])
+def test_ses_fp8_step_parity_shapes(n, d):
+    """SES with FP8 storage at every column layout (1 and 2 columns per lane
+    and 32 unpacked; 4, 8, 16 kept as packed code quadruples, filled by
+    16-, 8-, 4-, 2- and 1-byte loads), ragged n,
+    against the oracle on the stored values at the BF16_STEP bar: the per-
+    element arithmetic is binary32 as with BF16 storage (the stored value
+    s_r q is formed exactly inside a fused multiply-add), with the same
+    bound."""
+    import torch
+    V = synth.ses_gaussian_outliers(n, d, seed=n + d).astype(np.float32)
+    _, _, Vq = fp8_points(V)
+    P = oses.setup(Vq)
+    ses_compare_steps(dev(V, torch.float32), Vq, 0.8 * P.D, 3000, 12, tol=BF16_STEP, storage="fp8")
+
+
+def test_ses_fp8_spheres_strided_and_certificate():
+    """FP8 storage with sphere radii, an easy set other than row 0, strided
+    FP32 input, and the certificate passes of the early exits."""
+    import torch
+    n, d, ld = 2500, 100, 104
+    V = synth.ses_gaussian_outliers(n, d, seed=5).astype(np.float32)
+    buf = np.zeros((n, ld), np.float32)
+    buf[:, :d] = V
+    view = torch.from_numpy(buf).cuda()[:, :d]
+    radii = np.random.default_rng(6).uniform(0.0, 0.3, n)
+    _, _, Vq = fp8_points(V)
+    P = oses.setup(Vq, radii, 17)
+    ses_compare_steps(view, Vq, 0.9 * P.D, 3000, 15, radii=radii, v1=17, tol=BF16_STEP, storage="fp8")
+
+
+def test_ses_fp8_solve_certifies_stored_points():
+    """End to end with FP8 storage: the returned ball holds every stored
+    point (sphere), and its radius is within the solve's accuracy of the
+    oracle's radius on the same stored points."""
+    import torch
+    V = synth.ses_gaussian_outliers(2000, 64, seed=4).astype(np.float32)
+    _, _, Vq = fp8_points(V)
+    ref = oses.solve(Vq, eps=2e-2)
+    m = mwu(dev(V, torch.float32), "ses", eps=2e-2, storage="fp8")
+    out = m.solve()
+    m.close()
+    c = np.array(out["center"])
+    far = np.max(np.linalg.norm(Vq - c, axis=1))
+    assert far <= out["radius"] * (1 + 1e-9)
+    assert abs(out["radius"] - ref.radius) / ref.radius <= 2 * 2e-2
+    assert out["lower"] <= far
+
+
+@pytest.mark.parametrize("n1,n2,d", [(1500, 1300, 256), (700, 900, 16), (40, 25, 2), (3000, 2000, 100),
+                                     (500, 600, 300)])
+def test_svm_fp8_step_parity(n1, n2, d):
+    """SVM with FP8 storage: binary64 arithmetic on the codes, the row scale
+    applied to the dot product and to the weight, against the oracle on the
+    stored values at the 1e-9 bar."""
+    import torch
+    X, _ = synth.svm_planted(n1, n2, d, seed=d + 11)
+    X32 = X.astype(np.float32)
+    _, _, Xq = fp8_points(X32)
+    Pb = osvm.setup(Xq, n1)
+    svm_compare_steps(dev(X32, torch.float32), Xq, n1, 0.5 * Pb.D, 2000, 25, storage="fp8")
