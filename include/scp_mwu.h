@@ -279,6 +279,101 @@ const char *scp_mwu_last_error(const scp_mwu_ctx *ctx);
 const char *scp_mwu_strerror(int code);
 
 /*
+ * Batched smallest enclosing sphere: m independent SES point sets (Section
+ * 4.1 for each), advanced together.  Every MWU iteration of the batch is one
+ * streaming pass per column layout over all instances (each instance split
+ * into workgroup shares of about rows_per_group rows) and one epilogue launch
+ * with one workgroup per instance; `chunk` iterations are captured in one HIP
+ * graph.  Per instance the arithmetic, the alpha-feasibility test and the
+ * alpha search are those of scp_mwu_step / scp_mwu_solve for a point set
+ * (no radii, v1 = row 0, no certificates).
+ */
+typedef struct scp_mwu_batch_desc {
+  uint32_t struct_size;  /* sizeof(scp_mwu_batch_desc) as compiled by the caller */
+  int32_t dtype;         /* SCP_MWU_F32 */
+  int32_t storage;       /* 0 = dtype, or SCP_MWU_BF16: init rounds the points
+                            once into a library-owned BF16 copy (binary32
+                            per-element arithmetic, as for one problem) */
+  int32_t count;         /* number of instances m >= 1 */
+  const int64_t *n;      /* host, m values: points of instance k, >= 2 */
+  const int64_t *d;      /* host, m values: dimension of instance k, in [1, 512] */
+  const int64_t *offset; /* host, m values: element offset of instance k's first
+                            point in `points`; its n[k] rows are dense (stride
+                            d[k]); instances must not overlap */
+  const void *points;    /* device, binary32 */
+  double eps;            /* target accuracy of scp_mwu_batch_solve; default 1e-3 */
+  double delta;          /* stabilisation threshold; default 1e-4 */
+  int32_t patience;      /* default 10 */
+  int32_t flags;         /* SCP_MWU_FLAG_NO_EARLY_STOP, SCP_MWU_FLAG_THEORY */
+  int64_t t_cap;         /* cap on T per test; 0 = min(ceil(ln n_k / eps^2), 20000) */
+  int64_t max_iters;     /* per-instance iteration budget of scp_mwu_batch_solve,
+                            checked between tests; 0 = unlimited */
+  void *stream;          /* hipStream_t; NULL = the null stream */
+  int32_t chunk;         /* iterations per graph launch; default 32 */
+  int32_t rows_per_group;/* rows per workgroup share of the pass; default 16384 */
+} scp_mwu_batch_desc;
+
+typedef struct scp_mwu_batch scp_mwu_batch;
+
+/*
+ * Validate, allocate the batch's workspace (state, vectors and records of
+ * every instance, the tile tables, pinned readback), make the BF16 copy if
+ * asked, and compute every instance's D (one workgroup per instance).
+ * Errors: E_INVAL (NULL pointers, count < 1, n < 2, d outside [1, 512],
+ * negative offset, misaligned points, dtype other than F32, storage other
+ * than F32/BF16, an instance whose points all coincide), E_NUMERIC (NaN/Inf
+ * in some instance's points), E_NOMEM, E_HIP.  *out is NULL on error.
+ */
+int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out);
+
+/*
+ * Run up to k >= 0 iterations of every instance's alpha-feasibility test.
+ * alpha, T (host, m values each): instance j (re)starts its test when reset
+ * is non-zero, when it has none, or when alpha[j] or T[j] differ from its
+ * current test.  Instances whose test ends stop iterating.  info (host, m
+ * entries) receives each instance's state.  Errors: E_INVAL (NULL, k < 0,
+ * some alpha <= 0 or T < 1), E_HIP, E_NUMERIC (some outcome NUMERIC).
+ */
+int scp_mwu_batch_step(scp_mwu_batch *b, const double *alpha, const int64_t *T, int32_t k,
+                       int32_t reset, scp_mwu_stepinfo *info);
+
+/*
+ * Solve every instance to eps with the alpha search of scp_mwu_solve; the
+ * instances' searches run concurrently (a test that ends inside a graph chunk
+ * waits for the chunk's end).  res (host, m entries); y (host, may be NULL):
+ * instance k's centre (d_k values) then its radius, instances in order
+ * (sum of d_k + 1 values).  OK when every search met its stop rule, STOPPED
+ * when some budget ran out first (outputs valid).  Errors: E_INVAL, E_HIP,
+ * E_NUMERIC.
+ */
+int scp_mwu_batch_solve(scp_mwu_batch *b, scp_mwu_result *res, double *y);
+
+/*
+ * Vectors of every instance's current test (host, sum of d_k doubles,
+ * instances in order): which = 0 mean, 1 best mean, 2 last ORACLE output.
+ * E_INVAL (NULL, which outside [0, 2]), E_STATE before any test, E_HIP.
+ */
+int scp_mwu_batch_get_vector(scp_mwu_batch *b, int32_t which, double *y);
+
+/* D of every instance (host, m values); E_INVAL on NULL. */
+int scp_mwu_batch_get_D(const scp_mwu_batch *b, double *D);
+
+/*
+ * Measurement helper: k >= 1 further iterations of the current tests with
+ * HIP events around the streaming passes (all column layouts) and around the
+ * whole iteration, on the batch's stream; mean milliseconds of each in
+ * *ms_pass, *ms_iter (host).  E_INVAL, E_STATE (no test), E_HIP.
+ */
+int scp_mwu_batch_time_iters(scp_mwu_batch *b, int32_t k, double *ms_pass, double *ms_iter);
+
+/* Release the batch's workspace; NULL is a no-op. */
+void scp_mwu_batch_destroy(scp_mwu_batch *b);
+
+/* Text of the batch's last error ("" if none; b NULL: the last failed
+ * scp_mwu_batch_init in this thread). */
+const char *scp_mwu_batch_last_error(const scp_mwu_batch *b);
+
+/*
  * Round n FP32 values to BF16 (nearest, ties to even; NaN stays NaN) on the
  * device: src (device, n floats) -> dst (device, n uint16).  The storage
  * conversion init uses; exported so callers can build BF16 inputs.

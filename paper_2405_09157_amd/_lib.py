@@ -30,7 +30,10 @@ OUTCOME_NAMES = {0: "running", 1: "separated", 2: "beat_alpha", 3: "stabilized",
 EXPORTS = ("scp_mwu_init", "scp_mwu_step", "scp_mwu_solve", "scp_mwu_backward",
            "scp_mwu_get_state", "scp_mwu_set_state", "scp_mwu_get_vector", "scp_mwu_get_D",
            "scp_mwu_destroy", "scp_mwu_last_error", "scp_mwu_strerror", "scp_mwu_cast_bf16",
-           "scp_mwu_time_passes", "scp_mwu_read_reference", "scp_mwu_quantize_fp8")
+           "scp_mwu_time_passes", "scp_mwu_read_reference", "scp_mwu_quantize_fp8",
+           "scp_mwu_batch_init", "scp_mwu_batch_step", "scp_mwu_batch_solve", "scp_mwu_batch_get_vector",
+           "scp_mwu_batch_get_D", "scp_mwu_batch_time_iters", "scp_mwu_batch_destroy",
+           "scp_mwu_batch_last_error")
 
 
 class scp_mwu_desc(ctypes.Structure):
@@ -91,6 +94,28 @@ class scp_mwu_result(ctypes.Structure):
     ]
 
 
+class scp_mwu_batch_desc(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("dtype", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
+        ("count", ctypes.c_int32),
+        ("n", ctypes.POINTER(ctypes.c_int64)),
+        ("d", ctypes.POINTER(ctypes.c_int64)),
+        ("offset", ctypes.POINTER(ctypes.c_int64)),
+        ("points", ctypes.c_void_p),
+        ("eps", ctypes.c_double),
+        ("delta", ctypes.c_double),
+        ("patience", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("t_cap", ctypes.c_int64),
+        ("max_iters", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+        ("chunk", ctypes.c_int32),
+        ("rows_per_group", ctypes.c_int32),
+    ]
+
+
 _lib = None
 
 
@@ -121,6 +146,14 @@ def load() -> ctypes.CDLL:
         "scp_mwu_time_passes": (i32, [vp, i32, P(f64), P(f64)]),
         "scp_mwu_read_reference": (i32, [vp, i64, i32, vp, P(f64)]),
         "scp_mwu_quantize_fp8": (i32, [vp, i64, i64, i64, vp, vp, vp]),
+        "scp_mwu_batch_init": (i32, [P(scp_mwu_batch_desc), P(vp)]),
+        "scp_mwu_batch_step": (i32, [vp, P(f64), P(i64), i32, i32, P(scp_mwu_stepinfo)]),
+        "scp_mwu_batch_solve": (i32, [vp, P(scp_mwu_result), P(f64)]),
+        "scp_mwu_batch_get_vector": (i32, [vp, i32, P(f64)]),
+        "scp_mwu_batch_get_D": (i32, [vp, P(f64)]),
+        "scp_mwu_batch_time_iters": (i32, [vp, i32, P(f64), P(f64)]),
+        "scp_mwu_batch_destroy": (None, [vp]),
+        "scp_mwu_batch_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -223,3 +256,56 @@ def scp_mwu_read_reference(ptr: int, nbytes: int, reps: int = 20, stream: int = 
 
 def scp_mwu_strerror(code: int) -> str:
     return load().scp_mwu_strerror(code).decode()
+
+
+# ---- batched SES
+def _check_batch(code: int, b=None) -> int:
+    if code < 0:
+        lib = load()
+        text = lib.scp_mwu_batch_last_error(b).decode() or lib.scp_mwu_strerror(code).decode()
+        raise ScpMwuError(code, text)
+    return code
+
+
+def scp_mwu_batch_init(desc: scp_mwu_batch_desc) -> ctypes.c_void_p:
+    b = ctypes.c_void_p()
+    _check_batch(load().scp_mwu_batch_init(ctypes.byref(desc), ctypes.byref(b)))
+    return b
+
+
+def scp_mwu_batch_step(b, alpha, T, k: int, reset: int = 0):
+    m = len(alpha)
+    a = (ctypes.c_double * m)(*[float(v) for v in alpha])
+    t = (ctypes.c_int64 * m)(*[int(v) for v in T])
+    info = (scp_mwu_stepinfo * m)()
+    _check_batch(load().scp_mwu_batch_step(b, a, t, k, reset, info), b)
+    return list(info)
+
+
+def scp_mwu_batch_solve(b, m: int, d_total: int):
+    res = (scp_mwu_result * m)()
+    y = (ctypes.c_double * (d_total + m))()
+    code = _check_batch(load().scp_mwu_batch_solve(b, res, y), b)
+    return code, list(res), list(y)
+
+
+def scp_mwu_batch_get_vector(b, which: int, d_total: int):
+    y = (ctypes.c_double * d_total)()
+    _check_batch(load().scp_mwu_batch_get_vector(b, which, y), b)
+    return list(y)
+
+
+def scp_mwu_batch_get_D(b, m: int):
+    D = (ctypes.c_double * m)()
+    _check_batch(load().scp_mwu_batch_get_D(b, D), b)
+    return list(D)
+
+
+def scp_mwu_batch_time_iters(b, k: int):
+    mp, mi = ctypes.c_double(), ctypes.c_double()
+    _check_batch(load().scp_mwu_batch_time_iters(b, k, ctypes.byref(mp), ctypes.byref(mi)), b)
+    return mp.value, mi.value
+
+
+def scp_mwu_batch_destroy(b) -> None:
+    load().scp_mwu_batch_destroy(b)

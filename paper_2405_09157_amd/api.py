@@ -123,3 +123,102 @@ class MWU:
 
     def eta(self, T: int) -> float:
         return math.sqrt(math.log(self.r) / T)
+
+
+class MWUBatch:
+    """Many independent SES point sets solved together (one streaming pass per
+    column layout and one epilogue launch per MWU iteration of the batch).
+
+    points   device float32 tensor holding every instance's rows back to back
+             (instance k: n[k] dense rows of d[k] values from element
+             offset[k]; offsets default to the packed layout).
+    storage  None or "bf16" (library-owned BF16 copy).
+    """
+
+    def __init__(self, points, n, d, offset=None, *, eps: float = 1e-3, delta: float = 1e-4,
+                 patience: int = 10, flags: int = 0, t_cap: int = 0, max_iters: int = 0,
+                 storage: str | None = None, chunk: int = 0, rows_per_group: int = 0, stream=None):
+        import ctypes
+        import torch
+        L.load()
+        if not points.is_cuda or points.dtype != torch.float32 or not points.is_contiguous():
+            raise ValueError("points must be a contiguous float32 device tensor")
+        self.points = points
+        self.n = [int(v) for v in n]
+        self.d = [int(v) for v in d]
+        self.m = len(self.n)
+        if offset is None:
+            offset, o = [], 0
+            for nk, dk in zip(self.n, self.d):
+                offset.append(o)
+                o += nk * dk
+        self.offset = [int(v) for v in offset]
+        self.d_total = sum(self.d)
+        if stream is None:
+            stream = torch.cuda.current_stream(points.device)
+        self.stream = stream
+        I64 = ctypes.c_int64 * self.m
+        self._arrays = (I64(*self.n), I64(*self.d), I64(*self.offset))
+        desc = L.scp_mwu_batch_desc()
+        desc.struct_size = ctypes.sizeof(L.scp_mwu_batch_desc)
+        desc.dtype = L.SCP_MWU_F32
+        desc.storage = {None: 0, "bf16": L.SCP_MWU_BF16}[storage]
+        desc.count = self.m
+        desc.n, desc.d, desc.offset = self._arrays
+        desc.points = points.data_ptr()
+        desc.eps, desc.delta, desc.patience = float(eps), float(delta), int(patience)
+        desc.flags, desc.t_cap, desc.max_iters = int(flags), int(t_cap), int(max_iters)
+        desc.stream = stream.cuda_stream
+        desc.chunk, desc.rows_per_group = int(chunk), int(rows_per_group)
+        with torch.cuda.device(points.device):
+            self.b = L.scp_mwu_batch_init(desc)
+        self.D = L.scp_mwu_batch_get_D(self.b, self.m)
+
+    def close(self):
+        if getattr(self, "b", None):
+            L.scp_mwu_batch_destroy(self.b)
+            self.b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _split(self, flat, extra=0):
+        out, o = [], 0
+        for dk in self.d:
+            out.append(flat[o:o + dk + extra])
+            o += dk + extra
+        return out
+
+    def step(self, alpha, T, k: int, reset: bool = False) -> list:
+        infos = L.scp_mwu_batch_step(self.b, list(alpha), list(T), int(k), int(reset))
+        out = []
+        for info in infos:
+            r = {f: getattr(info, f) for f, _ in L.scp_mwu_stepinfo._fields_}
+            r["outcome_name"] = L.OUTCOME_NAMES[info.outcome]
+            out.append(r)
+        return out
+
+    def solve(self):
+        code, res, y = L.scp_mwu_batch_solve(self.b, self.m, self.d_total)
+        out = []
+        for r, yk in zip(res, self._split(y, 1)):
+            o = {f: getattr(r, f) for f, _ in L.scp_mwu_result._fields_}
+            o["center"], o["radius"] = yk[:-1], yk[-1]
+            out.append(o)
+        return code, out
+
+    def vectors(self, which: int) -> list:
+        return self._split(L.scp_mwu_batch_get_vector(self.b, which, self.d_total))
+
+    def time_iters(self, k: int):
+        """(pass ms, whole-iteration ms): HIP-event means over k further iterations."""
+        return L.scp_mwu_batch_time_iters(self.b, int(k))

@@ -22,7 +22,8 @@ OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libscpmwu.so")
 ARCH = os.environ.get("SCPMWU_ARCH", "gfx950")
 
-SOURCES = ["pass_f32.hip", "pass_bf16.hip", "pass_f64.hip", "pass_fp8.hip", "misc.hip", "scp_mwu_host.cpp"]
+SOURCES = ["pass_f32.hip", "pass_bf16.hip", "pass_f64.hip", "pass_fp8.hip", "batch_f32.hip", "batch_bf16.hip",
+           "misc.hip", "scp_mwu_host.cpp", "batch_host.cpp"]
 
 
 def hipcc() -> str:

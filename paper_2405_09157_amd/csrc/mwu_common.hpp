@@ -149,6 +149,23 @@ struct LaunchCfg {
   int pfm;     // Prefetch mode
 };
 
+// One workgroup's share of a batched pass: workgroup vb of the vg workgroups
+// of instance inst.
+struct BatchTile {
+  int32_t inst, vb, vg, pad;
+};
+
+#define SCPMWU_DECLARE_BATCH(name)                                                                       \
+  hipError_t launch_pass_batch_##name(int epl, int vec, int ntiles, const PassArgs *args,                \
+                                      const BatchTile *tiles, hipStream_t s);                            \
+  hipError_t launch_epilogue_batch_##name(int m, const PassArgs *args, const int32_t *nrec, hipStream_t s); \
+  hipError_t launch_init_batch_##name(int count, const PassArgs *args, const int32_t *list,              \
+                                      const InitParams *params, hipStream_t s);                          \
+  hipError_t launch_diameter_batch_##name(int m, const PassArgs *args, double *D, hipStream_t s);
+SCPMWU_DECLARE_BATCH(f32)
+SCPMWU_DECLARE_BATCH(bf16)
+#undef SCPMWU_DECLARE_BATCH
+
 hipError_t launch_read_reference(const void *buf, int64_t bytes, int grid, float *sink, hipStream_t s);
 hipError_t launch_quantize_fp8(const float *src, int64_t n, int64_t d, int64_t ld, uint8_t *codes, float *scales,
                                hipStream_t s);

@@ -396,9 +396,11 @@ __device__ __forceinline__ int lane_col(int cl, int k) {
   return ((k / VEC) * kG + cl) * VEC + (k % VEC);
 }
 
+// The SES pass of one problem, run by workgroup vb of the vg workgroups
+// assigned to it (its batches are b = vb * 8 + wave, strided by vg * 8; its
+// record goes to partials[vb]).
 template <typename T, int EPL, int VEC, bool CERT, int PFM>
-__global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
-void ses_pass_kernel(PassArgs a) {
+__device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg) {
   using Sh = PassShape<T, EPL, kSES, PFM>;
   constexpr int SB = Sh::SB, B = Sh::B;
   using Regs = typename Sh::Regs;
@@ -440,7 +442,7 @@ void ses_pass_kernel(PassArgs a) {
   double asum = 0.0, bsum = 0.0, esum = 0.0, gsum = 0.0, bd2 = 0.0, gmax = -INFINITY, fall = -INFINITY;
 
   const int64_t nb = (n + B - 1) / B;
-  const int64_t GW = (int64_t)gridDim.x * kPassWaves;
+  const int64_t GW = (int64_t)vg * kPassWaves;
   // lane offsets (bytes) of the lane's column chunks within its row of a
   // load step; chunks past column d get an offset beyond the buffer range
   int32_t voff[EPL / VEC];
@@ -468,12 +470,14 @@ void ses_pass_kernel(PassArgs a) {
     const int64_t r0 = b * B;
     // re-read the candidate each batch: it stays out of registers in phases 2-3
     asm volatile("" ::: "memory");
+    // binary32 storage types: the mean rounded to binary32, used by phases 1 and 3
+    float ub32[M32 ? EPL : 1];
     if constexpr (M32) {
       if constexpr (FP8) {
         if (lane < B) s_scl[wave][lane] = xs.sc;
         wave_lds_sync();
       }
-      float ub[EPL];
+      float *ub = ub32;
 #pragma unroll
       for (int k = 0; k < EPL; ++k) ub[k] = (float)s_ctr[lane_col<VEC>(cl, k)];
 #pragma unroll
@@ -527,16 +531,16 @@ void ses_pass_kernel(PassArgs a) {
       if (CERT) bd2 += bw * dsq;
       if (incl) gmax = fmax(gmax, h);
       if (valid) fall = fmax(fall, h);
-      // the weights of the stored codes: a_i x_i = (a_i s_i) q_i for FP8
-      const double sc = FP8 ? (double)xs.sc : 1.0;
-      s_wa[wave][lane] = aw * sc;
-      if (CERT) s_wb[wave][lane] = bw * sc;
+      s_wa[wave][lane] = aw;
+      if (CERT) s_wb[wave][lane] = bw;
     }
     wave_lds_sync();
     xs.pin();
-    // sum_i a_i x_i (and sum_i b_i x_i); the epilogue subtracts (sum a_i) ubar
     if constexpr (M32) {
-      // the batch's rows in binary32, added to the binary64 sums per batch
+      // sum_i a_i (x_i - ubar32) (and the b_i sum): the batch's rows in
+      // binary32 on the differences, so that no offset of the points from the
+      // origin cancels in binary32; added to the binary64 sums per batch (the
+      // epilogue adds (sum a_i)(ubar32 - ubar))
       float w32[EPL], c32[CERT ? EPL : 1];
 #pragma unroll
       for (int k = 0; k < EPL; ++k) w32[k] = 0.f;
@@ -545,12 +549,13 @@ void ses_pass_kernel(PassArgs a) {
 #pragma unroll
       for (int s = 0; s < SB; ++s) {
         const float ar = (float)s_wa[wave][s * kRowsPerStep + g];
+        const float sr = FP8 ? s_scl[wave][s * kRowsPerStep + g] : 1.f;
+        const float br = CERT ? (float)s_wb[wave][s * kRowsPerStep + g] : 0.f;
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) w32[k] = fmaf(ar, xs.getf(s, k), w32[k]);
-        if (CERT) {
-          const float br = (float)s_wb[wave][s * kRowsPerStep + g];
-#pragma unroll
-          for (int k = 0; k < EPL; ++k) c32[k] = fmaf(br, xs.getf(s, k), c32[k]);
+        for (int k = 0; k < EPL; ++k) {
+          const float df = FP8 ? fmaf(sr, xs.getf(s, k), -ub32[k]) : xs.getf(s, k) - ub32[k];
+          w32[k] = fmaf(ar, df, w32[k]);
+          if (CERT) c32[k] = fmaf(br, df, c32[k]);
         }
       }
 #pragma unroll
@@ -559,6 +564,7 @@ void ses_pass_kernel(PassArgs a) {
 #pragma unroll
         for (int k = 0; k < EPL; ++k) cacc[k] += (double)c32[k];
     } else {
+      // sum_i a_i x_i (and sum_i b_i x_i); the epilogue subtracts (sum a_i) ubar
 #pragma unroll
       for (int s = 0; s < SB; ++s) {
         const double ar = s_wa[wave][s * kRowsPerStep + g];
@@ -573,7 +579,7 @@ void ses_pass_kernel(PassArgs a) {
     }
     wave_lds_sync();
   };
-  const int64_t b0 = (int64_t)blockIdx.x * kPassWaves + wave;
+  const int64_t b0 = (int64_t)vb * kPassWaves + wave;
   // status0 is the same for the whole grid: either every wave returns below
   // (after this barrier) or none does
   __syncthreads();
@@ -635,7 +641,7 @@ void ses_pass_kernel(PassArgs a) {
     s_sc[wave][6] = fall;
   }
   __syncthreads();
-  double *rec = a.partials + (int64_t)blockIdx.x * pw;
+  double *rec = a.partials + (int64_t)vb * pw;
   const int dp = rec_dp(d);
   for (int c = tid; c < d; c += kPassBlock) rec[c] = sum_waves(s_vec, c);
   __syncthreads();
@@ -661,6 +667,12 @@ void ses_pass_kernel(PassArgs a) {
       v = -INFINITY;
     rec[dp + tid] = v;
   }
+}
+
+template <typename T, int EPL, int VEC, bool CERT, int PFM>
+__global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
+void ses_pass_kernel(PassArgs a) {
+  ses_pass_body<T, EPL, VEC, CERT, PFM>(a, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // =========================================================== SVM pass
@@ -901,7 +913,7 @@ constexpr int kPerLane = kMaxD / kWave;  // columns per lane in the one-wave epi
 // test, running mean and the bound for the next pass's exponent shift.
 // S, y (mean), Sv (running sum), v1 are LDS copies; results go to global.
 __device__ inline void ses_epilogue(const PassArgs &a, DevState &S, const double *y, const double *Sv,
-                                    const double *v1, const double *comb, bool cert) {
+                                    const double *v1, const double *comb, bool cert, bool centred) {
   const int d = (int)a.d, lane = threadIdx.x & 63;
   const double *sc = comb + rec_dp(d);
   const int64_t k = S.t + 1;
@@ -929,14 +941,15 @@ __device__ inline void ses_epilogue(const PassArgs &a, DevState &S, const double
 #pragma unroll
   for (int j = 0; j < kPerLane; ++j) {
     const int c = lane + j * kWave;
-    Wr[j] = c < d ? comb[c] - Asum * y[c] : 0.0;
+    // the record holds sum a_i x_i, or (centred) sum a_i (x_i - fl32(ubar))
+    Wr[j] = c < d ? comb[c] - Asum * (centred ? y[c] - (double)(float)y[c] : y[c]) : 0.0;
     p += Wr[j] * Wr[j];
     if (c < d) r += (v1[c] - y[c]) * Wr[j];
   }
   if (cert) {
     const double *cx = comb + rec_dp(d) + 8;
     for (int c = lane; c < d; c += kWave) {
-      const double cv = cx[c] - Bsum * y[c];
+      const double cv = cx[c] - Bsum * (centred ? y[c] - (double)(float)y[c] : y[c]);
       cc += cv * cv;
     }
     wave_sum3(p, r, cc);
@@ -1143,7 +1156,7 @@ constexpr int kStateWords = (int)(sizeof(DevState) / 8);
 // runs the FP64 epilogue on the LDS copies and writes the state back.  The
 // kernel boundary after the pass makes every record visible: no fences.
 template <typename T, int PROB, bool CERT>
-__global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P) {
+__device__ __forceinline__ void epilogue_body(const PassArgs &a, int P) {
   __shared__ double s_acc[2 * kCombBlock];
   __shared__ double s_comb[2 * kMaxD + 8];
   __shared__ double s_y[kMaxD], s_S[kMaxD], s_v1[kMaxD];
@@ -1186,11 +1199,16 @@ __global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P)
   __syncthreads();
   if (tid >= kWave || s_st.status != kRunning) return;
   if (PROB == kSES)
-    ses_epilogue(a, s_st, s_y, s_S, s_v1, s_comb, CERT);
+    ses_epilogue(a, s_st, s_y, s_S, s_v1, s_comb, CERT, sizeof(T) <= 2);
   else
     svm_epilogue(a, s_st, s_y, s_S, s_comb);
   wave_lds_sync();
   if (tid < kStateWords) reinterpret_cast<double *>(a.st)[tid] = reinterpret_cast<const double *>(&s_st)[tid];
+}
+
+template <typename T, int PROB, bool CERT>
+__global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P) {
+  epilogue_body<T, PROB, CERT>(a, P);
 }
 
 // ========================================================== monitor pass
@@ -1261,7 +1279,7 @@ __global__ __launch_bounds__(kBlock) void monitor_kernel(PassArgs a, const doubl
 
 // ======================================================= test (re)start
 template <typename T>
-__global__ __launch_bounds__(kBlock) void ftp_init_kernel(PassArgs a, InitParams p, int problem) {
+__device__ __forceinline__ void ftp_init_body(const PassArgs &a, const InitParams &p, int problem) {
   DevState *st = a.st;
   const int d = (int)a.d;
   const int tid = threadIdx.x;
@@ -1297,6 +1315,11 @@ __global__ __launch_bounds__(kBlock) void ftp_init_kernel(PassArgs a, InitParams
     s.bound = problem == kSES ? 0.0 : INFINITY;
     *st = s;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void ftp_init_kernel(PassArgs a, InitParams p, int problem) {
+  ftp_init_body<T>(a, p, problem);
 }
 
 // ============================================================== dispatch

@@ -110,6 +110,55 @@ def ses_ellipsoid(n: int, d: int, seed: int) -> np.ndarray:
     return (z * sigma) @ q.T + c
 
 
+def ses_batch_sizes(instances: int, n_lo: int, n_hi: int, dims, seed: int):
+    """Sizes of a batch of SES instances: n log-uniform in [n_lo, n_hi]
+    (rounded down to an integer), d drawn uniformly from ``dims``."""
+    g = rng(seed)
+    n = np.floor(np.exp(g.uniform(math.log(n_lo), math.log(n_hi), size=instances))).astype(np.int64)
+    d = np.asarray(dims, dtype=np.int64)[g.integers(0, len(dims), size=instances)]
+    return n, d
+
+
+def ses_batch_points(n, d, seed: int) -> np.ndarray:
+    """Every instance's points, back to back as one float32 array: instance k
+    is ses_ellipsoid(n[k], d[k], seed + 1 + k) rounded to float32."""
+    total = int(np.sum(np.asarray(n, dtype=np.int64) * np.asarray(d, dtype=np.int64)))
+    out = np.empty(total, dtype=np.float32)
+    o = 0
+    for k, (nk, dk) in enumerate(zip(n, d)):
+        out[o:o + nk * dk] = ses_ellipsoid(int(nk), int(dk), seed + 1 + k).astype(np.float32).ravel()
+        o += nk * dk
+    return out
+
+
+def ses_batch_points_device(n, d, seed: int, device="cuda"):
+    """The same recipe as ses_batch_points, drawn on the device with torch's
+    generator (a different random stream; for inputs too large to draw on the
+    host in reasonable time): returns one float32 device tensor, instances
+    back to back."""
+    import torch
+    total = int(np.sum(np.asarray(n, dtype=np.int64) * np.asarray(d, dtype=np.int64)))
+    out = torch.empty(total, dtype=torch.float32, device=device)
+    gen = torch.Generator(device=device)
+    o = 0
+    for k, (nk, dk) in enumerate(zip(n, d)):
+        nk, dk = int(nk), int(dk)
+        g = rng(seed + 1 + k)
+        q, r = np.linalg.qr(g.standard_normal(size=(dk, dk)))
+        q *= np.sign(np.diag(r))
+        sigma = np.exp(g.uniform(math.log(0.1), 0.0, size=dk))
+        c = g.standard_normal(dk)
+        A = torch.from_numpy((sigma[:, None] * q.T).astype(np.float32)).to(device)
+        gen.manual_seed(seed + 1 + k)
+        z = torch.randn(nk, dk, generator=gen, device=device)
+        z /= torch.linalg.vector_norm(z, dim=1, keepdim=True)
+        z *= torch.rand(nk, 1, generator=gen, device=device) ** (1.0 / dk)
+        y = z @ A + torch.from_numpy(c.astype(np.float32)).to(device)
+        out[o:o + nk * dk] = y.reshape(-1)
+        o += nk * dk
+    return out
+
+
 def bf16_round(x32: np.ndarray) -> np.ndarray:
     """FP32 -> BF16 bit patterns (uint16), round to nearest, ties to even.
     NaN stays NaN (quiet)."""
