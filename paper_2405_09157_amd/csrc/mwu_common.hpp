@@ -51,8 +51,8 @@ enum DType : int32_t { kF32 = 1, kBF16 = 2, kF64 = 3, kFP8 = 4 };
 // BF16 pairs for SES with an even count (at most 16), FP8 quadruples for a
 // count that is a multiple of 4 (at most 16); packing multiplies the rows per
 // batch.  SVM keeps two binary64 class accumulators per column and halves the
-// budget; with prefetch two batches share it.  At most 8 steps (16 packed,
-// where the per-row phase then fills the wave).
+// budget; with prefetch two batches share it.  At most 16 steps (64 rows,
+// one per lane in the per-row phase).
 inline __host__ __device__ constexpr bool pass_packed(int storage_size, int epl, int problem) {
   return (storage_size == 2 && epl % 2 == 0 && epl <= 16 && problem == kSES) ||
          (storage_size == 1 && epl % 4 == 0 && epl <= 16);
@@ -64,8 +64,7 @@ inline __host__ __device__ constexpr int pass_steps(int storage_size, int epl, i
   const bool pack = pass_packed(storage_size, epl, problem);
   const int lim = (storage_size == 8 ? 32 : (pack ? 128 : 64)) /
                   (problem == kSVM ? 2 : 1) / (pfm == kPrefetchRegs ? 2 : 1);
-  const int cap = pack ? 16 : 8;
-  return lim / epl < 1 ? 1 : (lim / epl > cap ? cap : lim / epl);
+  return lim / epl < 1 ? 1 : (lim / epl > 16 ? 16 : lim / epl);
 }
 
 enum Status : int32_t {

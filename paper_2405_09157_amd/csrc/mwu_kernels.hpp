@@ -166,6 +166,44 @@ struct Batch<uint16_t, SB, EPL, true> {
   }
 };
 
+// BF16 and FP8 with one column per lane: one raw code per 32-bit register,
+// widened on use.  (Widening at load time let the compiler route every narrow
+// load of a batch through one temporary register and wait for each in turn.)
+template <int SB>
+struct Batch<uint8_t, SB, 1, false> {
+  uint32_t w[SB];
+  double gi;
+  float sc;
+  __device__ __forceinline__ float getf(int s, int) const { return __builtin_amdgcn_cvt_f32_fp8(w[s], 0); }
+  __device__ __forceinline__ double get(int s, int k) const { return (double)getf(s, k); }
+  template <int VEC>
+  __device__ __forceinline__ void put(int s, int, const VecT<uint8_t, VEC> &raw) {
+    static_assert(VEC == 1, "one column per lane");
+    w[s] = raw.v[0];
+  }
+  __device__ __forceinline__ void pin() {
+#pragma unroll
+    for (int s = 0; s < SB; ++s) asm volatile("" : "+v"(w[s]));
+  }
+};
+template <int SB>
+struct Batch<uint16_t, SB, 1, false> {
+  uint32_t w[SB];
+  double gi;
+  float sc;
+  __device__ __forceinline__ float getf(int s, int) const { return __uint_as_float(w[s] << 16); }
+  __device__ __forceinline__ double get(int s, int k) const { return (double)getf(s, k); }
+  template <int VEC>
+  __device__ __forceinline__ void put(int s, int, const VecT<uint16_t, VEC> &raw) {
+    static_assert(VEC == 1, "one column per lane");
+    w[s] = raw.v[0];
+  }
+  __device__ __forceinline__ void pin() {
+#pragma unroll
+    for (int s = 0; s < SB; ++s) asm volatile("" : "+v"(w[s]));
+  }
+};
+
 // FP8 E4M3 codes kept packed, four per 32-bit register, decoded on use.
 template <int SB, int EPL>
 struct Batch<uint8_t, SB, EPL, true> {
