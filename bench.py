@@ -15,10 +15,20 @@ The same JSON line also carries
                 library's plain streaming-read kernel over the same number of
                 bytes; HBM traffic from the committed rocprofv3 counter
                 summary when it matches the kernel;
-  bf16          the same measurement with BF16 storage (library-rounded copy);
-  solve         eps = 1e-3 solves (FP32 and BF16 storage) with the paper's
+  bf16, fp8     the same measurement with BF16 storage (library-rounded copy)
+                and with FP8 E4M3 storage (library-quantized codes, one FP32
+                scale per row);
+  solve         eps = 1e-3 solves (FP32, BF16 and FP8 storage) with the paper's
                 Section 5 early stopping: wall time, iterations, tests,
                 certified bounds;
+  batched       the batched workload: 4,096 independent SES instances, n
+                log-uniform in [1e3, 1e5], d from {2, 3, 16, 64}, points
+                uniform in seeded random ellipsoids (86.7 M points, 7.4 GB as
+                FP32), drawn on the device; the rows per workgroup share are
+                picked by the library's autotuner; batched iterations/s (every
+                instance advances one MWU iteration), the pass's bytes over its
+                HIP-event time, FP32 and BF16 storage, and the eps = 1e-3 solve
+                of all 4,096 instances (solves/s);
   cpu_baseline  the FP64 reference implementation timed on this host on a
                 bounded sample (a few iterations at the full size), one
                 thread and all cores.
@@ -132,6 +142,63 @@ def solve(X, storage):
                 cert_gap=(out["upper"] - out["lower"]) / out["lower"], converged=bool(out["converged"]))
 
 
+BATCH = dict(name="ses_batched_4096", instances=4096, n_lo=1000, n_hi=100_000, dims=[2, 3, 16, 64], seed=0)
+
+
+def batched(steps, warmup, solve_storages):
+    """Batched SES: iteration rate and pass bandwidth for FP32 and BF16
+    storage, then eps = 1e-3 solves of the whole batch."""
+    import torch
+    import synth
+    import paper_2405_09157_amd as scp
+    B = BATCH
+    n, d = synth.ses_batch_sizes(B["instances"], B["n_lo"], B["n_hi"], B["dims"], B["seed"])
+    pts = synth.ses_batch_points_device(n, d, B["seed"])
+    torch.cuda.synchronize()
+    m = len(n)
+    nbytes = int((n * d).sum()) * 4
+    rpg, tune = scp.autotune_rows_per_group(pts, n, d)
+    print(f"# batched: {m} instances, {int(n.sum())} points, {nbytes / 1e9:.2f} GB; rows per group {rpg} "
+          f"(pass ms {tune})", file=sys.stderr, flush=True)
+    out = dict(workload=B["name"], instances=m, points=int(n.sum()), fp32_bytes=nbytes, rows_per_group=rpg,
+               autotune_pass_ms={str(k): round(v, 4) for k, v in tune.items()})
+    for storage in (None, "bf16"):
+        key = storage or "f32"
+        with scp.MWUBatch(pts, n, d, flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP, storage=storage,
+                          rows_per_group=rpg) as b:
+            b.step(b.D, [20000] * m, max(warmup, 32), reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = b.step(b.D, [20000] * m, steps)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            assert all(i["outcome_name"] == "running" for i in info)
+            mp, mi = b.time_iters(20)
+        nb = nbytes // (2 if storage else 1)
+        out[key] = dict(batched_iters_per_s=round(1.0 / dt, 1), instance_iters_per_s=round(m / dt, 0),
+                        ms_per_batched_iter=round(dt * 1e3, 4), pass_ms=round(mp, 4), bytes_per_pass=nb,
+                        pass_GBs=round(nb / (mp * 1e-3) / 1e9, 1),
+                        pass_hbm_frac=round(nb / (mp * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+        print(f"# batched {key}: {out[key]}", file=sys.stderr, flush=True)
+    for storage in solve_storages:
+        key = storage or "f32"
+        with scp.MWUBatch(pts, n, d, eps=1e-3, storage=storage, rows_per_group=rpg) as b:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            code, res = b.solve()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        its = np.array([r["iters"] for r in res])
+        out[key]["solve"] = dict(seconds=round(dt, 2), solves_per_s=round(m / dt, 2),
+                                 converged=int(sum(r["converged"] for r in res)), code=code,
+                                 iters_mean=round(float(its.mean()), 1), iters_max=int(its.max()),
+                                 instance_iters_per_s=round(float(its.sum()) / dt, 0))
+        print(f"# batched solve {key}: {out[key]['solve']}", file=sys.stderr, flush=True)
+    del pts
+    torch.cuda.empty_cache()
+    return out
+
+
 def _oracle_iters(V64, threads, warm, timed, budget_s):
     """Median seconds per FP64 oracle iteration of the benchmarked alpha-test."""
     from threadpoolctl import threadpool_limits
@@ -178,6 +245,10 @@ def main(argv=None):
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-fp8", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--batch-solve", default="f32",
+                    help="storage types of the batched eps solves: comma list of f32, bf16, or none")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain copy of the matrix (counter calibration)")
     a = ap.parse_args(argv)
@@ -199,12 +270,16 @@ def main(argv=None):
     print(f"# data ready: {w['n']} x {w['d']} float32, alpha {alpha:.4f}", file=sys.stderr, flush=True)
     f32 = measure(X, None, a.steps, a.warmup, alpha)
     print(f"# f32: {f32}", file=sys.stderr, flush=True)
-    bf16 = None if a.no_bf16 else measure(X, "bf16", a.steps, a.warmup, alpha)
-    if bf16:
-        print(f"# bf16: {bf16}", file=sys.stderr, flush=True)
+    # narrow storage types: bytes one pass must read (FP8: codes and row scales)
+    narrow = {k: v for k, v in (("bf16", w["n"] * w["d"] * 2), ("fp8", w["n"] * (w["d"] + 4)))
+              if not getattr(a, "no_" + k)}
+    res = {}
+    for k in narrow:
+        res[k] = measure(X, k, a.steps, a.warmup, alpha)
+        print(f"# {k}: {res[k]}", file=sys.stderr, flush=True)
     rref = dict(f32=read_reference(w["n"] * w["d"] * 4, X))
-    if bf16:
-        rref["bf16"] = read_reference(w["n"] * w["d"] * 2)
+    for k, nb in narrow.items():
+        rref[k] = read_reference(nb)
     print(f"# read reference: {rref}", file=sys.stderr, flush=True)
     probe = copy_probe(X) if a.copy_probe else None
     if probe:
@@ -213,12 +288,15 @@ def main(argv=None):
     if not a.no_solve:
         sol["f32"] = solve(X, None)
         print(f"# solve f32: {sol['f32']}", file=sys.stderr, flush=True)
-        if not a.no_bf16:
-            sol["bf16"] = solve(X, "bf16")
-            print(f"# solve bf16: {sol['bf16']}", file=sys.stderr, flush=True)
-            sol["bf16_over_f32_solve_rate"] = sol["bf16"]["solves_per_s"] / sol["f32"]["solves_per_s"]
+        for k in narrow:
+            sol[k] = solve(X, k)
+            sol[k]["radius_rel_to_f32"] = sol[k]["radius"] / sol["f32"]["radius"] - 1.0
+            print(f"# solve {k}: {sol[k]}", file=sys.stderr, flush=True)
+            sol[f"{k}_over_f32_solve_rate"] = sol[k]["solves_per_s"] / sol["f32"]["solves_per_s"]
     del X
     torch.cuda.empty_cache()
+    bsolve = [] if a.batch_solve == "none" else [None if s == "f32" else s for s in a.batch_solve.split(",")]
+    batch = None if a.no_batch else batched(min(a.steps, 320), a.warmup, bsolve)
     cpu = None if a.no_cpu else cpu_baseline(V)
     if cpu:
         print(f"# cpu: {cpu}", file=sys.stderr, flush=True)
@@ -237,21 +315,23 @@ def main(argv=None):
                 config=dict(workload=w["name"], n=w["n"], d=w["d"], storage="f32",
                             points="N(0,I), 1% rows x5, seed 0", problem="SES"),
                 roofline=roof, cpu_baseline=cpu)
-    if bf16:
-        b_bytes = w["n"] * w["d"] * 2
-        b_ach = b_bytes / (bf16["kernel_ms"] * 1e-3) / 1e9
-        line["bf16"] = dict(value=round(1e3 / bf16["ms_per_step"], 1), unit="iters/s",
-                            ms_per_step=round(bf16["ms_per_step"], 5),
-                            speedup_vs_f32=round(f32["ms_per_step"] / bf16["ms_per_step"], 3),
-                            roofline=dict(bound="hbm", achieved=round(b_ach, 1), peak=HBM_PEAK_GBS,
-                                          unit="GB/s", frac=round(b_ach / HBM_PEAK_GBS, 4),
-                                          traffic=traffic_for("bf16"),
-                                          kernel="ses_pass_kernel<uint16_t,8,4,false,0>",
-                                          kernel_ms=round(bf16["kernel_ms"], 5), bytes_per_launch=b_bytes,
-                                          read_reference_GBs=rref["bf16"]["GBs"],
-                                          frac_of_read_reference=round(b_ach / rref["bf16"]["GBs"], 4)))
+    kname = dict(bf16="ses_pass_kernel<uint16_t,8,4,false,0>", fp8="ses_pass_kernel<uint8_t,8,4,false,0>")
+    for k, nb in narrow.items():
+        r = res[k]
+        b_ach = nb / (r["kernel_ms"] * 1e-3) / 1e9
+        line[k] = dict(value=round(1e3 / r["ms_per_step"], 1), unit="iters/s",
+                       ms_per_step=round(r["ms_per_step"], 5),
+                       speedup_vs_f32=round(f32["ms_per_step"] / r["ms_per_step"], 3),
+                       roofline=dict(bound="hbm", achieved=round(b_ach, 1), peak=HBM_PEAK_GBS,
+                                     unit="GB/s", frac=round(b_ach / HBM_PEAK_GBS, 4),
+                                     traffic=traffic_for(k), kernel=kname[k],
+                                     kernel_ms=round(r["kernel_ms"], 5), bytes_per_launch=nb,
+                                     read_reference_GBs=rref[k]["GBs"],
+                                     frac_of_read_reference=round(b_ach / rref[k]["GBs"], 4)))
     if sol:
         line["solve"] = sol
+    if batch:
+        line["batched"] = batch
     if probe:
         line["copy_reference"] = probe
     print(json.dumps(line), flush=True)
