@@ -99,16 +99,17 @@ def measure(X, storage, steps, warmup, alpha, T=20000):
 
 
 def copy_probe(X, reps=10):
-    """A plain copy of the same 400 MB (torch copy_): the kernel of known size
-    whose rocprofv3 FETCH_SIZE / WRITE_SIZE readings scale the counters."""
+    """A plain elementwise copy of the same 400 MB (torch.neg into a second
+    tensor, a kernel of its own name): the kernel of known size whose
+    rocprofv3 FETCH_SIZE / WRITE_SIZE readings scale the counters."""
     import torch
     Y = torch.empty_like(X)
-    Y.copy_(X)
+    torch.neg(X, out=Y)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        Y.copy_(X)
+        torch.neg(X, out=Y)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -153,18 +154,18 @@ def batched(steps, warmup, solve_storages):
     import paper_2405_09157_amd as scp
     B = BATCH
     n, d = synth.ses_batch_sizes(B["instances"], B["n_lo"], B["n_hi"], B["dims"], B["seed"])
-    pts = synth.ses_batch_points_device(n, d, B["seed"])
+    pts, off = synth.ses_batch_points_device(n, d, B["seed"])
     torch.cuda.synchronize()
     m = len(n)
     nbytes = int((n * d).sum()) * 4
-    rpg, tune = scp.autotune_rows_per_group(pts, n, d)
+    rpg, tune = scp.autotune_rows_per_group(pts, n, d, off)
     print(f"# batched: {m} instances, {int(n.sum())} points, {nbytes / 1e9:.2f} GB; rows per group {rpg} "
           f"(pass ms {tune})", file=sys.stderr, flush=True)
     out = dict(workload=B["name"], instances=m, points=int(n.sum()), fp32_bytes=nbytes, rows_per_group=rpg,
                autotune_pass_ms={str(k): round(v, 4) for k, v in tune.items()})
     for storage in (None, "bf16"):
         key = storage or "f32"
-        with scp.MWUBatch(pts, n, d, flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP, storage=storage,
+        with scp.MWUBatch(pts, n, d, off, flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP, storage=storage,
                           rows_per_group=rpg) as b:
             b.step(b.D, [20000] * m, max(warmup, 32), reset=True)
             torch.cuda.synchronize()
@@ -182,7 +183,7 @@ def batched(steps, warmup, solve_storages):
         print(f"# batched {key}: {out[key]}", file=sys.stderr, flush=True)
     for storage in solve_storages:
         key = storage or "f32"
-        with scp.MWUBatch(pts, n, d, eps=1e-3, storage=storage, rows_per_group=rpg) as b:
+        with scp.MWUBatch(pts, n, d, off, eps=1e-3, storage=storage, rows_per_group=rpg) as b:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             code, res = b.solve()

@@ -224,15 +224,15 @@ class MWUBatch:
         return L.scp_mwu_batch_time_iters(self.b, int(k))
 
 
-def autotune_rows_per_group(points, n, d, candidates=(2048, 4096, 8192, 16384, 32768), iters: int = 10,
-                            storage: str | None = None):
+def autotune_rows_per_group(points, n, d, offset=None, candidates=(2048, 4096, 8192, 16384, 32768),
+                            iters: int = 10, storage: str | None = None):
     """Pick the workgroup share (rows per workgroup) of a batch's streaming
     pass by timing `iters` iterations of a running test (alpha = D, the
     points' own enclosing radius) for each candidate with the library's HIP
     event timer.  Returns (best, {candidate: pass ms})."""
     times = {}
     for rpg in candidates:
-        with MWUBatch(points, n, d, flags=L.SCP_MWU_FLAG_NO_EARLY_STOP, storage=storage,
+        with MWUBatch(points, n, d, offset, flags=L.SCP_MWU_FLAG_NO_EARLY_STOP, storage=storage,
                       rows_per_group=int(rpg)) as b:
             b.step(b.D, [20000] * b.m, 2, reset=True)
             times[int(rpg)] = b.time_iters(iters)[0]

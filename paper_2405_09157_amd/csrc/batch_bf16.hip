@@ -14,6 +14,10 @@ hipError_t launch_init_batch_bf16(int count, const PassArgs *args, const int32_t
                                 hipStream_t s) {
   return launch_init_batch_typed<uint16_t>(count, args, list, params, s);
 }
+hipError_t launch_rows_batch_bf16(int dm, int vec, int ntiles, const PassArgs *args, const BatchTile *tiles,
+                               hipStream_t s) {
+  return launch_rows_batch_typed<uint16_t>(dm, vec, ntiles, args, tiles, s);
+}
 hipError_t launch_diameter_batch_bf16(int m, const PassArgs *args, double *D, hipStream_t s) {
   return launch_diameter_batch_typed<uint16_t>(m, args, D, s);
 }

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -79,6 +80,7 @@ struct SesSearch {
 
 struct Inst {
   int64_t n = 0, d = 0, offset = 0;
+  int rows = 0;  // 1: row-per-lane layout (d <= 16), epl = columns held per lane
   int epl = 1, vec = 1, vg = 1;
   int64_t rec_off = 0, vec_off = 0;
   double D = 0, rho = 0, R = 0;
@@ -90,7 +92,7 @@ struct Inst {
 };
 
 struct Layout {
-  int epl, vec;
+  int rows, epl, vec;
   BatchTile *tiles;  // device
   int ntiles;
 };
@@ -137,6 +139,9 @@ struct scp_mwu_batch {
 namespace {
 
 hipError_t pass_launch(scp_mwu_batch *b, const Layout &l, hipStream_t s) {
+  if (l.rows)
+    return b->dtype == kBF16 ? launch_rows_batch_bf16(l.epl, l.vec, l.ntiles, b->args, l.tiles, s)
+                             : launch_rows_batch_f32(l.epl, l.vec, l.ntiles, b->args, l.tiles, s);
   return b->dtype == kBF16 ? launch_pass_batch_bf16(l.epl, l.vec, l.ntiles, b->args, l.tiles, s)
                            : launch_pass_batch_f32(l.epl, l.vec, l.ntiles, b->args, l.tiles, s);
 }
@@ -358,14 +363,22 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
 
   // instance layout: column layout, workgroup shares, record and vector blocks
   b->inst.resize(m);
-  std::map<std::pair<int, int>, std::vector<int>> groups;
+  std::map<std::tuple<int, int, int>, std::vector<int>> groups;
   int64_t rec_total = 0;
   for (int k = 0; k < m; ++k) {
     Inst &I = b->inst[k];
     I.n = desc->n[k];
     I.d = desc->d[k];
     I.offset = desc->offset[k];
-    while (kG * I.epl < I.d) I.epl *= 2;
+    // d <= 16: one lane per row, epl = columns held per lane (2, 4, 8, 16);
+    // otherwise 16 lanes per row with epl columns each
+    I.rows = I.d <= 16 ? 1 : 0;
+    if (I.rows) {
+      I.epl = 2;
+      while (I.epl < I.d) I.epl *= 2;
+    } else {
+      while (kG * I.epl < I.d) I.epl *= 2;
+    }
     const int vf = std::min<int>(I.epl, (int)(16 / es));
     const uintptr_t base = (uintptr_t)b->X + (uintptr_t)(I.offset * es);
     for (int v : {vf, vf >= 4 ? vf / 2 : 1, 1}) {
@@ -383,7 +396,7 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
     I.r = 2 * (I.n - 1);
     I.t_cap = b->t_cap > 0 ? b->t_cap
                            : std::min<int64_t>((int64_t)std::ceil(std::log((double)I.n) / (b->eps * b->eps)), 20000);
-    groups[{I.epl, I.vec}].push_back(k);
+    groups[{I.rows, I.epl, I.vec}].push_back(k);
   }
   if (hipMalloc(&b->args, sizeof(PassArgs) * m) != hipSuccess ||
       hipMalloc(&b->st, sizeof(DevState) * m) != hipSuccess ||
@@ -425,7 +438,7 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
     std::vector<BatchTile> tiles;
     for (int k : kv.second)
       for (int v = 0; v < b->inst[k].vg; ++v) tiles.push_back(BatchTile{k, v, b->inst[k].vg, 0});
-    Layout l{kv.first.first, kv.first.second, nullptr, (int)tiles.size()};
+    Layout l{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), nullptr, (int)tiles.size()};
     if (hipMalloc(&l.tiles, sizeof(BatchTile) * tiles.size()) != hipSuccess) return fail(SCP_MWU_E_NOMEM, "tiles");
     b->layouts.push_back(l);
     if (hipMemcpy(l.tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)

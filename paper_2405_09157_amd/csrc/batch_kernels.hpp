@@ -21,6 +21,141 @@ void ses_pass_batch_kernel(const PassArgs *__restrict__ args, const BatchTile *_
   ses_pass_body<T, EPL, VEC, false, kPrefetchNone>(a, tl.vb, tl.vg);
 }
 
+// Row-per-lane SES pass for instances with d <= DM <= 16 columns: every lane
+// owns RL whole rows of a batch (a wave batch is 64 * RL rows), so a row's
+// squared distance is summed inside the lane and the binary64 chains of the
+// per-row phase (sqrt, exp, expm1, division) of RL rows run side by side; the
+// weighted sums are kept per lane and reduced once per workgroup.  Point sets
+// only (no radii).  Arithmetic is binary64 per element for every storage
+// type; with BF16 storage the weighted sums are taken about fl32(ubar), the
+// origin its epilogue expects.  The record has the layout of ses_pass_body's.
+template <typename T, int DM, int VEC>
+__device__ __forceinline__ void ses_rows_body(const PassArgs &a, int vb, int vg) {
+  static_assert(DM % VEC == 0 && DM <= 16, "row layout");
+  constexpr int RL = DM <= 4 ? 4 : 2;
+  constexpr int NQ = DM / VEC;
+  constexpr int B = kWave * RL;
+  constexpr bool M32 = sizeof(T) <= 2;
+  __shared__ double s_vec[kPassWaves][DM];
+  __shared__ double s_sc[kPassWaves][8];
+
+  DevState *st = a.st;
+  const int32_t status0 = __builtin_amdgcn_readfirstlane(st->status);  // uniform over the instance
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t n = a.n, ld = a.ld;
+  const int d = (int)a.d;
+  const T *__restrict__ X = reinterpret_cast<const T *>(a.X);
+  const double kappa = st->kscale * (double)st->t;
+  const double Gb = st->shift_bound;
+  const int64_t v1 = a.v1;
+  double ub[DM], org[DM], acc[DM];
+#pragma unroll
+  for (int c = 0; c < DM; ++c) {
+    ub[c] = c < d ? a.vec[kVecMean * d + c] : 0.0;
+    org[c] = M32 ? (double)(float)ub[c] : 0.0;
+    acc[c] = 0.0;
+  }
+  double asum = 0.0, bsum = 0.0, esum = 0.0, gmax = -INFINITY, fall = -INFINITY;
+
+  const int64_t nb = (n + B - 1) / B;
+  const int64_t GW = (int64_t)vg * kPassWaves;
+  // byte offsets of lane row j's column chunks within a batch; chunks past
+  // column d get an offset beyond any batch (read as zero)
+  int32_t voff[RL][NQ];
+#pragma unroll
+  for (int j = 0; j < RL; ++j)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      voff[j][q] = q * VEC < d ? (int32_t)(((int64_t)(lane + kWave * j) * ld + q * VEC) * (int64_t)sizeof(T))
+                               : kOffInvalid;
+  const int64_t b0 = (int64_t)vb * kPassWaves + wave;
+  __syncthreads();
+  for (int64_t b = b0; b < nb; b += GW) {
+    const int64_t r0 = b * B;
+    const int64_t rows = n - r0 < B ? n - r0 : B;
+    const __amdgpu_buffer_rsrc_t rs = rows_rsrc<T>(X, r0, rows, ld, d);
+    VecT<T, VEC> x[RL][NQ];
+#pragma unroll
+    for (int j = 0; j < RL; ++j)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) x[j][q] = buf_load<T, VEC>(rs, voff[j][q], 0);
+    // the first batch's loads go out before the state word is waited on
+    if (b == b0 && status0 != kRunning) return;
+#pragma unroll
+    for (int j = 0; j < RL; ++j) {
+      double dsq = 0.0;
+#pragma unroll
+      for (int c = 0; c < DM; ++c) {
+        const double df = to_f64(x[j][c / VEC].v[c % VEC]) - ub[c];
+        dsq = fma(df, df, dsq);
+      }
+      const int64_t row = r0 + lane + kWave * j;
+      const bool valid = row < n;
+      const bool incl = valid && row != v1;
+      // the cone exponential of ses_pass_body for a point (gamma_i = 0)
+      const double di = sqrt(dsq);
+      const double ep = exp(kappa * (di - Gb));
+      const double om = -expm1(-2.0 * kappa * di);
+      double aw = di > 0.0 ? ep * om / di : 2.0 * kappa * ep;
+      double bw = ep * (2.0 - om);
+      double ew = ep * om * di;
+      if (!incl) aw = bw = ew = 0.0;
+      asum += aw;
+      bsum += bw;
+      esum += ew;
+      if (incl) gmax = fmax(gmax, di);
+      if (valid) fall = fmax(fall, di);
+#pragma unroll
+      for (int c = 0; c < DM; ++c) acc[c] = fma(aw, to_f64(x[j][c / VEC].v[c % VEC]) - org[c], acc[c]);
+    }
+  }
+  if (status0 != kRunning) return;
+
+  // ---- workgroup record: sums, maxima
+#pragma unroll
+  for (int c = 0; c < DM; ++c) {
+    const double v = wave_sum(acc[c]);
+    if (lane == 0) s_vec[wave][c] = v;
+  }
+  asum = wave_sum(asum);
+  bsum = wave_sum(bsum);
+  esum = wave_sum(esum);
+  gmax = wave_max(gmax);
+  fall = wave_max(fall);
+  if (lane == 0) {
+    s_sc[wave][0] = bsum;
+    s_sc[wave][1] = esum;
+    s_sc[wave][2] = 0.0;  // sum gamma_i b_i: no radii
+    s_sc[wave][3] = 0.0;  // no certificate
+    s_sc[wave][4] = asum;
+    s_sc[wave][5] = gmax;
+    s_sc[wave][6] = fall;
+  }
+  __syncthreads();
+  double *rec = a.partials + (int64_t)vb * rec_width(d);
+  const int dp = rec_dp(d);
+  if (tid < d) rec[tid] = sum_waves(s_vec, tid);
+  if (tid < 8) {
+    double v;
+    if (tid < 5)
+      v = sum_waves(s_sc, tid);
+    else if (tid < 7)
+      v = max_waves(s_sc, tid);
+    else
+      v = -INFINITY;
+    rec[dp + tid] = v;
+  }
+}
+
+template <typename T, int DM, int VEC>
+__global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
+void ses_rows_batch_kernel(const PassArgs *__restrict__ args, const BatchTile *__restrict__ tiles) {
+  const BatchTile tl = tiles[blockIdx.x];
+  const PassArgs a = args[tl.inst];
+  ses_rows_body<T, DM, VEC>(a, tl.vb, tl.vg);
+}
+
 // Epilogue of every instance (workgroup k sums instance k's nrec[k] records;
 // an instance whose test has ended only reads its state).
 template <typename T>
@@ -105,6 +240,41 @@ hipError_t launch_pass_batch_typed(int epl, int vec, int ntiles, const PassArgs 
     case 8: return launch_pass_batch_v<T, 8>(vec, ntiles, args, tiles, s);
     case 16: return launch_pass_batch_v<T, 16>(vec, ntiles, args, tiles, s);
     case 32: return launch_pass_batch_v<T, 32>(vec, ntiles, args, tiles, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int DM>
+hipError_t launch_rows_batch_v(int vec, int ntiles, const PassArgs *args, const BatchTile *tiles, hipStream_t s) {
+  constexpr int VF = (16 / (int)sizeof(T)) < DM ? (16 / (int)sizeof(T)) : DM;
+  if (vec == VF) {
+    hipLaunchKernelGGL((ses_rows_batch_kernel<T, DM, VF>), dim3(ntiles), dim3(kPassBlock), 0, s, args, tiles);
+    return hipGetLastError();
+  }
+  if constexpr (VF >= 2) {
+    if (vec == VF / 2) {
+      hipLaunchKernelGGL((ses_rows_batch_kernel<T, DM, VF / 2>), dim3(ntiles), dim3(kPassBlock), 0, s, args, tiles);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (VF > 2) {
+    if (vec == 1) {
+      hipLaunchKernelGGL((ses_rows_batch_kernel<T, DM, 1>), dim3(ntiles), dim3(kPassBlock), 0, s, args, tiles);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+// Row-per-lane layout: dm = columns held per lane (2, 4, 8 or 16 >= d).
+template <typename T>
+hipError_t launch_rows_batch_typed(int dm, int vec, int ntiles, const PassArgs *args, const BatchTile *tiles,
+                                   hipStream_t s) {
+  switch (dm) {
+    case 2: return launch_rows_batch_v<T, 2>(vec, ntiles, args, tiles, s);
+    case 4: return launch_rows_batch_v<T, 4>(vec, ntiles, args, tiles, s);
+    case 8: return launch_rows_batch_v<T, 8>(vec, ntiles, args, tiles, s);
+    case 16: return launch_rows_batch_v<T, 16>(vec, ntiles, args, tiles, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -160,7 +160,9 @@ struct BatchTile {
   hipError_t launch_epilogue_batch_##name(int m, const PassArgs *args, const int32_t *nrec, hipStream_t s); \
   hipError_t launch_init_batch_##name(int count, const PassArgs *args, const int32_t *list,              \
                                       const InitParams *params, hipStream_t s);                          \
-  hipError_t launch_diameter_batch_##name(int m, const PassArgs *args, double *D, hipStream_t s);
+  hipError_t launch_diameter_batch_##name(int m, const PassArgs *args, double *D, hipStream_t s);         \
+  hipError_t launch_rows_batch_##name(int dm, int vec, int ntiles, const PassArgs *args,                  \
+                                      const BatchTile *tiles, hipStream_t s);
 SCPMWU_DECLARE_BATCH(f32)
 SCPMWU_DECLARE_BATCH(bf16)
 #undef SCPMWU_DECLARE_BATCH

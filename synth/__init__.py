@@ -119,29 +119,40 @@ def ses_batch_sizes(instances: int, n_lo: int, n_hi: int, dims, seed: int):
     return n, d
 
 
-def ses_batch_points(n, d, seed: int) -> np.ndarray:
-    """Every instance's points, back to back as one float32 array: instance k
-    is ses_ellipsoid(n[k], d[k], seed + 1 + k) rounded to float32."""
-    total = int(np.sum(np.asarray(n, dtype=np.int64) * np.asarray(d, dtype=np.int64)))
-    out = np.empty(total, dtype=np.float32)
-    o = 0
+def ses_batch_offsets(n, d, align: int = 8):
+    """Element offsets of the instances in one buffer, each instance's rows
+    dense and starting at a multiple of `align` elements (so that vector
+    loads of every instance are aligned); returns (offsets, total length)."""
+    off, o = [], 0
+    for nk, dk in zip(n, d):
+        o = (o + align - 1) // align * align
+        off.append(o)
+        o += int(nk) * int(dk)
+    return np.asarray(off, dtype=np.int64), o
+
+
+def ses_batch_points(n, d, seed: int, align: int = 8):
+    """Every instance's points in one float32 array at ses_batch_offsets:
+    instance k is ses_ellipsoid(n[k], d[k], seed + 1 + k) rounded to float32
+    (the gaps hold zeros).  Returns (points, offsets)."""
+    off, total = ses_batch_offsets(n, d, align)
+    out = np.zeros(total, dtype=np.float32)
     for k, (nk, dk) in enumerate(zip(n, d)):
-        out[o:o + nk * dk] = ses_ellipsoid(int(nk), int(dk), seed + 1 + k).astype(np.float32).ravel()
-        o += nk * dk
-    return out
+        out[off[k]:off[k] + nk * dk] = ses_ellipsoid(int(nk), int(dk), seed + 1 + k).astype(np.float32).ravel()
+    return out, off
 
 
-def ses_batch_points_device(n, d, seed: int, device="cuda"):
-    """The same recipe as ses_batch_points, drawn on the device with torch's
-    generator (a different random stream; for inputs too large to draw on the
-    host in reasonable time): returns one float32 device tensor, instances
-    back to back."""
+def ses_batch_points_device(n, d, seed: int, device="cuda", align: int = 8):
+    """The same recipe and layout as ses_batch_points, drawn on the device
+    with torch's generator (a different random stream; for inputs too large
+    to draw on the host in reasonable time).  Returns (float32 device tensor,
+    offsets)."""
     import torch
-    total = int(np.sum(np.asarray(n, dtype=np.int64) * np.asarray(d, dtype=np.int64)))
-    out = torch.empty(total, dtype=torch.float32, device=device)
+    off, total = ses_batch_offsets(n, d, align)
+    out = torch.zeros(total, dtype=torch.float32, device=device)
     gen = torch.Generator(device=device)
-    o = 0
     for k, (nk, dk) in enumerate(zip(n, d)):
+        o = int(off[k])
         nk, dk = int(nk), int(dk)
         g = rng(seed + 1 + k)
         q, r = np.linalg.qr(g.standard_normal(size=(dk, dk)))
@@ -155,8 +166,7 @@ def ses_batch_points_device(n, d, seed: int, device="cuda"):
         z *= torch.rand(nk, 1, generator=gen, device=device) ** (1.0 / dk)
         y = z @ A + torch.from_numpy(c.astype(np.float32)).to(device)
         out[o:o + nk * dk] = y.reshape(-1)
-        o += nk * dk
-    return out
+    return out, off
 
 
 def bf16_round(x32: np.ndarray) -> np.ndarray:
