@@ -234,6 +234,7 @@ class SolveResult:
     iters: int
     steps: list
     converged: bool
+    passes: int = 0             # k-way search: sum over rounds of the longest test
 
 
 def solve(V, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Optional[int] = None,
@@ -283,3 +284,63 @@ def solve(V, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Optional[int] = 
         converged = U - L <= eps * L
     return SolveResult(radius=Uc, center=center, lower=Lc, upper=Uc, L=L, U=U,
                        iters=iters, steps=steps, converged=converged)
+
+
+def solve_kway(V, k: int, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Optional[int] = None,
+               delta: float = 1e-4, patience: int = 10, tau: float = 1e-12,
+               max_iters: Optional[int] = None, max_rounds: int = 200,
+               theory: bool = False) -> SolveResult:
+    """k-way alpha search (Section 3 names other searching methods besides
+    the one it spells out; reading K1): each round cuts [L, U] into 2k + 1
+    equal parts and runs the k alpha-feasibility tests at
+    alpha_i = L + (2i - 1)(U - L)/(2k + 1) with eps_i = (U - L)/((2k + 1) alpha_i),
+    so that (1 + eps_i) alpha_i = L + 2i (U - L)/(2k + 1).  After the round,
+    every separated test raises L to its alpha (a certificate); every other
+    test whose alpha is not below the new L lowers U to its conclusion (f_best
+    when f beat alpha, else L + 2i (U - L)/(2k + 1)); every f seen tightens U and
+    the certified radius.  k = 1 is solve()'s search.  `passes` counts the
+    iterations of the rounds when the k tests advance together (the longest
+    test of each round)."""
+    P = setup(V, gamma, v1)
+    n = P.V.shape[0]
+    if t_cap is None:
+        t_cap = min(int(math.ceil(math.log(n) / eps ** 2)), 20000)
+    L, U = P.D / 2.0, P.D
+    Lc, Uc = L, U
+    center = P.V[v1].copy()
+    iters = passes = 0
+    steps = []
+    converged = False
+    g = 2 * k + 1
+    for _ in range(max_rounds):
+        if U - L <= eps * L:
+            converged = True
+            break
+        if max_iters is not None and iters >= max_iters:
+            break
+        round_ = []
+        for i in range(1, k + 1):
+            alpha = L + (2 * i - 1) * (U - L) / g
+            eps_i = (U - L) / (g * alpha)
+            T = theory_T(P, eps_i, alpha) if theory else min(theory_T(P, eps_i, alpha), t_cap)
+            T = max(T, min_T(P))
+            eta = math.sqrt(math.log(P.r) / T)
+            r = ftp(P, alpha, T, eta, delta, patience, tau, early_stop=not theory)
+            round_.append((alpha, L + 2 * i * (U - L) / g, T, r))
+            steps.append((alpha, T, r.outcome, r.t, r.f_best))
+        iters += sum(r.t for _, _, _, r in round_)
+        passes += max(r.t for _, _, _, r in round_)
+        for alpha, concl, T, r in round_:
+            if r.f_best < Uc:
+                Uc, center = r.f_best, r.ubar_best.copy()
+        L_new = max([L] + [a for a, _, _, r in round_ if r.outcome == SEPARATED])
+        Lc = max(Lc, L_new)
+        U_new = min(U, Uc)
+        for alpha, concl, T, r in round_:
+            if r.outcome != SEPARATED and alpha >= L_new:
+                U_new = min(U_new, r.f_best if r.outcome == BEAT else concl)
+        L, U = L_new, U_new
+    else:
+        converged = U - L <= eps * L
+    return SolveResult(radius=Uc, center=center, lower=Lc, upper=Uc, L=L, U=U, iters=iters,
+                       steps=steps, converged=converged, passes=passes)

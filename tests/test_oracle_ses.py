@@ -175,3 +175,41 @@ def test_step_matches_ftp_trajectory():
         assert st["value"] == r.values[t - 1]
         S = st["S"]
         assert ses.monitor(P, st["ubar"]) == r.f_traj[t - 1]
+
+
+def test_kway_search_with_one_test_is_the_paper_search():
+    V = synth.ses_uniform(300, 3, 21)
+    a = ses.solve(V, eps=1e-2)
+    b = ses.solve_kway(V, 1, eps=1e-2)
+    assert [s[:4] for s in a.steps] == [s[:4] for s in b.steps]
+    assert a.iters == b.iters == b.passes
+    assert a.radius == b.radius and a.lower == b.lower and np.array_equal(a.center, b.center)
+    assert (a.L, a.U) == (b.L, b.U)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("k", [2, 3])
+def test_kway_theory_solve_within_eps_of_exact(k):
+    V = synth.ses_uniform(8, 2, 12)
+    c, R = exact.brute_ses(V)
+    eps = 0.1
+    r = ses.solve_kway(V, k, eps=eps, theory=True)
+    assert r.converged
+    assert R <= r.radius * (1 + 1e-12) and r.radius <= (1 + eps) * R
+    assert r.lower <= R * (1 + 1e-12)
+    assert certify.ses_upper(V, None, r.center) <= r.radius * (1 + 1e-12)
+    # each round's guesses split the interval into 2k + 1 equal parts
+    assert len(r.steps) % k == 0
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("k", [2, 4])
+def test_kway_practical_solve_brackets_exact(k):
+    V = synth.ses_uniform(400, 3, 3)
+    c, R = exact.welzl(V)
+    r = ses.solve_kway(V, k, eps=1e-3)
+    assert r.radius >= R * (1 - 1e-12)
+    assert r.lower <= R * (1 + 1e-12)
+    assert r.radius <= 1.02 * R
+    assert abs(certify.ses_upper(V, None, r.center) - r.radius) < 1e-12
+    assert r.passes <= r.iters
