@@ -174,9 +174,13 @@ typedef struct scp_mwu_result {
   double search_hi;
   double D;            /* SES: max_{i != v1} ||v1 - v_i|| + gamma1 + gamma_i;
                           SVM: max_i ||x_i|| */
-  int64_t iters;       /* MWU iterations (streaming passes) over all tests */
+  int64_t iters;       /* MWU iterations over all tests */
   int32_t tests;       /* alpha-feasibility tests run */
   int32_t converged;   /* 1 if the search met its stop rule */
+  int64_t passes;      /* streaming passes over the points: iters, except for
+                          the k-way search (scp_mwu_batch_solve_kway), whose k
+                          tests of a round share passes (sum over rounds of
+                          the longest test) */
 } scp_mwu_result;
 
 typedef struct scp_mwu_ctx scp_mwu_ctx;
@@ -347,6 +351,25 @@ int scp_mwu_batch_step(scp_mwu_batch *b, const double *alpha, const int64_t *T, 
  * E_NUMERIC.
  */
 int scp_mwu_batch_solve(scp_mwu_batch *b, scp_mwu_result *res, double *y);
+
+/*
+ * k-way alpha search on one point set (Section 3 allows other searching
+ * methods than the one it details).  The batch must hold k >= 1 instances
+ * that are the same point set (equal n, d and offset); they serve as the k
+ * test slots.  Each round cuts [L, U] into 2k + 1 equal parts and runs the k
+ * alpha-feasibility tests at alpha_i = L + (2i - 1)(U - L)/(2k + 1) with
+ * eps_i = (U - L)/((2k + 1) alpha_i) together (their workgroups interleaved
+ * by rows, so that the k reads of a row block coincide in the cache); after
+ * the round every separation raises L to its alpha, every other test whose
+ * alpha is not below the new L lowers U to f_best (f beat alpha) or to
+ * L + 2i(U - L)/(2k + 1), and every f seen tightens U and the certified
+ * radius.  k = 1 is the search of scp_mwu_solve.  res (host, one entry): as
+ * scp_mwu_solve, with passes = sum over rounds of the longest test; y (host,
+ * d + 1 doubles, may be NULL): centre then radius.  OK / STOPPED as
+ * scp_mwu_solve.  Errors: E_INVAL (instances not all the same point set,
+ * res NULL), E_HIP, E_NUMERIC.
+ */
+int scp_mwu_batch_solve_kway(scp_mwu_batch *b, scp_mwu_result *res, double *y);
 
 /*
  * Vectors of every instance's current test (host, sum of d_k doubles,

@@ -33,7 +33,7 @@ EXPORTS = ("scp_mwu_init", "scp_mwu_step", "scp_mwu_solve", "scp_mwu_backward",
            "scp_mwu_time_passes", "scp_mwu_read_reference", "scp_mwu_quantize_fp8",
            "scp_mwu_batch_init", "scp_mwu_batch_step", "scp_mwu_batch_solve", "scp_mwu_batch_get_vector",
            "scp_mwu_batch_get_D", "scp_mwu_batch_time_iters", "scp_mwu_batch_destroy",
-           "scp_mwu_batch_last_error")
+           "scp_mwu_batch_last_error", "scp_mwu_batch_solve_kway")
 
 
 class scp_mwu_desc(ctypes.Structure):
@@ -91,6 +91,7 @@ class scp_mwu_result(ctypes.Structure):
         ("iters", ctypes.c_int64),
         ("tests", ctypes.c_int32),
         ("converged", ctypes.c_int32),
+        ("passes", ctypes.c_int64),
     ]
 
 
@@ -149,6 +150,7 @@ def load() -> ctypes.CDLL:
         "scp_mwu_batch_init": (i32, [P(scp_mwu_batch_desc), P(vp)]),
         "scp_mwu_batch_step": (i32, [vp, P(f64), P(i64), i32, i32, P(scp_mwu_stepinfo)]),
         "scp_mwu_batch_solve": (i32, [vp, P(scp_mwu_result), P(f64)]),
+        "scp_mwu_batch_solve_kway": (i32, [vp, P(scp_mwu_result), P(f64)]),
         "scp_mwu_batch_get_vector": (i32, [vp, i32, P(f64)]),
         "scp_mwu_batch_get_D": (i32, [vp, P(f64)]),
         "scp_mwu_batch_time_iters": (i32, [vp, i32, P(f64), P(f64)]),
@@ -287,6 +289,13 @@ def scp_mwu_batch_solve(b, m: int, d_total: int):
     y = (ctypes.c_double * (d_total + m))()
     code = _check_batch(load().scp_mwu_batch_solve(b, res, y), b)
     return code, list(res), list(y)
+
+
+def scp_mwu_batch_solve_kway(b, d: int):
+    res = scp_mwu_result()
+    y = (ctypes.c_double * (d + 1))()
+    code = _check_batch(load().scp_mwu_batch_solve_kway(b, ctypes.byref(res), y), b)
+    return code, res, list(y)
 
 
 def scp_mwu_batch_get_vector(b, which: int, d_total: int):

@@ -216,6 +216,21 @@ class MWUBatch:
             out.append(o)
         return code, out
 
+    def solve_kway(self):
+        """k-way alpha search over one point set: the batch's k instances must
+        be that point set (see MWUBatch.kway)."""
+        code, res, y = L.scp_mwu_batch_solve_kway(self.b, self.d[0])
+        out = {f: getattr(res, f) for f, _ in L.scp_mwu_result._fields_}
+        out["code"], out["center"], out["radius"] = code, y[:-1], y[-1]
+        return out
+
+    @classmethod
+    def kway(cls, points, k: int, **kw):
+        """A batch of k test slots over one n x d point set (a 2-D float32
+        device tensor) for solve_kway."""
+        n, d = points.shape
+        return cls(points.reshape(-1), [n] * k, [d] * k, [0] * k, **kw)
+
     def vectors(self, which: int) -> list:
         return self._split(L.scp_mwu_batch_get_vector(self.b, which, self.d_total))
 

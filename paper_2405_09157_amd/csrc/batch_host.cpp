@@ -435,9 +435,15 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
       hipMemcpy(b->nrec, hn.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice) != hipSuccess)
     return fail(SCP_MWU_E_HIP, "instance table upload");
   for (auto &kv : groups) {
+    // tiles interleaved by share index: share v of every instance of the
+    // layout, then share v + 1, ...  Instances over the same rows (the
+    // k-way search) then read each row block at about the same time.
     std::vector<BatchTile> tiles;
-    for (int k : kv.second)
-      for (int v = 0; v < b->inst[k].vg; ++v) tiles.push_back(BatchTile{k, v, b->inst[k].vg, 0});
+    int vmax = 0;
+    for (int k : kv.second) vmax = std::max(vmax, b->inst[k].vg);
+    for (int v = 0; v < vmax; ++v)
+      for (int k : kv.second)
+        if (v < b->inst[k].vg) tiles.push_back(BatchTile{k, v, b->inst[k].vg, 0});
     Layout l{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), nullptr, (int)tiles.size()};
     if (hipMalloc(&l.tiles, sizeof(BatchTile) * tiles.size()) != hipSuccess) return fail(SCP_MWU_E_NOMEM, "tiles");
     b->layouts.push_back(l);
@@ -635,6 +641,7 @@ int scp_mwu_batch_solve(scp_mwu_batch *b, scp_mwu_result *res, double *y) {
     r.search_hi = s.U;
     r.D = b->inst[k].D;
     r.iters = s.iters;
+    r.passes = s.iters;
     r.tests = s.tests;
     r.converged = s.converged ? 1 : 0;
     all = all && s.converged;
@@ -645,6 +652,103 @@ int scp_mwu_batch_solve(scp_mwu_batch *b, scp_mwu_result *res, double *y) {
     }
   }
   return all ? SCP_MWU_OK : SCP_MWU_STOPPED;
+}
+
+int scp_mwu_batch_solve_kway(scp_mwu_batch *b, scp_mwu_result *res, double *y) {
+  if (!b) return SCP_MWU_E_INVAL;
+  if (!res) return b->fail(SCP_MWU_E_INVAL, "res is NULL");
+  const int k = b->m;
+  const Inst &I0 = b->inst[0];
+  for (const Inst &I : b->inst)
+    if (I.n != I0.n || I.d != I0.d || I.offset != I0.offset)
+      return b->fail(SCP_MWU_E_INVAL, "k-way search: the instances must be one point set");
+  const bool theory = (b->flags & SCP_MWU_FLAG_THEORY) != 0;
+  const bool early = !(b->flags & (SCP_MWU_FLAG_NO_EARLY_STOP | SCP_MWU_FLAG_THEORY));
+  const int64_t d = I0.d;
+  const double D = I0.D;
+  double L = D / 2.0, U = D, Lc = L, Uc = U;
+  std::vector<double> best((size_t)d), alpha(k), concl(k);
+  int64_t iters = 0, passes = 0;
+  int tests = 0, rc;
+  bool converged = false;
+  // the search starts from the sphere at v1 of radius D
+  for (int j = 0; j < k; ++j) {
+    b->h_list[j] = j;
+    b->h_params[j] = test_params(b, b->inst[j], 1.0, 1, false);
+  }
+  if ((rc = start_tests(b, k)) || (rc = read_vectors(b))) return rc;
+  std::memcpy(best.data(), b->h_vec + I0.vec_off + kVecBest * d, sizeof(double) * d);
+  int round = 0;
+  for (; round < 200; ++round) {
+    if (U - L <= b->eps * L) {
+      converged = true;
+      break;
+    }
+    if (b->max_iters > 0 && iters >= b->max_iters) break;
+    const double g = 2.0 * k + 1.0;
+    for (int i = 1; i <= k; ++i) {
+      const Inst &I = b->inst[i - 1];
+      alpha[i - 1] = L + (2.0 * i - 1.0) * (U - L) / g;
+      concl[i - 1] = L + 2.0 * i * (U - L) / g;
+      const double eps_i = (U - L) / (g * alpha[i - 1]);
+      int64_t T = theory ? theory_T(I, eps_i, alpha[i - 1]) : std::min(theory_T(I, eps_i, alpha[i - 1]), I.t_cap);
+      T = std::max<int64_t>(T, std::max<int64_t>(1, (int64_t)std::ceil(std::log((double)I.r))));
+      b->h_list[i - 1] = i - 1;
+      b->h_params[i - 1] = test_params(b, I, alpha[i - 1], T, early);
+    }
+    if ((rc = start_tests(b, k))) return rc;
+    while (true) {
+      if ((rc = run_iters(b, b->chunk))) return rc;
+      if (!any_running(b)) break;
+    }
+    bool need_vec = false;
+    int64_t longest = 0;
+    for (int j = 0; j < k; ++j) {
+      const DevState &s = b->h_st[j];
+      if (s.status == kNumeric) return b->fail(SCP_MWU_E_NUMERIC, "non-finite value in the iteration");
+      need_vec = need_vec || s.f_best < Uc;
+      iters += s.t_end;
+      longest = std::max<int64_t>(longest, s.t_end);
+      b->inst[j].active = false;
+    }
+    passes += longest;
+    tests += k;
+    if (need_vec && (rc = read_vectors(b))) return rc;
+    for (int j = 0; j < k; ++j) {
+      const DevState &s = b->h_st[j];
+      if (s.f_best < Uc) {
+        Uc = s.f_best;
+        std::memcpy(best.data(), b->h_vec + b->inst[j].vec_off + kVecBest * d, sizeof(double) * d);
+      }
+    }
+    double Ln = L;
+    for (int j = 0; j < k; ++j)
+      if (b->h_st[j].status == kSeparated) Ln = std::max(Ln, alpha[j]);
+    Lc = std::max(Lc, Ln);
+    double Un = std::min(U, Uc);
+    for (int j = 0; j < k; ++j) {
+      const DevState &s = b->h_st[j];
+      if (s.status != kSeparated && alpha[j] >= Ln) Un = std::min(Un, s.status == kBeat ? s.f_best : concl[j]);
+    }
+    L = Ln;
+    U = Un;
+  }
+  if (round == 200) converged = U - L <= b->eps * L;
+  res->value = Uc;
+  res->lower = Lc;
+  res->upper = Uc;
+  res->search_lo = L;
+  res->search_hi = U;
+  res->D = D;
+  res->iters = iters;
+  res->passes = passes;
+  res->tests = tests;
+  res->converged = converged ? 1 : 0;
+  if (y) {
+    std::memcpy(y, best.data(), sizeof(double) * d);
+    y[d] = Uc;
+  }
+  return converged ? SCP_MWU_OK : SCP_MWU_STOPPED;
 }
 
 }  // extern "C"

@@ -673,6 +673,7 @@ int scp_mwu_solve(scp_mwu_ctx *c, scp_mwu_result *res, double *y) {
   if (!converged) converged = (U - L <= c->eps * (ses ? L : U));
   res->D = c->D;
   res->iters = iters;
+  res->passes = iters;
   res->tests = tests;
   res->converged = converged ? 1 : 0;
   res->search_lo = L;

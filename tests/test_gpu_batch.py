@@ -24,9 +24,11 @@ SEP_SLACK = 5  # iterations per test by which a slow separation may move
 # The radius of a solve is the least f over tests of up to thousands of
 # iterations; summation order perturbs a trajectory at the rounding level and
 # the perturbation grows along a test, so which iteration attains the least f
-# (and its value) can differ slightly: results are compared at SOLVE_TOL, far
-# below the solve's eps, and the returned centre must realise its radius.
-SOLVE_TOL = 5e-5
+# (and its value) can differ.  Near OPT f fluctuates along a test at the 1e-4
+# level (the least f of the final tests of one oracle search spread by 7e-5),
+# so results are compared at SOLVE_TOL, 50x below the solves' eps = 1e-2, and
+# the returned centre must realise its radius exactly.
+SOLVE_TOL = 2e-4
 
 # (n, d): one and several workgroup shares, ragged last batches, every column
 # layout the batched config uses (d in {2, 3, 16, 64}) and a few others
@@ -189,3 +191,51 @@ def test_batch_invalid_descriptors():
     with pytest.raises(scp.ScpMwuError):
         b.step([1.0, -1.0], [10, 10], 1)
     b.close()
+
+
+# ------------------------------------------------------- k-way alpha search
+@pytest.mark.parametrize("n,d,seed,k", [(1500, 3, 500, 2), (1200, 16, 501, 3)])
+def test_kway_search_matches_oracle(n, d, seed, k):
+    """The k-way search (k tests per round sharing the passes) against the
+    oracle's k-way search on the same points: the same number of tests,
+    iterations and shared passes within SEP_SLACK per test, radius and lower
+    bound within SOLVE_TOL, and a centre that realises the radius."""
+    import torch
+    import paper_2405_09157_amd as scp
+    V = synth.ses_ellipsoid(n, d, seed).astype(np.float32)
+    V64 = V.astype(np.float64)
+    ref = oses.solve_kway(V64, k, eps=1e-2, t_cap=1500)
+    with scp.MWUBatch.kway(torch.from_numpy(V).cuda(), k, eps=1e-2, t_cap=1500, chunk=8) as b:
+        out = b.solve_kway()
+    assert out["code"] == scp.SCP_MWU_OK and out["converged"] == int(ref.converged)
+    assert out["tests"] == len(ref.steps)
+    assert abs(out["iters"] - ref.iters) <= SEP_SLACK * out["tests"], (out["iters"], ref.iters)
+    assert abs(out["passes"] - ref.passes) <= SEP_SLACK * out["tests"], (out["passes"], ref.passes)
+    far = np.max(np.linalg.norm(V64 - np.array(out["center"]), axis=1))
+    assert abs(far - out["radius"]) <= 1e-9 * out["radius"]
+    assert abs(out["radius"] - ref.radius) / ref.radius <= SOLVE_TOL
+    assert abs(out["lower"] - ref.lower) / ref.radius <= SOLVE_TOL
+
+
+def test_kway_search_with_one_slot_is_the_paper_search():
+    """k = 1 against the oracle's search of Section 3 (the k-way search with
+    one test per round is that search, pinned step for step on the CPU)."""
+    import torch
+    import paper_2405_09157_amd as scp
+    V = synth.ses_ellipsoid(2000, 3, 300).astype(np.float32)
+    ref = oses.solve(V.astype(np.float64), eps=1e-2, t_cap=1500)
+    with scp.MWUBatch.kway(torch.from_numpy(V).cuda(), 1, eps=1e-2, t_cap=1500) as b:
+        out = b.solve_kway()
+    assert out["tests"] == len(ref.steps) and out["passes"] == out["iters"]
+    assert abs(out["iters"] - ref.iters) <= SEP_SLACK * out["tests"]
+    assert abs(out["radius"] - ref.radius) / ref.radius <= SOLVE_TOL
+
+
+def test_kway_search_needs_one_point_set():
+    import torch
+    import paper_2405_09157_amd as scp
+    X = torch.from_numpy(np.random.default_rng(5).standard_normal(4000).astype(np.float32)).cuda()
+    with scp.MWUBatch(X, [100, 100], [3, 3], [0, 300]) as b:
+        with pytest.raises(scp.ScpMwuError) as e:
+            b.solve_kway()
+        assert e.value.code == scp.SCP_MWU_E_INVAL
