@@ -314,7 +314,9 @@ typedef struct scp_mwu_batch_desc {
                             checked between tests; 0 = unlimited */
   void *stream;          /* hipStream_t; NULL = the null stream */
   int32_t chunk;         /* iterations per graph launch; default 32 */
-  int32_t rows_per_group;/* rows per workgroup share of the pass; default 16384 */
+  int32_t rows_per_group;/* rows per workgroup share of the pass; 0 = about two
+                            workgroups per compute unit over all instances,
+                            within [1024, 16384] */
 } scp_mwu_batch_desc;
 
 typedef struct scp_mwu_batch scp_mwu_batch;

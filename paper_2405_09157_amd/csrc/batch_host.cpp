@@ -347,7 +347,19 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
   b->patience = desc->patience > 0 ? desc->patience : 10;
   b->flags = desc->flags;
   b->chunk = desc->chunk > 0 ? desc->chunk : 32;
-  b->rows_per_group = desc->rows_per_group > 0 ? desc->rows_per_group : 16384;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return fail(SCP_MWU_E_HIP, "no HIP device");
+  if (desc->rows_per_group > 0) {
+    b->rows_per_group = desc->rows_per_group;
+  } else {
+    // about two workgroups per compute unit over all instances, within
+    // [1024, 16384] rows per workgroup share
+    int64_t rows = 0;
+    for (int k = 0; k < m; ++k) rows += desc->n[k];
+    const int64_t want = (rows + 2 * (int64_t)cus - 1) / (2 * (int64_t)cus);
+    b->rows_per_group = (int32_t)std::min<int64_t>(16384, std::max<int64_t>(1024, want));
+  }
   b->t_cap = desc->t_cap;
   b->max_iters = desc->max_iters;
   b->stream = (hipStream_t)desc->stream;
