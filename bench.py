@@ -29,6 +29,8 @@ The same JSON line also carries
                 instance advances one MWU iteration), the pass's bytes over its
                 HIP-event time, FP32 and BF16 storage, and the eps = 1e-3 solve
                 of all 4,096 instances (solves/s);
+  solve_kway    eps = 1e-3 solves of the 1e6 x 100 workload by the k-way alpha
+                search (k tests per round sharing the passes), FP32 storage;
   cpu_baseline  the FP64 reference implementation timed on this host on a
                 bounded sample (a few iterations at the full size), one
                 thread and all cores.
@@ -126,6 +128,20 @@ def read_reference(nbytes, X=None, reps=20):
     buf = X if X is not None else torch.empty(nbytes // 2, dtype=torch.int16, device="cuda")
     ms = scp.scp_mwu_read_reference(buf.data_ptr(), nbytes, reps, torch.cuda.current_stream().cuda_stream)
     return dict(ms=round(ms, 5), GBs=round(nbytes / (ms * 1e-3) / 1e9, 1), bytes=nbytes)
+
+
+def solve_kway(X, k):
+    """eps = 1e-3 solve of the headline workload by the k-way alpha search."""
+    import torch
+    import paper_2405_09157_amd as scp
+    with scp.MWUBatch.kway(X, k, eps=1e-3, chunk=32) as b:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = b.solve_kway()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    return dict(k=k, seconds=round(dt, 3), solves_per_s=round(1.0 / dt, 4), tests=out["tests"], iters=out["iters"],
+                passes=out["passes"], radius=out["radius"], lower=out["lower"], converged=bool(out["converged"]))
 
 
 def solve(X, storage):
@@ -294,6 +310,11 @@ def main(argv=None):
             sol[k]["radius_rel_to_f32"] = sol[k]["radius"] / sol["f32"]["radius"] - 1.0
             print(f"# solve {k}: {sol[k]}", file=sys.stderr, flush=True)
             sol[f"{k}_over_f32_solve_rate"] = sol[k]["solves_per_s"] / sol["f32"]["solves_per_s"]
+        kway = [solve_kway(X, k) for k in (2, 4)]
+        for r in kway:
+            r["over_f32_solve_rate"] = round(r["solves_per_s"] / sol["f32"]["solves_per_s"], 3)
+            print(f"# solve k-way: {r}", file=sys.stderr, flush=True)
+        sol["kway"] = kway
     del X
     torch.cuda.empty_cache()
     bsolve = [] if a.batch_solve == "none" else [None if s == "f32" else s for s in a.batch_solve.split(",")]
