@@ -158,11 +158,12 @@ void ses_rows_batch_kernel(const PassArgs *__restrict__ args, const BatchTile *_
 
 // Epilogue of every instance (workgroup k sums instance k's nrec[k] records;
 // an instance whose test has ended only reads its state).
+constexpr int kBatchEpiBlock = 256;
 template <typename T>
-__global__ __launch_bounds__(kCombBlock) void epilogue_batch_kernel(const PassArgs *__restrict__ args,
-                                                                    const int32_t *__restrict__ nrec) {
+__global__ __launch_bounds__(kBatchEpiBlock) void epilogue_batch_kernel(const PassArgs *__restrict__ args,
+                                                                        const int32_t *__restrict__ nrec) {
   const PassArgs a = args[blockIdx.x];
-  epilogue_body<T, kSES, false>(a, nrec[blockIdx.x]);
+  epilogue_body<T, kSES, false, kBatchEpiBlock>(a, nrec[blockIdx.x]);
 }
 
 // (Re)start the alpha-tests of the instances list[0 .. count) with params[j].
@@ -281,7 +282,7 @@ hipError_t launch_rows_batch_typed(int dm, int vec, int ntiles, const PassArgs *
 
 template <typename T>
 hipError_t launch_epilogue_batch_typed(int m, const PassArgs *args, const int32_t *nrec, hipStream_t s) {
-  hipLaunchKernelGGL((epilogue_batch_kernel<T>), dim3(m), dim3(kCombBlock), 0, s, args, nrec);
+  hipLaunchKernelGGL((epilogue_batch_kernel<T>), dim3(m), dim3(kBatchEpiBlock), 0, s, args, nrec);
   return hipGetLastError();
 }
 

@@ -1193,9 +1193,13 @@ constexpr int kStateWords = (int)(sizeof(DevState) / 8);
 // into LDS; the records are summed in a fixed transposed order; one wave then
 // runs the FP64 epilogue on the LDS copies and writes the state back.  The
 // kernel boundary after the pass makes every record visible: no fences.
-template <typename T, int PROB, bool CERT>
+// NT threads: the one-problem epilogue uses kCombBlock, the batched one a
+// smaller block (its instances have few records).
+template <typename T, int PROB, bool CERT, int NT = kCombBlock>
 __device__ __forceinline__ void epilogue_body(const PassArgs &a, int P) {
-  __shared__ double s_acc[2 * kCombBlock];
+  // group partial sums (groups x ncols), or the column sums when a record has
+  // more column pairs than threads
+  __shared__ double s_acc[2 * NT > 2 * kMaxD + 8 ? 2 * NT : 2 * kMaxD + 8];
   __shared__ double s_comb[2 * kMaxD + 8];
   __shared__ double s_y[kMaxD], s_S[kMaxD], s_v1[kMaxD];
   __shared__ DevState s_st;
@@ -1205,16 +1209,16 @@ __device__ __forceinline__ void epilogue_body(const PassArgs &a, int P) {
   const int ncols = rec_read_cols<PROB, CERT>(d);  // the certificate half is read only with one
   const int nsc = PROB == kSES ? 5 : 4;                      // summed scalars
   const int npairs = ncols / 2;
-  const int groups = kCombBlock / npairs;
+  const int groups = npairs <= NT ? NT / npairs : 1;
   // state, mean, running sum, row v1
   if (tid < kStateWords) reinterpret_cast<double *>(&s_st)[tid] = reinterpret_cast<const double *>(a.st)[tid];
-  for (int c = tid; c < d; c += kCombBlock) {
+  for (int c = tid; c < d; c += NT) {
     s_y[c] = a.vec[kVecMean * d + c];
     s_S[c] = a.vec[kVecS * d + c];
     if (PROB == kSES) s_v1[c] = row_value<T>(a, a.v1, c);
   }
-  const int j = tid % npairs, grp = tid / npairs;
-  if (grp < groups) {
+  for (int jp = tid; jp < npairs * groups; jp += NT) {
+    const int j = jp % npairs, grp = jp / npairs;
     const int c0 = 2 * j;
     const bool m0 = c0 >= dp + nsc && c0 < dp + 8, m1 = c0 + 1 >= dp + nsc && c0 + 1 < dp + 8;
     double acc0 = m0 ? -INFINITY : 0.0, acc1 = m1 ? -INFINITY : 0.0;
@@ -1228,7 +1232,7 @@ __device__ __forceinline__ void epilogue_body(const PassArgs &a, int P) {
     s_acc[grp * ncols + c0 + 1] = acc1;
   }
   __syncthreads();
-  for (int c = tid; c < ncols; c += kCombBlock) {
+  for (int c = tid; c < ncols; c += NT) {
     const bool mx = c >= dp + nsc && c < dp + 8;
     double r = mx ? -INFINITY : 0.0;
     for (int g = 0; g < groups; ++g) r = mx ? fmax(r, s_acc[g * ncols + c]) : r + s_acc[g * ncols + c];

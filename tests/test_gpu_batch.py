@@ -31,9 +31,10 @@ SEP_SLACK = 5  # iterations per test by which a slow separation may move
 SOLVE_TOL = 2e-4
 
 # (n, d): one and several workgroup shares, ragged last batches, every column
-# layout the batched config uses (d in {2, 3, 16, 64}) and a few others
+# layout the batched config uses (d in {2, 3, 16, 64}) and a few others, up to
+# d = 512 (a record with more column pairs than the batched epilogue's threads)
 SHAPES = [(1000, 2), (3001, 3), (517, 16), (2049, 64), (40, 5), (20000, 3), (777, 100), (4500, 64), (2, 7),
-          (1301, 33)]
+          (1301, 33), (600, 512)]
 
 
 def _instances(shapes, seed, bf16=False):
