@@ -303,7 +303,8 @@ typedef struct scp_mwu_batch_desc {
   const int64_t *d;      /* host, m values: dimension of instance k, in [1, 512] */
   const int64_t *offset; /* host, m values: element offset of instance k's first
                             point in `points`; its n[k] rows are dense (stride
-                            d[k]); instances must not overlap */
+                            d[k]).  Instances may share rows (the points are
+                            only read), as the k-way search's slots do */
   const void *points;    /* device, binary32 */
   double eps;            /* target accuracy of scp_mwu_batch_solve; default 1e-3 */
   double delta;          /* stabilisation threshold; default 1e-4 */
