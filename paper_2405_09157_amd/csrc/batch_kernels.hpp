@@ -22,7 +22,7 @@ void ses_pass_batch_kernel(const PassArgs *__restrict__ args, const BatchTile *_
 }
 
 // Row-per-lane SES pass for instances with d <= DM <= 16 columns: every lane
-// owns RL whole rows of a batch (a wave batch is 64 * RL rows), so a row's
+// owns RL = 2 whole rows of a batch (a wave batch is 128 rows), so a row's
 // squared distance is summed inside the lane and the binary64 chains of the
 // per-row phase (sqrt, exp, expm1, division) of RL rows run side by side; the
 // weighted sums are kept per lane and reduced once per workgroup.  Point sets
@@ -32,7 +32,7 @@ void ses_pass_batch_kernel(const PassArgs *__restrict__ args, const BatchTile *_
 template <typename T, int DM, int VEC>
 __device__ __forceinline__ void ses_rows_body(const PassArgs &a, int vb, int vg) {
   static_assert(DM % VEC == 0 && DM <= 16, "row layout");
-  constexpr int RL = DM <= 4 ? 4 : 2;
+  constexpr int RL = 2;
   constexpr int NQ = DM / VEC;
   constexpr int B = kWave * RL;
   constexpr bool M32 = sizeof(T) <= 2;
@@ -148,8 +148,10 @@ __device__ __forceinline__ void ses_rows_body(const PassArgs &a, int vb, int vg)
   }
 }
 
+// With at most 4 columns per lane the kernel fits 128 VGPRs, i.e. four waves
+// per SIMD (two workgroups per compute unit) to hide the per-row latency.
 template <typename T, int DM, int VEC>
-__global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
+__global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(DM <= 4 ? 4 : SCPMWU_PASS_WAVES)))
 void ses_rows_batch_kernel(const PassArgs *__restrict__ args, const BatchTile *__restrict__ tiles) {
   const BatchTile tl = tiles[blockIdx.x];
   const PassArgs a = args[tl.inst];
