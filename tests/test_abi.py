@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_c(tmp_path):
     from paper_2405_09157_amd import _lib
     structs = {"scp_mwu_desc": _lib.scp_mwu_desc, "scp_mwu_stepinfo": _lib.scp_mwu_stepinfo,
-               "scp_mwu_result": _lib.scp_mwu_result}
+               "scp_mwu_result": _lib.scp_mwu_result, "scp_mwu_batch_desc": _lib.scp_mwu_batch_desc}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "scp_mwu.h"', "int main(void){"]
     for sname, cls in structs.items():
         lines.append(f'printf("{sname} %zu\\n", sizeof({sname}));')
