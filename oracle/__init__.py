@@ -18,6 +18,8 @@ ses      Smallest enclosing sphere via the max-form meta-algorithm
          monitor f(t), early stopping (Section 5), adaptive alpha search.
 svm      Hard-margin SVM / polytope distance via the min-form meta-algorithm
          (Section 3 "Extension to minimization problems" with Section 4.2).
+ses_grad Gradient of the radius after a fixed number of SES iterations by
+         the adjoint recursion (reverse pass through the unrolled iterations).
 exact    Exact references used to pin the above: Welzl's algorithm and brute
          force for SES, direction enumeration for 2-D SVM.
 certify  Certified bounds for any candidate (upper/lower bounds on OPT).

@@ -95,3 +95,41 @@ def test_svm_500k_d256_fullsize(storage):
     assert abs(info["log_trace"] - st["logC"]) / max(1.0, abs(st["logC"])) <= tol
     if st["f_prev"] > 0:
         assert abs(info["f_last"] - st["f_prev"]) / st["f_prev"] <= tol
+
+
+@pytest.mark.parametrize("rows_per_group", [8192, 16384])
+def test_batched_4096_fullsize(rows_per_group):
+    """The batched configuration at full size (4,096 instances, 86.7 M points)
+    at the workgroup shares the bench's autotuner picks on this workload
+    (8192 or 16384 rows per share): after 37 iterations of every
+    instance, the next iteration of sampled instances (the largest of each
+    dimension and a few seeded others) against one oracle step from that
+    instance's state (running sum = mean x t)."""
+    import torch
+    import paper_2405_09157_amd as scp
+    n, d = synth.ses_batch_sizes(4096, 1000, 100_000, [2, 3, 16, 64], 0)
+    pts, off = synth.ses_batch_points_device(n, d, 0)
+    m = len(n)
+    T = 20000
+    with scp.MWUBatch(pts, n, d, off, flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP,
+                      rows_per_group=rows_per_group) as b:
+        alphas = list(b.D)             # the ball at v1 of radius D encloses every point
+        b.step(alphas, [T] * m, 37)
+        before = b.step(alphas, [T] * m, 0)
+        means = b.vectors(0)
+        infos = b.step(alphas, [T] * m, 1)
+        us = b.vectors(2)
+        D = list(b.D)
+    sample = {int(np.flatnonzero(d == dd)[np.argmax(n[d == dd])]) for dd in (2, 3, 16, 64)}
+    sample |= set(int(k) for k in np.random.default_rng(3).choice(m, 4, replace=False))
+    for k in sorted(sample):
+        V = pts[int(off[k]):int(off[k]) + int(n[k] * d[k])].reshape(int(n[k]), int(d[k])).cpu().double().numpy()
+        P = oses.setup(V)
+        assert abs(D[k] - P.D) <= 1e-12 * P.D
+        t = before[k]["t"]
+        assert t == 37 and infos[k]["outcome_name"] == "running"
+        st = oses.step(P, np.array(means[k]) * t, t, alphas[k], math.sqrt(math.log(P.r) / T))
+        assert np.linalg.norm(np.array(us[k]) - st["u"]) / alphas[k] <= TIGHT, k
+        assert abs(infos[k]["value"] - st["value"]) / st["scale"] <= TIGHT, k
+        assert abs(infos[k]["log_trace"] - st["logC"]) / abs(st["logC"]) <= TIGHT, k
+        assert abs(infos[k]["f_last"] - st["f_prev"]) / st["f_prev"] <= TIGHT, k

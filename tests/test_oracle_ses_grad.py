@@ -1,0 +1,74 @@
+"""Pins of the gradient oracle (oracle/ses_grad.py): the adjoint recursion
+against central finite differences of the forward map itself, the forward map
+against the alpha-test with early exits off, and the two invariances of an
+enclosing radius under rigid motions."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ses, ses_grad
+
+# (n, d, T, seed): small inputs on which the map is smooth at the step sizes
+# used (the unrolled map can amplify perturbations over many iterations when
+# ||W_t|| becomes small, so cases are fixed, not drawn).
+CASES = [(10, 3, 30, 0), (12, 3, 40, 3), (9, 5, 25, 4)]
+
+
+def central_fd(V, alpha, T, h, v1=0):
+    G = np.zeros_like(V)
+    for i in range(V.shape[0]):
+        for k in range(V.shape[1]):
+            Vp, Vm = V.copy(), V.copy()
+            Vp[i, k] += h
+            Vm[i, k] -= h
+            G[i, k] = (ses_grad.radius(Vp, alpha, T, v1) - ses_grad.radius(Vm, alpha, T, v1)) / (2 * h)
+    return G
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_gradient_vs_central_differences(case):
+    n, d, T, seed = case
+    V = synth.ses_uniform(n, d, seed)
+    alpha = 2.0 * ses.setup(V).D / 3.0
+    R, G = ses_grad.radius_grad(V, alpha, T)
+    assert R == ses_grad.radius(V, alpha, T)
+    # truncation O(h^2) against rounding O(1e-16 / h): the better of two steps
+    err = min(np.abs(G - central_fd(V, alpha, T, h)).max() for h in (1e-5, 1e-6))
+    assert err <= 2e-6 * np.abs(G).max()
+
+
+def test_gradient_vs_central_differences_v1_not_first():
+    V = synth.ses_uniform(9, 3, 7)
+    alpha = 2.0 * ses.setup(V, None, 4).D / 3.0
+    _, G = ses_grad.radius_grad(V, alpha, 30, v1=4)
+    err = min(np.abs(G - central_fd(V, alpha, 30, h, v1=4)).max() for h in (1e-5, 1e-6))
+    assert err <= 2e-6 * np.abs(G).max()
+
+
+@pytest.mark.parametrize("case", CASES + [(200, 8, 60, 11)])
+def test_rigid_motion_invariances(case):
+    """R is unchanged when every point moves by the same vector or is rotated
+    about the origin, so sum_i g_i = 0 and sum_i v_i g_i^T is symmetric."""
+    n, d, T, seed = case
+    V = synth.ses_uniform(n, d, seed)
+    alpha = 2.0 * ses.setup(V).D / 3.0
+    _, G = ses_grad.radius_grad(V, alpha, T)
+    scale = np.abs(G).max() * np.abs(V).max()
+    assert np.abs(G.sum(axis=0)).max() <= 1e-10 * np.abs(G).max() * n
+    M = V.T @ G
+    assert np.abs(M - M.T).max() <= 1e-10 * scale * n
+
+
+def test_forward_is_the_alpha_test_without_exits():
+    V = synth.ses_uniform(30, 4, 5)
+    P = ses.setup(V)
+    alpha, T = 2.0 * P.D / 3.0, 50
+    fw = ses_grad.forward(V, alpha, T)
+    res = ses.ftp(P, alpha, T, math.sqrt(math.log(P.r) / T), early_stop=False, record=True)
+    assert res.outcome in (ses.T_REACHED, ses.SEPARATED)
+    np.testing.assert_allclose(fw.S[res.t_done], res.S, rtol=0, atol=1e-12)
+    assert abs(res.f_traj[-1] - ses.monitor(P, fw.S[res.t_done] / res.t_done)) <= 1e-12
+    if res.outcome == ses.T_REACHED:
+        assert abs(fw.R - res.f_traj[-1]) <= 1e-12 * fw.R
