@@ -216,6 +216,45 @@ def batched(steps, warmup, solve_storages):
     return out
 
 
+GRAD = dict(name="ses_grad_200k_d64_T2000", n=200_000, d=64, T=2000, seed=0)
+
+
+def gradient(reps=3):
+    """Reverse pass of the radius after T fixed-alpha iterations (FP32 points
+    N(0, I), alpha = 2D/3): wall time of scp_mwu_backward (forward with
+    stored running sums, per-segment recomputation, reverse iterations) and,
+    beside it, T forward iterations of the streaming pass at the same alpha."""
+    import numpy as np
+    import torch
+    import paper_2405_09157_amd as scp
+    import synth
+    g = GRAD
+    V = synth.ses_gaussian_outliers(g["n"], g["d"], g["seed"], frac=0.0, dtype=np.float32)
+    X = torch.from_numpy(V).cuda()
+    out = torch.empty_like(X)
+    with scp.MWU(X, "ses", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP) as m:
+        alpha = 2.0 * m.D / 3.0
+        m.step(alpha, g["T"], 0, reset=True)
+        R, _ = m.backward(1.0, out)           # warm-up
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m.backward(1.0, out)
+            times.append(time.perf_counter() - t0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.step(alpha, g["T"], g["T"], reset=True)
+        torch.cuda.synchronize()
+        fwd = time.perf_counter() - t0
+    bwd = min(times)
+    return dict(workload=g["name"], n=g["n"], d=g["d"], T=g["T"], checkpoint_every=50,
+                storage="f32", radius=R, backward_s=round(bwd, 4),
+                reverse_iters_per_s=round(g["T"] / bwd, 1),
+                forward_s=round(fwd, 4), backward_over_forward=round(bwd / fwd, 2),
+                grad_abs_sum=float(out.abs().sum()))
+
+
 def _oracle_iters(V64, threads, warm, timed, budget_s):
     """Median seconds per FP64 oracle iteration of the benchmarked alpha-test."""
     from threadpoolctl import threadpool_limits
@@ -266,6 +305,7 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--batch-solve", default="f32",
                     help="storage types of the batched eps solves: comma list of f32, bf16, or none")
+    ap.add_argument("--no-grad", action="store_true", help="skip the reverse-pass workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain copy of the matrix (counter calibration)")
     a = ap.parse_args(argv)
@@ -319,6 +359,9 @@ def main(argv=None):
     torch.cuda.empty_cache()
     bsolve = [] if a.batch_solve == "none" else [None if s == "f32" else s for s in a.batch_solve.split(",")]
     batch = None if a.no_batch else batched(min(a.steps, 320), a.warmup, bsolve)
+    grad = None if a.no_grad else gradient()
+    if grad:
+        print(f"# gradient: {grad}", file=sys.stderr, flush=True)
     cpu = None if a.no_cpu else cpu_baseline(V)
     if cpu:
         print(f"# cpu: {cpu}", file=sys.stderr, flush=True)
@@ -354,6 +397,8 @@ def main(argv=None):
         line["solve"] = sol
     if batch:
         line["batched"] = batch
+    if grad:
+        line["gradient"] = grad
     if probe:
         line["copy_reference"] = probe
     print(json.dumps(line), flush=True)

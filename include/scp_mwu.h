@@ -230,12 +230,31 @@ int scp_mwu_step(scp_mwu_ctx *ctx, double alpha, int64_t T, int32_t k,
 int scp_mwu_solve(scp_mwu_ctx *ctx, scp_mwu_result *res, double *y);
 
 /*
- * Gradient of the solved value with respect to the points (adjoint of the
- * unrolled fixed-alpha, fixed-T iterations).  Not implemented in this
- * version: always returns E_UNSUPPORTED and writes nothing.
- * grad_points: device, n x d FP32 owned by the caller.
+ * Gradient of the radius after the current test with respect to the points:
+ * the adjoint of the unrolled fixed-alpha, fixed-T iterations of the SES
+ * split (Section 4.1; ORACLE eq.(ses_oracle); SOC exponential, Section 2.1).
+ * The differentiated map runs T iterations at the test's alpha and
+ * eta = sqrt(ln r / T) from an empty running sum, with the exponent scale
+ * kappa_t = eta (t - 1) / (3D) and D = max_i ||v1 - v_i|| recomputed from the
+ * points, and returns R = max_i ||v_i - ubar_T|| (the Section 5 monitor at the
+ * final mean); R is differentiable where both maxima are attained once.
+ * The call recomputes the forward iterations, keeping the running sum every
+ * 50 iterations, then walks each 50-iteration segment back after recomputing
+ * it: three streaming passes over the points per iteration.
+ * Requires: an SES context on points without radii, streamed as F32 or F64
+ * (no BF16/FP8 storage), d <= 512, and a current test (scp_mwu_step with
+ * reset, any k >= 0): its alpha and T define the map, which always runs all
+ * T iterations, also where the test itself stopped earlier (a separation
+ * or a Section 5 exit).  The test's state is left unchanged.
+ * grad_value: the upstream scalar dL/dR; the output is grad_value * dR/dV.
+ * grad_points: device, n x d FP32, row stride d, owned by the caller;
+ *   overwritten.
+ * value (host, may be NULL): receives R as the recomputed forward found it.
+ * Errors: E_INVAL (NULL grad_points, non-finite grad_value), E_UNSUPPORTED
+ * (SVM, radii, BF16/FP8 storage, d > 512), E_STATE (no test started),
+ * E_NOMEM, E_HIP.  Blocks until the result is written.
  */
-int scp_mwu_backward(scp_mwu_ctx *ctx, double grad_value, float *grad_points);
+int scp_mwu_backward(scp_mwu_ctx *ctx, double grad_value, float *grad_points, double *value);
 
 /*
  * Inspect or replace the running sums of the current test (checkpoint /

@@ -121,6 +121,19 @@ class MWU:
         """(pass-kernel ms, whole-iteration ms): HIP-event means over k further iterations."""
         return L.scp_mwu_time_passes(self.ctx, int(k))
 
+    def backward(self, grad_value: float = 1.0, out=None):
+        """(R, grad_value * dR/dV) of the T-iteration map at the current
+        test's alpha and T: R = max_i ||v_i - ubar_T||, the gradient an
+        n x d float32 device tensor (written into `out` when given)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, self.d, dtype=torch.float32, device=self.points.device)
+        if out.dtype != torch.float32 or out.shape != (self.n, self.d) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 n x d tensor")
+        with torch.cuda.device(self.points.device):
+            R = L.scp_mwu_backward(self.ctx, float(grad_value), out.data_ptr())
+        return R, out
+
     def eta(self, T: int) -> float:
         return math.sqrt(math.log(self.r) / T)
 
@@ -237,6 +250,41 @@ class MWUBatch:
     def time_iters(self, k: int):
         """(pass ms, whole-iteration ms): HIP-event means over k further iterations."""
         return L.scp_mwu_batch_time_iters(self.b, int(k))
+
+
+def _radius_function():
+    import torch
+
+    class _Radius(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, points, alpha, T):
+            with MWU(points.detach(), "ses", flags=L.SCP_MWU_FLAG_NO_EARLY_STOP) as m:
+                m.step(alpha, T, 0, reset=True)   # starts the test that fixes alpha and T
+                R, g = m.backward(1.0)
+            ctx.save_for_backward(g)
+            ctx.points_dtype = points.dtype
+            return torch.tensor(R, dtype=torch.float64, device=points.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            return (g * grad_out.to(g.dtype)).to(ctx.points_dtype), None, None
+
+    return _Radius
+
+
+_RADIUS = None
+
+
+def ses_radius(points, alpha: float, T: int):
+    """R = max_i ||v_i - ubar_T|| after T fixed-alpha SES iterations on the
+    points (float32 or float64 device tensor, n x d) as a differentiable
+    torch scalar (float64).  The forward call also computes dR/dV (one
+    reverse pass), which backward scales by the incoming gradient."""
+    global _RADIUS
+    if _RADIUS is None:
+        _RADIUS = _radius_function()
+    return _RADIUS.apply(points, float(alpha), int(T))
 
 
 def autotune_rows_per_group(points, n, d, offset=None, candidates=(2048, 4096, 8192, 16384, 32768),

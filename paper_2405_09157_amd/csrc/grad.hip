@@ -1,0 +1,471 @@
+// Reverse pass of the SES radius after T fixed-alpha iterations: the adjoint
+// recursion through the unrolled iterations (Section 4.1 split, eq.(ses_oracle),
+// Section 2.1 SOC exponential), with the running sum stored every kSegment
+// iterations and each segment recomputed forward before it is reversed.
+//
+// Per iteration t (reverse order), with lambda the adjoint of S_t:
+//   lambda_W = alpha (I - What What^T) lambda / ||W_t||
+//   row i != v1: delta_i = v_i - c_t, a_i, a_i' = da/dd, beta_i = a_i' (delta_i . lambda_W) / d_i;
+//                grad_i += a_i lambda_W + beta_i delta_i
+//   lambda <- lambda - (sum_i a_i lambda_W + beta_i delta_i) / (t - 1)
+//   v1 collects lambda (u(t) = v1 + ...); D collects -kappa_t/D sum_i (da_i/dkappa)(delta_i . lambda_W)
+// and finally R's own term at its active row and D's at v1 and its far row.
+//
+// Lanes run over the columns of a row (d <= 512: PER <= 8 columns per lane);
+// each wave takes rows kRB at a time (all loads issued before the arithmetic)
+// and reduces a row's sums with a butterfly.  All arithmetic is binary64; the
+// gradient is accumulated in a binary64 workspace and rounded once to the
+// caller's FP32 buffer.
+#include <algorithm>
+#include <cmath>
+
+#include "grad.hpp"
+
+namespace scpmwu {
+namespace grad {
+
+constexpr int kBlk = 256, kW = 64, kNW = kBlk / kW, kMaxPer = 8, kRB = 4;
+constexpr int kMaxCols = kMaxPer * kW;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kW);
+  return v;
+}
+
+// Sum over the 256 threads of one workgroup (every thread gets the result).
+__device__ __forceinline__ double bsum(double v, double *s_r) {
+  v = wsum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_r[w] = v;
+  __syncthreads();
+  return (s_r[0] + s_r[1]) + (s_r[2] + s_r[3]);
+}
+
+template <typename P>
+__device__ __forceinline__ double xval(const Buffers &b, int64_t i, int col) {
+  return (double)((const P *)b.X)[i * b.ld + col];
+}
+
+// dst[c] = sum over the grid's partial rows of column c, c < ncol (fixed order).
+__device__ void reduce_parts(const double *part, int G, int ncol, double *dst, double *tmp) {
+  const int tid = threadIdx.x;
+  if (ncol <= kBlk) {
+    const int groups = kBlk / ncol;
+    const int grp = tid / ncol, col = tid - grp * ncol;
+    double acc = 0.0;
+    if (grp < groups)
+      for (int g = grp; g < G; g += groups) acc += part[(int64_t)g * ncol + col];
+    tmp[tid] = acc;
+    __syncthreads();
+    if (tid < ncol) {
+      double s = 0.0;
+      for (int q = 0; q < groups; ++q) s += tmp[q * ncol + tid];
+      dst[tid] = s;
+    }
+  } else {
+    for (int col = tid; col < ncol; col += kBlk) {
+      double s = 0.0;
+      for (int g = 0; g < G; ++g) s += part[(int64_t)g * ncol + col];
+      dst[col] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// ---- forward iteration t = t0 + 1 + slot: partial sums of W_t
+template <typename P, int PER>
+__global__ __launch_bounds__(kBlk) void fwd_pass(Buffers b, int slot) {
+  __shared__ double red[kNW][kMaxCols];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
+  const double *c = b.tc + (int64_t)slot * d;
+  const double kap = b.ts[slot * 4 + 0], sh = b.ts[slot * 4 + 1];
+  double cr[PER], acc[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int col = lane + j * kW;
+    cr[j] = col < d ? c[col] : 0.0;
+    acc[j] = 0.0;
+  }
+  if (kap > 0.0) {
+    const int64_t stride = (int64_t)gridDim.x * kNW;
+    for (int64_t base = (int64_t)blockIdx.x * kNW + w; base < b.n; base += kRB * stride) {
+      double x[kRB][PER];
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int64_t i = base + r * stride;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          const int col = lane + j * kW;
+          x[r][j] = (i < b.n && col < d) ? xval<P>(b, i, col) : cr[j];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int64_t i = base + r * stride;
+        if (i >= b.n || i == b.v1) continue;
+        double dl[PER], s2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          dl[j] = x[r][j] - cr[j];
+          s2 += dl[j] * dl[j];
+        }
+        const double di = sqrt(wsum(s2));
+        if (!(di > 0.0)) continue;  // a row at the centre adds a_i * 0
+        const double ep = exp(kap * di - sh), em = exp(-kap * di - sh);
+        const double a = (ep - em) / di;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) acc[j] += a * dl[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) red[w][lane + j * kW] = acc[j];
+  __syncthreads();
+  double *p = b.part + (int64_t)blockIdx.x * (d + 2);
+  for (int col = threadIdx.x; col < d + 2; col += kBlk)
+    p[col] = col < d ? (red[0][col] + red[1][col]) + (red[2][col] + red[3][col]) : 0.0;
+}
+
+// ---- forward epilogue of iteration t: u(t), S_t, the tape of slot and the
+// centre, kappa and shift of the next iteration (slot + 1).
+template <typename P>
+__global__ __launch_bounds__(kBlk) void fwd_epi(Buffers b, int slot, int64_t t, int write_ck) {
+  __shared__ double s_W[kMaxCols + 2], tmp[kBlk], s_r[kNW];
+  const int tid = threadIdx.x, d = (int)b.d;
+  reduce_parts(b.part, b.grid, d + 2, s_W, tmp);
+  double p = 0.0;
+  for (int col = tid; col < d; col += kBlk) p += s_W[col] * s_W[col];
+  const double nW = sqrt(bsum(p, s_r));
+  const double kap = b.ts[slot * 4 + 0];
+  const bool ok = kap > 0.0 && nW > 0.0;
+  const double tt = (double)t;
+  double q = 0.0;
+  for (int col = tid; col < d; col += kBlk) {
+    const double v1c = xval<P>(b, b.v1, col);
+    const double wh = ok ? s_W[col] / nW : 0.0;
+    const double S = b.S[col] + (v1c + b.alpha * wh);
+    b.S[col] = S;
+    b.tw[(int64_t)slot * d + col] = wh;
+    const double cn = S / tt;
+    b.tc[(int64_t)(slot + 1) * d + col] = cn;
+    q += (v1c - cn) * (v1c - cn);
+    if (write_ck && t % kSegment == 0) b.ck[(t / kSegment) * d + col] = S;
+  }
+  q = bsum(q, s_r);
+  if (tid == 0) {
+    b.ts[slot * 4 + 2] = ok ? nW : 0.0;
+    const double kn = b.eta * tt / (3.0 * b.misc[2]);
+    b.ts[(slot + 1) * 4 + 0] = kn;
+    // kappa d_i <= kappa (||v_i - v1|| + ||v1 - c||) <= kappa (D + ||v1 - c||)
+    b.ts[(slot + 1) * 4 + 1] = kn * (b.misc[2] + sqrt(q));
+  }
+}
+
+// ---- start of the segment whose first iteration is t0 + 1: S = S_{t0}.
+template <typename P>
+__global__ __launch_bounds__(kBlk) void seg_init(Buffers b, int64_t t0) {
+  __shared__ double s_r[kNW];
+  const int tid = threadIdx.x, d = (int)b.d;
+  double q = 0.0;
+  for (int col = tid; col < d; col += kBlk) {
+    const double S = b.ck[(t0 / kSegment) * d + col];
+    const double v1c = xval<P>(b, b.v1, col);
+    const double cn = t0 > 0 ? S / (double)t0 : v1c;
+    b.S[col] = S;
+    b.tc[col] = cn;
+    q += (v1c - cn) * (v1c - cn);
+  }
+  q = bsum(q, s_r);
+  if (tid == 0) {
+    const double k0 = b.eta * (double)t0 / (3.0 * b.misc[2]);
+    b.ts[0] = k0;
+    b.ts[1] = k0 * (b.misc[2] + sqrt(q));
+  }
+}
+
+// lambda_W of slot from lambda (shared by the reverse pass and its epilogue so
+// that both see the same values).
+__device__ __forceinline__ void lambda_w(const Buffers &b, int slot, double *s_lw, double *s_r) {
+  const int tid = threadIdx.x, d = (int)b.d;
+  const double *Wh = b.tw + (int64_t)slot * d;
+  const double nW = b.ts[slot * 4 + 2];
+  double p = 0.0;
+  for (int col = tid; col < d; col += kBlk) p += Wh[col] * b.lam[col];
+  p = bsum(p, s_r);
+  for (int col = tid; col < d; col += kBlk)
+    s_lw[col] = nW > 0.0 ? b.alpha * (b.lam[col] - Wh[col] * p) / nW : 0.0;
+  __syncthreads();
+}
+
+// ---- reverse iteration t = t0 + 1 + slot (t >= 2)
+template <typename P, int PER>
+__global__ __launch_bounds__(kBlk) void bwd_pass(Buffers b, int slot) {
+  __shared__ double red[kNW][kMaxCols];
+  __shared__ double s_lw[kMaxCols], s_r[kNW], s_a[kNW], s_k[kNW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
+  lambda_w(b, slot, s_lw, s_r);
+  const double *c = b.tc + (int64_t)slot * d;
+  const double kap = b.ts[slot * 4 + 0], sh = b.ts[slot * 4 + 1], nW = b.ts[slot * 4 + 2];
+  double cr[PER], lw[PER], accB[PER];
+  double accA = 0.0, accK = 0.0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int col = lane + j * kW;
+    cr[j] = col < d ? c[col] : 0.0;
+    lw[j] = col < d ? s_lw[col] : 0.0;
+    accB[j] = 0.0;
+  }
+  if (kap > 0.0 && nW > 0.0) {
+    const int64_t stride = (int64_t)gridDim.x * kNW;
+    for (int64_t base = (int64_t)blockIdx.x * kNW + w; base < b.n; base += kRB * stride) {
+      double x[kRB][PER];
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int64_t i = base + r * stride;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          const int col = lane + j * kW;
+          x[r][j] = (i < b.n && col < d) ? xval<P>(b, i, col) : cr[j];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int64_t i = base + r * stride;
+        if (i >= b.n || i == b.v1) continue;
+        double dl[PER], s2 = 0.0, q = 0.0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          dl[j] = x[r][j] - cr[j];
+          s2 += dl[j] * dl[j];
+          q += dl[j] * lw[j];
+        }
+        s2 = wsum(s2);
+        q = wsum(q);
+        const double di = sqrt(s2);
+        if (!(di > 0.0)) continue;
+        const double ep = exp(kap * di - sh), em = exp(-kap * di - sh);
+        const double a = (ep - em) / di;
+        const double a1 = (kap * (ep + em) * di - (ep - em)) / (di * di);
+        const double beta = a1 * q / di;
+        double *g = b.gacc + i * b.d;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          const int col = lane + j * kW;
+          if (col < d) g[col] += a * lw[j] + beta * dl[j];
+          accB[j] += beta * dl[j];
+        }
+        accA += a;
+        accK += (ep + em) * q;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) red[w][lane + j * kW] = accB[j];
+  if (lane == 0) {
+    s_a[w] = accA;
+    s_k[w] = accK;
+  }
+  __syncthreads();
+  double *p = b.part + (int64_t)blockIdx.x * (d + 2);
+  for (int col = threadIdx.x; col < d + 2; col += kBlk) {
+    double v;
+    if (col < d)
+      v = (red[0][col] + red[1][col]) + (red[2][col] + red[3][col]);
+    else if (col == d)
+      v = (s_a[0] + s_a[1]) + (s_a[2] + s_a[3]);
+    else
+      v = (s_k[0] + s_k[1]) + (s_k[2] + s_k[3]);
+    p[col] = v;
+  }
+}
+
+// ---- reverse epilogue of iteration t: v1's share, the D share, lambda_{t-1}.
+__global__ __launch_bounds__(kBlk) void bwd_epi(Buffers b, int slot, int64_t t) {
+  __shared__ double s_P[kMaxCols + 2], tmp[kBlk], s_lw[kMaxCols], s_r[kNW];
+  const int tid = threadIdx.x, d = (int)b.d;
+  if (t >= 2) {
+    reduce_parts(b.part, b.grid, d + 2, s_P, tmp);
+    lambda_w(b, slot, s_lw, s_r);
+  }
+  for (int col = tid; col < d; col += kBlk) {
+    const double lam = b.lam[col];
+    b.gv1[col] += lam;
+    if (t >= 2) {
+      const double lc = -s_P[d] * s_lw[col] - s_P[col];
+      b.lam[col] = lam + lc / (double)(t - 1);
+    }
+  }
+  if (tid == 0 && t >= 2) b.misc[0] += -(b.ts[slot * 4 + 0] / b.misc[2]) * s_P[d + 1];
+}
+
+// ---- farthest row from a centre (ties: smallest index), per workgroup
+template <typename P, int PER>
+__global__ __launch_bounds__(kBlk) void far_pass(Buffers b, const double *center, int64_t exclude) {
+  __shared__ double s_d[kNW];
+  __shared__ int64_t s_i[kNW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
+  double cr[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int col = lane + j * kW;
+    cr[j] = col < d ? center[col] : 0.0;
+  }
+  double best = -1.0;
+  int64_t bi = -1;
+  const int64_t stride = (int64_t)gridDim.x * kNW;
+  for (int64_t i = (int64_t)blockIdx.x * kNW + w; i < b.n; i += stride) {
+    if (i == exclude) continue;
+    double s2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int col = lane + j * kW;
+      const double dl = col < d ? xval<P>(b, i, col) - cr[j] : 0.0;
+      s2 += dl * dl;
+    }
+    s2 = wsum(s2);
+    if (s2 > best) {  // rows ascend within a wave: the first maximum stays
+      best = s2;
+      bi = i;
+    }
+  }
+  if (lane == 0) {
+    s_d[w] = best;
+    s_i[w] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < kNW; ++q)
+      if (s_d[q] > best || (s_d[q] == best && s_i[q] >= 0 && (bi < 0 || s_i[q] < bi))) {
+        best = s_d[q];
+        bi = s_i[q];
+      }
+    b.part[2 * blockIdx.x] = best;
+    b.part[2 * blockIdx.x + 1] = (double)bi;
+  }
+}
+
+__global__ __launch_bounds__(kW) void far_final(Buffers b, int which) {
+  if (threadIdx.x != 0) return;
+  double best = -1.0;
+  int64_t bi = -1;
+  for (int g = 0; g < b.grid; ++g) {
+    const double v = b.part[2 * g];
+    const int64_t i = (int64_t)b.part[2 * g + 1];
+    if (i >= 0 && (v > best || (v == best && i < bi))) {
+      best = v;
+      bi = i;
+    }
+  }
+  b.misc[which == 0 ? 1 : 2] = sqrt(best);
+  b.idx[which] = bi;
+}
+
+// v1 as a centre, zero checkpoint, zero accumulators.
+template <typename P>
+__global__ __launch_bounds__(kBlk) void init_kernel(Buffers b) {
+  const int d = (int)b.d;
+  for (int col = threadIdx.x; col < d; col += kBlk) {
+    b.ubar[col] = xval<P>(b, b.v1, col);
+    b.ck[col] = 0.0;
+    b.gv1[col] = 0.0;
+  }
+  if (threadIdx.x == 0) b.misc[0] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlk) void mean_kernel(Buffers b) {
+  for (int col = threadIdx.x; col < (int)b.d; col += kBlk) b.ubar[col] = b.S[col] / (double)b.T;
+}
+
+// lambda_T = g (ubar_T - v_i*) / (R T)
+template <typename P>
+__global__ __launch_bounds__(kBlk) void lambda_init(Buffers b, double gv) {
+  const int64_t is = b.idx[0];
+  const double R = b.misc[1];
+  if (is < 0) return;  // no finite distance: the result stays zero
+  for (int col = threadIdx.x; col < (int)b.d; col += kBlk)
+    b.lam[col] = R > 0.0 ? gv * (b.ubar[col] - xval<P>(b, is, col)) / (R * (double)b.T) : 0.0;
+}
+
+// The rows of v1 (its share of every u(t) and of D), of D's far row j* and of
+// R's active row i*, added in that order by one thread per column.
+template <typename P>
+__global__ __launch_bounds__(kBlk) void final_kernel(Buffers b, double gv) {
+  const int64_t v1 = b.v1, js = b.idx[1], is = b.idx[0];
+  const double lD = b.misc[0], R = b.misc[1], D = b.misc[2];
+  if (is < 0 || js < 0) return;
+  for (int col = threadIdx.x; col < (int)b.d; col += kBlk) {
+    const double e = (xval<P>(b, v1, col) - xval<P>(b, js, col)) / D;
+    double *g = b.gacc;
+    g[v1 * b.d + col] += b.gv1[col] + lD * e;
+    g[js * b.d + col] += -lD * e;
+    if (R > 0.0) g[is * b.d + col] += gv * (xval<P>(b, is, col) - b.ubar[col]) / R;
+  }
+}
+
+__global__ __launch_bounds__(kBlk) void round_kernel(const double *src, float *dst, int64_t count) {
+  for (int64_t k = (int64_t)blockIdx.x * kBlk + threadIdx.x; k < count; k += (int64_t)gridDim.x * kBlk)
+    dst[k] = (float)src[k];
+}
+
+template <typename P, int PER>
+hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
+  const int G = b.grid;
+  const int64_t T = b.T;
+  hipError_t e = hipMemsetAsync(b.gacc, 0, (size_t)b.n * b.d * sizeof(double), s);
+  if (e != hipSuccess) return e;
+  init_kernel<P><<<1, kBlk, 0, s>>>(b);
+  far_pass<P, PER><<<G, kBlk, 0, s>>>(b, b.ubar, b.v1);
+  far_final<<<1, kW, 0, s>>>(b, 1);
+  const int64_t nseg = (T + kSegment - 1) / kSegment;
+  // forward, storing S every kSegment iterations
+  for (int64_t sg = 0; sg < nseg; ++sg) {
+    const int64_t t0 = sg * kSegment, t1 = std::min<int64_t>(t0 + kSegment, T);
+    seg_init<P><<<1, kBlk, 0, s>>>(b, t0);
+    for (int64_t t = t0 + 1; t <= t1; ++t) {
+      const int slot = (int)(t - t0 - 1);
+      fwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+      fwd_epi<P><<<1, kBlk, 0, s>>>(b, slot, t, 1);
+    }
+  }
+  mean_kernel<<<1, kBlk, 0, s>>>(b);
+  far_pass<P, PER><<<G, kBlk, 0, s>>>(b, b.ubar, -1);
+  far_final<<<1, kW, 0, s>>>(b, 0);
+  lambda_init<P><<<1, kBlk, 0, s>>>(b, gv);
+  // reverse, one segment at a time: recompute its tape, then walk it back
+  for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+    const int64_t t0 = sg * kSegment, t1 = std::min<int64_t>(t0 + kSegment, T);
+    seg_init<P><<<1, kBlk, 0, s>>>(b, t0);
+    for (int64_t t = t0 + 1; t <= t1; ++t) {
+      const int slot = (int)(t - t0 - 1);
+      fwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+      fwd_epi<P><<<1, kBlk, 0, s>>>(b, slot, t, 0);
+    }
+    for (int64_t t = t1; t > t0; --t) {
+      const int slot = (int)(t - t0 - 1);
+      if (t >= 2) bwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+      bwd_epi<<<1, kBlk, 0, s>>>(b, slot, t);
+    }
+  }
+  final_kernel<P><<<1, kBlk, 0, s>>>(b, gv);
+  round_kernel<<<G, kBlk, 0, s>>>(b.gacc, b.grad, b.n * b.d);
+  return hipGetLastError();
+}
+
+template <typename P>
+hipError_t run_per(const Buffers &b, double gv, hipStream_t s) {
+  const int64_t per = (b.d + kW - 1) / kW;
+  if (per <= 1) return run_typed<P, 1>(b, gv, s);
+  if (per <= 2) return run_typed<P, 2>(b, gv, s);
+  if (per <= 4) return run_typed<P, 4>(b, gv, s);
+  return run_typed<P, 8>(b, gv, s);
+}
+
+hipError_t run_backward(const Buffers &b, double gv, hipStream_t s) {
+  if (b.d < 1 || b.d > kMaxCols || b.n < 2 || b.T < 1 || b.grid < 1) return hipErrorInvalidValue;
+  return b.dtype == 1 ? run_per<double>(b, gv, s) : run_per<float>(b, gv, s);
+}
+
+}  // namespace grad
+}  // namespace scpmwu

@@ -1,0 +1,51 @@
+// Gradient of the SES radius after T fixed-alpha iterations (point sets): the
+// map, its adjoint recursion and the device buffers of the reverse pass.
+//
+// The map (Section 4.1 split, eq.(ses_oracle) ORACLE, Section 2.1 SOC
+// exponential, Section 5 monitor): u(t) = v1 + alpha W_t/||W_t|| with
+// W_t = sum_{i != v1} a_i (v_i - c_t), c_t the mean of u(1..t-1),
+// a_i = (e^{kappa_t d_i - s_t} - e^{-kappa_t d_i - s_t}) / d_i,
+// d_i = ||v_i - c_t||, kappa_t = eta (t-1) / (3D) and s_t any shift common to
+// all rows; R = max_i ||v_i - ubar_T||.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace scpmwu {
+namespace grad {
+
+constexpr int kSegment = 50;  // iterations between stored running sums
+
+// Device buffers of one reverse pass (allocated by the host for one call).
+struct Buffers {
+  int64_t n, d, ld, v1, T;
+  int dtype;         // 0: float points, 1: double points
+  const void *X;
+  double alpha, eta;     // kappa_t = eta (t - 1) / (3D), D recomputed on the device
+  int grid;
+  // running sum and its checkpoints S_{k * kSegment}
+  double *S, *ck;
+  // tape of one segment, slot j = iteration t0 + 1 + j:
+  //   tc: c_t (kSegment + 1 slots), tw: W_t/||W_t|| (kSegment slots),
+  //   ts: {kappa_t, s_t, ||W_t||, 0} (kSegment + 1 slots)
+  double *tc, *tw, *ts;
+  double *part;      // grid x (d + 2) per-workgroup partial sums
+  double *lam;       // adjoint of S_t
+  double *gv1;       // accumulated adjoint of v1 from u(t) = v1 + ...
+  double *ubar;      // ubar_T
+  double *misc;      // [0] adjoint of D, [1] R, [2] D (recomputed), [3..4] scratch
+  int64_t *idx;      // [0] i* (argmax of R), [1] j* (argmax of D)
+  double *gacc;      // n x d accumulator of the gradient (row stride d)
+  float *grad;       // caller's n x d output (row stride d)
+};
+
+// Sizes of the buffers (in doubles) for given d, T.
+inline int64_t ck_count(int64_t T) { return T / kSegment + 2; }
+
+// Launch the whole reverse pass (forward with checkpoints, reverse segments,
+// the terms of R and D) on stream s.  grad_value scales the result.
+hipError_t run_backward(const Buffers &b, double grad_value, hipStream_t s);
+
+}  // namespace grad
+}  // namespace scpmwu

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/scp_mwu.h"
+#include "grad.hpp"
 #include "mwu_common.hpp"
 
 
@@ -583,11 +584,58 @@ int scp_mwu_get_vector(scp_mwu_ctx *c, int32_t which, double *y) {
   return SCP_MWU_OK;
 }
 
-int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points) {
-  (void)grad_value;
-  (void)grad_points;
-  if (c) c->err = "scp_mwu_backward is not implemented in this version";
-  return SCP_MWU_E_UNSUPPORTED;
+int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points, double *value) {
+  if (!c) return SCP_MWU_E_INVAL;
+  if (!grad_points) return c->fail(SCP_MWU_E_INVAL, "grad_points is NULL");
+  if (!std::isfinite(grad_value)) return c->fail(SCP_MWU_E_INVAL, "grad_value is not finite");
+  if (c->problem != kSES || c->radii)
+    return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: SES on point sets only");
+  if (c->dtype != kF32 && c->dtype != kF64)
+    return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: points streamed as F32 or F64 only (no BF16/FP8 storage)");
+  if (c->d > 512) return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: d > 512");
+  if (!c->active) return c->fail(SCP_MWU_E_STATE, "backward before any test");
+  int rc = SCP_MWU_OK;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return c->fail(SCP_MWU_E_HIP, "device query failed");
+  grad::Buffers b{};
+  b.n = c->n;
+  b.d = c->d;
+  b.ld = c->ld;
+  b.v1 = c->v1;
+  b.T = c->T;
+  b.dtype = c->dtype == kF64 ? 1 : 0;
+  b.X = c->X;
+  b.alpha = c->alpha;
+  b.eta = c->eta;
+  // four workgroups per CU, at least 64 rows per workgroup
+  b.grid = (int)std::max<int64_t>(1, std::min<int64_t>(4 * (int64_t)std::max(cus, 1), (c->n + 63) / 64));
+  const int64_t d = c->d, K = grad::kSegment;
+  const int64_t sizes[] = {d, grad::ck_count(c->T) * d, (K + 1) * d, K * d, (K + 1) * 4,
+                           (int64_t)b.grid * (d + 2), d, d, d, 8, 2, c->n * d};
+  int64_t total = 0;
+  for (int64_t v : sizes) total += (v + 31) / 32 * 32;
+  void *mem = nullptr;
+  if (hipMalloc(&mem, (size_t)total * sizeof(double)) != hipSuccess)
+    return c->fail(SCP_MWU_E_NOMEM, "backward workspace");
+  double *p = (double *)mem;
+  double **dst[] = {&b.S, &b.ck, &b.tc, &b.tw, &b.ts, &b.part, &b.lam, &b.gv1, &b.ubar, &b.misc};
+  for (int k = 0; k < 10; ++k) {
+    *dst[k] = p;
+    p += (sizes[k] + 31) / 32 * 32;
+  }
+  b.idx = (int64_t *)p;
+  p += 32;
+  b.gacc = p;
+  b.grad = grad_points;
+  rc = c->hip(grad::run_backward(b, grad_value, c->stream), "backward");
+  double misc[3] = {0, 0, 0};
+  if (!rc) rc = c->hip(hipMemcpyAsync(misc, b.misc, sizeof(misc), hipMemcpyDeviceToHost, c->stream), "backward readback");
+  const hipError_t es = hipStreamSynchronize(c->stream);  // the workspace is freed only when idle
+  if (!rc) rc = c->hip(es, "backward sync");
+  hipFree(mem);
+  if (!rc && value) *value = misc[1];
+  return rc;
 }
 
 int scp_mwu_solve(scp_mwu_ctx *c, scp_mwu_result *res, double *y) {

@@ -133,3 +133,48 @@ def test_batched_4096_fullsize(rows_per_group):
         assert abs(infos[k]["value"] - st["value"]) / st["scale"] <= TIGHT, k
         assert abs(infos[k]["log_trace"] - st["logC"]) / abs(st["logC"]) <= TIGHT, k
         assert abs(infos[k]["f_last"] - st["f_prev"]) / st["f_prev"] <= TIGHT, k
+
+
+def test_grad_200k_d64_fullsize():
+    """The gradient workload at full size (n = 200,000, d = 64, T = 2,000,
+    FP32 points N(0, I), alpha = 2D/3) through the reverse pass, checked by
+    properties that hold at any size: the two rigid-motion invariances of R
+    (sum_i g_i = 0; sum_i v_i g_i^T symmetric) and the directional derivative
+    along a fixed direction against central differences of the same map
+    evaluated by the library in binary64 (R returned by the reverse pass on
+    binary64 copies of V +- h Delta)."""
+    import torch
+    import paper_2405_09157_amd as scp
+    n, d, T = 200_000, 64, 2000
+    V32 = synth.ses_gaussian_outliers(n, d, 0, frac=0.0, dtype=np.float32)
+    X = torch.from_numpy(V32).cuda()
+
+    def run(Xt, gv=1.0):
+        with scp.MWU(Xt, "ses", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP) as m:
+            m.step(alpha, T, 0, reset=True)
+            return m.backward(gv)
+
+    with scp.MWU(X, "ses") as m:
+        alpha = 2.0 * m.D / 3.0
+    R, g = run(X)
+    G = g.cpu().double().numpy()
+    V = V32.astype(np.float64)
+    A = np.abs(G)
+    assert np.all(np.abs(G.sum(axis=0)) <= 1e-6 * A.sum(axis=0))
+    M = V.T @ G
+    assert np.all(np.abs(M - M.T) <= 1e-6 * (np.abs(V).T @ A + A.T @ np.abs(V)))
+    # direction: the gradient itself plus a seeded random part, unit norm
+    rnd = np.random.default_rng(5).standard_normal((n, d))
+    Dl = G / np.linalg.norm(G) + 0.5 * rnd / np.linalg.norm(rnd)
+    Dl /= np.linalg.norm(Dl)
+    slope = float(np.sum(G * Dl))
+    X64 = torch.from_numpy(V).cuda()
+    Dt = torch.from_numpy(Dl).cuda()
+    errs = []
+    for h in (1e-3, 1e-4):
+        Rp, _ = run(X64 + h * Dt)
+        Rm, _ = run(X64 - h * Dt)
+        errs.append(abs((Rp - Rm) / (2 * h) - slope))
+    R64, _ = run(X64)
+    assert abs(R - R64) <= 1e-12 * R64
+    assert min(errs) <= 1e-5 * abs(slope), (errs, slope)

@@ -1,0 +1,147 @@
+"""GPU parity of the reverse pass (scp_mwu_backward) against the gradient
+oracle (oracle/ses_grad.py).
+
+Tolerance.  The kernels widen the stored points exactly to binary64 and do
+every operation in binary64, as the oracle does on the same values, so the
+two differ by summation order (n-term sums per iteration and T iterations of
+the recursion, ~1e-12 relative on these inputs) and by the final rounding of
+the gradient to FP32 (2^-24 ~ 6e-8 relative per element).  GRAD_TOL = 1e-6
+relative to max |g| is the stated FP32 result bar and holds both with a wide
+margin; R itself is a binary64 value (TIGHT).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ses as oses
+from oracle import ses_grad
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = 1e-9
+GRAD_TOL = 1e-6
+
+# (n, d, T, seed, v1, dtype): the segment boundary (every 50 iterations)
+# crossed and ragged; d from 1 to 512 (1 to 8 columns per lane, ragged
+# column tails); v1 not the first row.
+CASES = [
+    (12, 3, 30, 0, 0, "f64"),
+    (12, 3, 40, 3, 0, "f32"),
+    (9, 5, 25, 4, 0, "f32"),
+    (200, 5, 123, 1, 0, "f32"),
+    (150, 1, 60, 8, 3, "f32"),
+    (2000, 64, 60, 2, 0, "f32"),
+    (1500, 100, 51, 4, 7, "f64"),
+    (64, 65, 100, 6, 0, "f32"),
+    (300, 512, 20, 5, 0, "f32"),
+    (5000, 16, 50, 9, 11, "f32"),
+]
+
+
+def points(n, d, seed, dtype):
+    import torch
+    V = synth.ses_uniform(n, d, seed)
+    if dtype == "f32":
+        V = V.astype(np.float32)
+    t = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    return t, V.astype(np.float64)
+
+
+def gpu_grad(X, alpha, T, v1=0, gv=1.0):
+    import paper_2405_09157_amd as scp
+    with scp.MWU(X, "ses", v1=v1, flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP) as m:
+        m.step(alpha, T, 0, reset=True)
+        R, g = m.backward(gv)
+        return R, g.cpu().double().numpy()
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "n%d_d%d_T%d_v%d_%s" % (c[0], c[1], c[2], c[4], c[5]))
+def test_backward_vs_oracle(case):
+    n, d, T, seed, v1, dtype = case
+    X, V = points(n, d, seed, dtype)
+    alpha = 2.0 * oses.setup(V, None, v1).D / 3.0
+    R, G = gpu_grad(X, alpha, T, v1)
+    R0, G0 = ses_grad.radius_grad(V, alpha, T, v1)
+    assert abs(R - R0) <= TIGHT * R0
+    assert np.abs(G - G0).max() <= GRAD_TOL * np.abs(G0).max()
+
+
+def test_backward_scales_with_grad_value_and_leaves_the_test():
+    import paper_2405_09157_amd as scp
+    X, V = points(400, 7, 12, "f32")
+    alpha = 2.0 * oses.setup(V).D / 3.0
+    with scp.MWU(X, "ses", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP) as m:
+        m.step(alpha, 80, 10, reset=True)
+        before = m.get_state()
+        R1, g1 = m.backward(1.0)
+        g1 = g1.cpu().double().numpy()
+        R2, g2 = m.backward(-2.5)
+        g2 = g2.cpu().double().numpy()
+        assert m.get_state() == before
+        info = m.step(alpha, 80, 1)
+        assert info["t"] == 11
+    assert R1 == R2
+    assert np.abs(g2 + 2.5 * g1).max() <= GRAD_TOL * np.abs(g2).max()
+
+
+def test_backward_errors():
+    import torch
+    import paper_2405_09157_amd as scp
+    X, V = points(100, 4, 13, "f32")
+    out = torch.empty(100, 4, dtype=torch.float32, device="cuda")
+    with scp.MWU(X, "ses") as m:
+        with pytest.raises(scp.ScpMwuError) as e:
+            scp.scp_mwu_backward(m.ctx, 1.0, out.data_ptr())
+        assert e.value.code == scp.SCP_MWU_E_STATE
+        m.step(1.0, 10, 0, reset=True)
+        with pytest.raises(scp.ScpMwuError) as e:
+            scp.scp_mwu_backward(m.ctx, float("nan"), out.data_ptr())
+        assert e.value.code == scp.SCP_MWU_E_INVAL
+    with scp.MWU(X, "ses", storage="bf16") as m:
+        m.step(1.0, 10, 0, reset=True)
+        with pytest.raises(scp.ScpMwuError) as e:
+            scp.scp_mwu_backward(m.ctx, 1.0, out.data_ptr())
+        assert e.value.code == scp.SCP_MWU_E_UNSUPPORTED
+    radii = torch.full((100,), 0.01, dtype=torch.float64, device="cuda")
+    with scp.MWU(X, "ses", radii=radii) as m:
+        m.step(1.0, 10, 0, reset=True)
+        with pytest.raises(scp.ScpMwuError) as e:
+            scp.scp_mwu_backward(m.ctx, 1.0, out.data_ptr())
+        assert e.value.code == scp.SCP_MWU_E_UNSUPPORTED
+    with scp.MWU(X, "svm", n_pos=50) as m:
+        m.step(0.01, 10, 0, reset=True)
+        with pytest.raises(scp.ScpMwuError) as e:
+            scp.scp_mwu_backward(m.ctx, 1.0, out.data_ptr())
+        assert e.value.code == scp.SCP_MWU_E_UNSUPPORTED
+
+
+def test_backward_of_a_separated_test_runs_the_full_map():
+    """A test at alpha below OPT separates, but the differentiated map runs
+    all T iterations."""
+    import paper_2405_09157_amd as scp
+    X, V = points(300, 3, 14, "f32")
+    P = oses.setup(V)
+    alpha, T = 0.51 * P.D, 70
+    with scp.MWU(X, "ses") as m:
+        info = m.step(alpha, T, T, reset=True)
+        assert info["outcome_name"] == "separated" and info["t"] < T
+        R, g = m.backward(1.0)
+    R0, G0 = ses_grad.radius_grad(V, alpha, T)
+    assert abs(R - R0) <= TIGHT * R0
+    assert np.abs(g.cpu().double().numpy() - G0).max() <= GRAD_TOL * np.abs(G0).max()
+
+
+def test_autograd_function():
+    import torch
+    import paper_2405_09157_amd as scp
+    X, V = points(500, 6, 15, "f32")
+    alpha = 2.0 * oses.setup(V).D / 3.0
+    Xg = X.clone().requires_grad_(True)
+    R = scp.ses_radius(Xg, alpha, 60)
+    (3.0 * R).backward()
+    R0, G0 = ses_grad.radius_grad(V, alpha, 60)
+    assert abs(float(R.detach()) - R0) <= TIGHT * R0
+    assert Xg.grad.dtype == torch.float32
+    assert np.abs(Xg.grad.cpu().double().numpy() - 3.0 * G0).max() <= GRAD_TOL * 3.0 * np.abs(G0).max()
