@@ -8,6 +8,8 @@
 //   row i != v1: delta_i = v_i - c_t, a_i, a_i' = da/dd, beta_i = a_i' (delta_i . lambda_W) / d_i;
 //                grad_i += a_i lambda_W + beta_i delta_i
 //   lambda <- lambda - (sum_i a_i lambda_W + beta_i delta_i) / (t - 1)
+//   (the rows' own terms are kept as the two coefficients a_i, beta_i per
+//   iteration and contracted once per segment)
 //   v1 collects lambda (u(t) = v1 + ...); D collects -kappa_t/D sum_i (da_i/dkappa)(delta_i . lambda_W)
 // and finally R's own term at its active row and D's at v1 and its far row.
 //
@@ -25,6 +27,7 @@ namespace scpmwu {
 namespace grad {
 
 constexpr int kBlk = 256, kW = 64, kNW = kBlk / kW, kMaxPer = 8, kRB = 4;
+constexpr int kEpi = 1024;  // threads of the one-workgroup epilogues
 constexpr int kMaxCols = kMaxPer * kW;
 
 __device__ __forceinline__ double wsum(double v) {
@@ -33,14 +36,18 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-// Sum over the 256 threads of one workgroup (every thread gets the result).
+// Sum over the NT threads of one workgroup (every thread gets the result).
+template <int NT>
 __device__ __forceinline__ double bsum(double v, double *s_r) {
   v = wsum(v);
   const int w = threadIdx.x >> 6;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) s_r[w] = v;
   __syncthreads();
-  return (s_r[0] + s_r[1]) + (s_r[2] + s_r[3]);
+  double r = 0.0;
+#pragma unroll
+  for (int q = 0; q < NT / kW; ++q) r += s_r[q];
+  return r;
 }
 
 template <typename P>
@@ -48,30 +55,35 @@ __device__ __forceinline__ double xval(const Buffers &b, int64_t i, int col) {
   return (double)((const P *)b.X)[i * b.ld + col];
 }
 
-// dst[c] = sum over the grid's partial rows of column c, c < ncol (fixed order).
+// dst[c] = sum over the grid's partial rows of column c, c < ncol, by the NT
+// threads of one workgroup (fixed order; four loads in flight per thread).
+template <int NT>
 __device__ void reduce_parts(const double *part, int G, int ncol, double *dst, double *tmp) {
   const int tid = threadIdx.x;
-  if (ncol <= kBlk) {
-    const int groups = kBlk / ncol;
-    const int grp = tid / ncol, col = tid - grp * ncol;
-    double acc = 0.0;
-    if (grp < groups)
-      for (int g = grp; g < G; g += groups) acc += part[(int64_t)g * ncol + col];
-    tmp[tid] = acc;
+  const int groups = ncol <= NT ? NT / ncol : 1;
+  for (int c0 = 0; c0 < ncol; c0 += NT) {
+    const int span = ncol - c0 < NT ? ncol - c0 : NT;
+    const int grp = tid / span, col = c0 + tid - grp * span;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (grp < groups) {
+      int g = grp;
+      for (; g + 3 * groups < G; g += 4 * groups) {
+        a0 += part[(int64_t)g * ncol + col];
+        a1 += part[(int64_t)(g + groups) * ncol + col];
+        a2 += part[(int64_t)(g + 2 * groups) * ncol + col];
+        a3 += part[(int64_t)(g + 3 * groups) * ncol + col];
+      }
+      for (; g < G; g += groups) a0 += part[(int64_t)g * ncol + col];
+    }
+    tmp[tid] = (a0 + a1) + (a2 + a3);
     __syncthreads();
-    if (tid < ncol) {
-      double s = 0.0;
-      for (int q = 0; q < groups; ++q) s += tmp[q * ncol + tid];
-      dst[tid] = s;
+    if (tid < span) {
+      double r = 0.0;
+      for (int q = 0; q < groups; ++q) r += tmp[q * span + tid];
+      dst[c0 + tid] = r;
     }
-  } else {
-    for (int col = tid; col < ncol; col += kBlk) {
-      double s = 0.0;
-      for (int g = 0; g < G; ++g) s += part[(int64_t)g * ncol + col];
-      dst[col] = s;
-    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // ---- forward iteration t = t0 + 1 + slot: partial sums of W_t
@@ -131,18 +143,18 @@ __global__ __launch_bounds__(kBlk) void fwd_pass(Buffers b, int slot) {
 // ---- forward epilogue of iteration t: u(t), S_t, the tape of slot and the
 // centre, kappa and shift of the next iteration (slot + 1).
 template <typename P>
-__global__ __launch_bounds__(kBlk) void fwd_epi(Buffers b, int slot, int64_t t, int write_ck) {
-  __shared__ double s_W[kMaxCols + 2], tmp[kBlk], s_r[kNW];
+__global__ __launch_bounds__(kEpi) void fwd_epi(Buffers b, int slot, int64_t t, int write_ck) {
+  __shared__ double s_W[kMaxCols + 2], tmp[kEpi], s_r[kEpi / kW];
   const int tid = threadIdx.x, d = (int)b.d;
-  reduce_parts(b.part, b.grid, d + 2, s_W, tmp);
+  reduce_parts<kEpi>(b.part, b.grid, d + 2, s_W, tmp);
   double p = 0.0;
-  for (int col = tid; col < d; col += kBlk) p += s_W[col] * s_W[col];
-  const double nW = sqrt(bsum(p, s_r));
+  for (int col = tid; col < d; col += kEpi) p += s_W[col] * s_W[col];
+  const double nW = sqrt(bsum<kEpi>(p, s_r));
   const double kap = b.ts[slot * 4 + 0];
   const bool ok = kap > 0.0 && nW > 0.0;
   const double tt = (double)t;
   double q = 0.0;
-  for (int col = tid; col < d; col += kBlk) {
+  for (int col = tid; col < d; col += kEpi) {
     const double v1c = xval<P>(b, b.v1, col);
     const double wh = ok ? s_W[col] / nW : 0.0;
     const double S = b.S[col] + (v1c + b.alpha * wh);
@@ -153,7 +165,7 @@ __global__ __launch_bounds__(kBlk) void fwd_epi(Buffers b, int slot, int64_t t, 
     q += (v1c - cn) * (v1c - cn);
     if (write_ck && t % kSegment == 0) b.ck[(t / kSegment) * d + col] = S;
   }
-  q = bsum(q, s_r);
+  q = bsum<kEpi>(q, s_r);
   if (tid == 0) {
     b.ts[slot * 4 + 2] = ok ? nW : 0.0;
     const double kn = b.eta * tt / (3.0 * b.misc[2]);
@@ -177,7 +189,7 @@ __global__ __launch_bounds__(kBlk) void seg_init(Buffers b, int64_t t0) {
     b.tc[col] = cn;
     q += (v1c - cn) * (v1c - cn);
   }
-  q = bsum(q, s_r);
+  q = bsum<kBlk>(q, s_r);
   if (tid == 0) {
     const double k0 = b.eta * (double)t0 / (3.0 * b.misc[2]);
     b.ts[0] = k0;
@@ -185,17 +197,20 @@ __global__ __launch_bounds__(kBlk) void seg_init(Buffers b, int64_t t0) {
   }
 }
 
-// lambda_W of slot from lambda (shared by the reverse pass and its epilogue so
-// that both see the same values).
+// lambda_W of slot from lambda, computed by every workgroup of the reverse
+// pass; workgroup 0 also stores it for the epilogue.
 __device__ __forceinline__ void lambda_w(const Buffers &b, int slot, double *s_lw, double *s_r) {
   const int tid = threadIdx.x, d = (int)b.d;
   const double *Wh = b.tw + (int64_t)slot * d;
   const double nW = b.ts[slot * 4 + 2];
   double p = 0.0;
   for (int col = tid; col < d; col += kBlk) p += Wh[col] * b.lam[col];
-  p = bsum(p, s_r);
-  for (int col = tid; col < d; col += kBlk)
-    s_lw[col] = nW > 0.0 ? b.alpha * (b.lam[col] - Wh[col] * p) / nW : 0.0;
+  p = bsum<kBlk>(p, s_r);
+  for (int col = tid; col < d; col += kBlk) {
+    const double v = nW > 0.0 ? b.alpha * (b.lam[col] - Wh[col] * p) / nW : 0.0;
+    s_lw[col] = v;
+    if (blockIdx.x == 0) b.lw[(int64_t)slot * d + col] = v;
+  }
   __syncthreads();
 }
 
@@ -217,7 +232,9 @@ __global__ __launch_bounds__(kBlk) void bwd_pass(Buffers b, int slot) {
     lw[j] = col < d ? s_lw[col] : 0.0;
     accB[j] = 0.0;
   }
-  if (kap > 0.0 && nW > 0.0) {
+  const bool live = kap > 0.0 && nW > 0.0;
+  double *sa = b.sa + (int64_t)slot * b.n, *sb = b.sb + (int64_t)slot * b.n;
+  {
     const int64_t stride = (int64_t)gridDim.x * kNW;
     for (int64_t base = (int64_t)blockIdx.x * kNW + w; base < b.n; base += kRB * stride) {
       double x[kRB][PER];
@@ -233,7 +250,7 @@ __global__ __launch_bounds__(kBlk) void bwd_pass(Buffers b, int slot) {
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         const int64_t i = base + r * stride;
-        if (i >= b.n || i == b.v1) continue;
+        if (i >= b.n) continue;
         double dl[PER], s2 = 0.0, q = 0.0;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
@@ -244,18 +261,22 @@ __global__ __launch_bounds__(kBlk) void bwd_pass(Buffers b, int slot) {
         s2 = wsum(s2);
         q = wsum(q);
         const double di = sqrt(s2);
-        if (!(di > 0.0)) continue;
-        const double ep = exp(kap * di - sh), em = exp(-kap * di - sh);
-        const double a = (ep - em) / di;
-        const double a1 = (kap * (ep + em) * di - (ep - em)) / (di * di);
-        const double beta = a1 * q / di;
-        double *g = b.gacc + i * b.d;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-          const int col = lane + j * kW;
-          if (col < d) g[col] += a * lw[j] + beta * dl[j];
-          accB[j] += beta * dl[j];
+        const bool valid = live && i != b.v1 && di > 0.0;
+        double a = 0.0, beta = 0.0, ep = 0.0, em = 0.0;
+        if (valid) {
+          ep = exp(kap * di - sh);
+          em = exp(-kap * di - sh);
+          a = (ep - em) / di;
+          const double a1 = (kap * (ep + em) * di - (ep - em)) / (di * di);
+          beta = a1 * q / di;
         }
+        if (lane == 0) {  // the row's coefficients, contracted after the segment
+          sa[i] = a;
+          sb[i] = beta;
+        }
+        if (!valid) continue;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) accB[j] += beta * dl[j];
         accA += a;
         accK += (ep + em) * q;
       }
@@ -281,19 +302,204 @@ __global__ __launch_bounds__(kBlk) void bwd_pass(Buffers b, int slot) {
   }
 }
 
-// ---- reverse epilogue of iteration t: v1's share, the D share, lambda_{t-1}.
-__global__ __launch_bounds__(kBlk) void bwd_epi(Buffers b, int slot, int64_t t) {
-  __shared__ double s_P[kMaxCols + 2], tmp[kBlk], s_lw[kMaxCols], s_r[kNW];
-  const int tid = threadIdx.x, d = (int)b.d;
-  if (t >= 2) {
-    reduce_parts(b.part, b.grid, d + 2, s_P, tmp);
-    lambda_w(b, slot, s_lw, s_r);
+// ---- the same two passes for d <= 64 with 16 lanes per row (4 rows per
+// wave at a time, CPL <= 4 adjacent columns per lane): the row sums take a
+// 4-step butterfly inside the 16 lanes and serve 4 rows at once.
+constexpr int kLPR = 16, kRPW = kW / kLPR;
+
+__device__ __forceinline__ double gsum16(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, kLPR);
+  return v;
+}
+
+template <typename P, int CPL>
+__global__ __launch_bounds__(kBlk) void fwd_rows(Buffers b, int slot) {
+  __shared__ double red[kNW * kRPW][kLPR * CPL];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
+  const int rg = lane >> 4, cl = lane & 15;
+  const double *c = b.tc + (int64_t)slot * d;
+  const double kap = b.ts[slot * 4 + 0], sh = b.ts[slot * 4 + 1];
+  double cr[CPL], acc[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int col = cl * CPL + j;
+    cr[j] = col < d ? c[col] : 0.0;
+    acc[j] = 0.0;
   }
-  for (int col = tid; col < d; col += kBlk) {
+  if (kap > 0.0) {
+    const int64_t wstride = (int64_t)gridDim.x * kNW * kRPW;
+    for (int64_t wb = ((int64_t)blockIdx.x * kNW + w) * kRPW; wb < b.n; wb += kRB * wstride) {
+      double x[kRB][CPL];
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int64_t i = wb + r * wstride + rg;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const int col = cl * CPL + j;
+          x[r][j] = (i < b.n && col < d) ? xval<P>(b, i, col) : cr[j];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int64_t i = wb + r * wstride + rg;
+        double dl[CPL], s2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          dl[j] = x[r][j] - cr[j];
+          s2 += dl[j] * dl[j];
+        }
+        const double di = sqrt(gsum16(s2));
+        const bool valid = i < b.n && i != b.v1 && di > 0.0;
+        const double ep = exp(kap * di - sh), em = exp(-kap * di - sh);
+        const double a = valid ? (ep - em) / di : 0.0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) acc[j] += a * dl[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) red[w * kRPW + rg][cl * CPL + j] = acc[j];
+  __syncthreads();
+  double *p = b.part + (int64_t)blockIdx.x * (d + 2);
+  for (int col = threadIdx.x; col < d + 2; col += kBlk) {
+    double v = 0.0;
+    if (col < d)
+#pragma unroll
+      for (int q = 0; q < kNW * kRPW; ++q) v += red[q][col];
+    p[col] = v;
+  }
+}
+
+template <typename P, int CPL>
+__global__ __launch_bounds__(kBlk) void bwd_rows(Buffers b, int slot) {
+  __shared__ double red[kNW * kRPW][kLPR * CPL];
+  __shared__ double s_lw[kMaxCols], s_r[kNW], s_a[kNW], s_k[kNW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
+  const int rg = lane >> 4, cl = lane & 15;
+  lambda_w(b, slot, s_lw, s_r);
+  const double *c = b.tc + (int64_t)slot * d;
+  const double kap = b.ts[slot * 4 + 0], sh = b.ts[slot * 4 + 1], nW = b.ts[slot * 4 + 2];
+  double cr[CPL], lw[CPL], accB[CPL];
+  double accA = 0.0, accK = 0.0;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int col = cl * CPL + j;
+    cr[j] = col < d ? c[col] : 0.0;
+    lw[j] = col < d ? s_lw[col] : 0.0;
+    accB[j] = 0.0;
+  }
+  const bool live = kap > 0.0 && nW > 0.0;
+  double *sa = b.sa + (int64_t)slot * b.n, *sb = b.sb + (int64_t)slot * b.n;
+  {
+    const int64_t wstride = (int64_t)gridDim.x * kNW * kRPW;
+    for (int64_t wb = ((int64_t)blockIdx.x * kNW + w) * kRPW; wb < b.n; wb += kRB * wstride) {
+      double x[kRB][CPL];
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int64_t i = wb + r * wstride + rg;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const int col = cl * CPL + j;
+          x[r][j] = (i < b.n && col < d) ? xval<P>(b, i, col) : cr[j];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int64_t i = wb + r * wstride + rg;
+        double dl[CPL], s2 = 0.0, q = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          dl[j] = x[r][j] - cr[j];
+          s2 += dl[j] * dl[j];
+          q += dl[j] * lw[j];
+        }
+        s2 = gsum16(s2);
+        q = gsum16(q);
+        const double di = sqrt(s2);
+        const bool valid = live && i < b.n && i != b.v1 && di > 0.0;
+        double a = 0.0, beta = 0.0;
+        if (valid) {  // a row's 16 lanes agree
+          const double ep = exp(kap * di - sh), em = exp(-kap * di - sh);
+          a = (ep - em) / di;
+          const double a1 = (kap * (ep + em) * di - (ep - em)) / (di * di);
+          beta = a1 * q / di;
+#pragma unroll
+          for (int j = 0; j < CPL; ++j) accB[j] += beta * dl[j];
+          if (cl == 0) {
+            accA += a;
+            accK += (ep + em) * q;
+          }
+        }
+        if (cl == 0 && i < b.n) {  // the row's coefficients, contracted after the segment
+          sa[i] = a;
+          sb[i] = beta;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) red[w * kRPW + rg][cl * CPL + j] = accB[j];
+  accA = wsum(accA);
+  accK = wsum(accK);
+  if (lane == 0) {
+    s_a[w] = accA;
+    s_k[w] = accK;
+  }
+  __syncthreads();
+  double *p = b.part + (int64_t)blockIdx.x * (d + 2);
+  for (int col = threadIdx.x; col < d + 2; col += kBlk) {
+    double v = 0.0;
+    if (col < d) {
+#pragma unroll
+      for (int q = 0; q < kNW * kRPW; ++q) v += red[q][col];
+    } else if (col == d) {
+      v = (s_a[0] + s_a[1]) + (s_a[2] + s_a[3]);
+    } else {
+      v = (s_k[0] + s_k[1]) + (s_k[2] + s_k[3]);
+    }
+    p[col] = v;
+  }
+}
+
+// ---- the rows' share of a walked-back segment, slots [jlo, jhi):
+// grad_i += sum_j a_{j,i} lambda_W(j) + beta_{j,i} (v_i - c(j)).  A workgroup
+// holds the segment's lambda_W and c for its 64 columns in LDS; each wave
+// takes one row at a time, a lane one column.
+template <typename P>
+__global__ __launch_bounds__(kBlk) void seg_contract(Buffers b, int jlo, int jhi) {
+  __shared__ double s_l[kSegment][kW], s_c[kSegment][kW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
+  const int col = blockIdx.y * kW + lane;
+  for (int k = threadIdx.x; k < (jhi - jlo) * kW; k += kBlk) {
+    const int j = jlo + k / kW, cc = blockIdx.y * kW + (k % kW);
+    s_l[j][k % kW] = cc < d ? b.lw[(int64_t)j * d + cc] : 0.0;
+    s_c[j][k % kW] = cc < d ? b.tc[(int64_t)j * d + cc] : 0.0;
+  }
+  __syncthreads();
+  if (col >= d) return;
+  for (int64_t i = (int64_t)blockIdx.x * kNW + w; i < b.n; i += (int64_t)gridDim.x * kNW) {
+    const double x = xval<P>(b, i, col);
+    double acc = 0.0;
+#pragma unroll 5
+    for (int j = jlo; j < jhi; ++j) {
+      const double a = b.sa[(int64_t)j * b.n + i], be = b.sb[(int64_t)j * b.n + i];
+      acc += a * s_l[j][lane] + be * (x - s_c[j][lane]);
+    }
+    b.gacc[i * b.d + col] += acc;
+  }
+}
+
+// ---- reverse epilogue of iteration t: v1's share, the D share, lambda_{t-1}.
+__global__ __launch_bounds__(kEpi) void bwd_epi(Buffers b, int slot, int64_t t) {
+  __shared__ double s_P[kMaxCols + 2], tmp[kEpi];
+  const int tid = threadIdx.x, d = (int)b.d;
+  if (t >= 2) reduce_parts<kEpi>(b.part, b.grid, d + 2, s_P, tmp);
+  for (int col = tid; col < d; col += kEpi) {
     const double lam = b.lam[col];
     b.gv1[col] += lam;
     if (t >= 2) {
-      const double lc = -s_P[d] * s_lw[col] - s_P[col];
+      const double lc = -s_P[d] * b.lw[(int64_t)slot * d + col] - s_P[col];
       b.lam[col] = lam + lc / (double)(t - 1);
     }
   }
@@ -409,14 +615,14 @@ __global__ __launch_bounds__(kBlk) void round_kernel(const double *src, float *d
     dst[k] = (float)src[k];
 }
 
-template <typename P, int PER>
+template <typename P, int PER, bool ROWS>
 hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
   const int G = b.grid;
   const int64_t T = b.T;
   hipError_t e = hipMemsetAsync(b.gacc, 0, (size_t)b.n * b.d * sizeof(double), s);
   if (e != hipSuccess) return e;
   init_kernel<P><<<1, kBlk, 0, s>>>(b);
-  far_pass<P, PER><<<G, kBlk, 0, s>>>(b, b.ubar, b.v1);
+  far_pass<P, ROWS ? 1 : PER><<<G, kBlk, 0, s>>>(b, b.ubar, b.v1);
   far_final<<<1, kW, 0, s>>>(b, 1);
   const int64_t nseg = (T + kSegment - 1) / kSegment;
   // forward, storing S every kSegment iterations
@@ -425,12 +631,15 @@ hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
     seg_init<P><<<1, kBlk, 0, s>>>(b, t0);
     for (int64_t t = t0 + 1; t <= t1; ++t) {
       const int slot = (int)(t - t0 - 1);
-      fwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
-      fwd_epi<P><<<1, kBlk, 0, s>>>(b, slot, t, 1);
+      if constexpr (ROWS)
+        fwd_rows<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+      else
+        fwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+      fwd_epi<P><<<1, kEpi, 0, s>>>(b, slot, t, 1);
     }
   }
   mean_kernel<<<1, kBlk, 0, s>>>(b);
-  far_pass<P, PER><<<G, kBlk, 0, s>>>(b, b.ubar, -1);
+  far_pass<P, ROWS ? 1 : PER><<<G, kBlk, 0, s>>>(b, b.ubar, -1);
   far_final<<<1, kW, 0, s>>>(b, 0);
   lambda_init<P><<<1, kBlk, 0, s>>>(b, gv);
   // reverse, one segment at a time: recompute its tape, then walk it back
@@ -439,14 +648,25 @@ hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
     seg_init<P><<<1, kBlk, 0, s>>>(b, t0);
     for (int64_t t = t0 + 1; t <= t1; ++t) {
       const int slot = (int)(t - t0 - 1);
-      fwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
-      fwd_epi<P><<<1, kBlk, 0, s>>>(b, slot, t, 0);
+      if constexpr (ROWS)
+        fwd_rows<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+      else
+        fwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+      fwd_epi<P><<<1, kEpi, 0, s>>>(b, slot, t, 0);
     }
     for (int64_t t = t1; t > t0; --t) {
       const int slot = (int)(t - t0 - 1);
-      if (t >= 2) bwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
-      bwd_epi<<<1, kBlk, 0, s>>>(b, slot, t);
+      if (t >= 2) {
+        if constexpr (ROWS)
+          bwd_rows<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+        else
+          bwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+      }
+      bwd_epi<<<1, kEpi, 0, s>>>(b, slot, t);
     }
+    const int jlo = t0 == 0 ? 1 : 0, jhi = (int)(t1 - t0);  // slots of t >= 2
+    if (jhi > jlo)
+      seg_contract<P><<<dim3(G, (unsigned)((b.d + kW - 1) / kW)), kBlk, 0, s>>>(b, jlo, jhi);
   }
   final_kernel<P><<<1, kBlk, 0, s>>>(b, gv);
   round_kernel<<<G, kBlk, 0, s>>>(b.gacc, b.grad, b.n * b.d);
@@ -455,11 +675,14 @@ hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
 
 template <typename P>
 hipError_t run_per(const Buffers &b, double gv, hipStream_t s) {
+  // d <= 64: 16 lanes per row with 1, 2 or 4 columns each; else 64 lanes per row
+  if (b.d <= 16) return run_typed<P, 1, true>(b, gv, s);
+  if (b.d <= 32) return run_typed<P, 2, true>(b, gv, s);
+  if (b.d <= 64) return run_typed<P, 4, true>(b, gv, s);
   const int64_t per = (b.d + kW - 1) / kW;
-  if (per <= 1) return run_typed<P, 1>(b, gv, s);
-  if (per <= 2) return run_typed<P, 2>(b, gv, s);
-  if (per <= 4) return run_typed<P, 4>(b, gv, s);
-  return run_typed<P, 8>(b, gv, s);
+  if (per <= 2) return run_typed<P, 2, false>(b, gv, s);
+  if (per <= 4) return run_typed<P, 4, false>(b, gv, s);
+  return run_typed<P, 8, false>(b, gv, s);
 }
 
 hipError_t run_backward(const Buffers &b, double gv, hipStream_t s) {

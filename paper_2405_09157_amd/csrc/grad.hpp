@@ -32,6 +32,8 @@ struct Buffers {
   double *tc, *tw, *ts;
   double *part;      // grid x (d + 2) per-workgroup partial sums
   double *lam;       // adjoint of S_t
+  double *lw;        // lambda_W of each slot of the segment (kSegment x d)
+  double *sa, *sb;   // a_i and beta_i of each slot and row (kSegment x n each)
   double *gv1;       // accumulated adjoint of v1 from u(t) = v1 + ...
   double *ubar;      // ubar_T
   double *misc;      // [0] adjoint of D, [1] R, [2] D (recomputed), [3..4] scratch

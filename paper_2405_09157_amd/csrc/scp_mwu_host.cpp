@@ -612,15 +612,15 @@ int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points, doub
   b.grid = (int)std::max<int64_t>(1, std::min<int64_t>(4 * (int64_t)std::max(cus, 1), (c->n + 63) / 64));
   const int64_t d = c->d, K = grad::kSegment;
   const int64_t sizes[] = {d, grad::ck_count(c->T) * d, (K + 1) * d, K * d, (K + 1) * 4,
-                           (int64_t)b.grid * (d + 2), d, d, d, 8, 2, c->n * d};
+                           (int64_t)b.grid * (d + 2), d, K * d, d, d, 8, K * c->n, K * c->n, 2, c->n * d};
   int64_t total = 0;
   for (int64_t v : sizes) total += (v + 31) / 32 * 32;
   void *mem = nullptr;
   if (hipMalloc(&mem, (size_t)total * sizeof(double)) != hipSuccess)
     return c->fail(SCP_MWU_E_NOMEM, "backward workspace");
   double *p = (double *)mem;
-  double **dst[] = {&b.S, &b.ck, &b.tc, &b.tw, &b.ts, &b.part, &b.lam, &b.gv1, &b.ubar, &b.misc};
-  for (int k = 0; k < 10; ++k) {
+  double **dst[] = {&b.S, &b.ck, &b.tc, &b.tw, &b.ts, &b.part, &b.lam, &b.lw, &b.gv1, &b.ubar, &b.misc, &b.sa, &b.sb};
+  for (int k = 0; k < 13; ++k) {
     *dst[k] = p;
     p += (sizes[k] + 31) / 32 * 32;
   }
