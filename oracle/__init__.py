@@ -12,7 +12,8 @@ Modules
 eja      Euclidean Jordan algebra of the second-order cone and the orthant:
          Jordan product, spectral decomposition, trace, Loewner exponential
          (Section 2.1).
-scmwu    The SCMWU online learner over product cones (Section 2.3, eq. SCMWU).
+scmwu    The SCMWU online learner over product cones (Section 2.3, eq. SCMWU),
+         including a product of an orthant and Lorentz blocks of mixed sizes.
 ses      Smallest enclosing sphere via the max-form meta-algorithm
          (Section 3 with Section 4.1): alpha-FTP loop, closed-form ORACLE,
          monitor f(t), early stopping (Section 5), adaptive alpha search.

@@ -60,3 +60,36 @@ def orthant_run(losses, eta: float):
         out.append(orthant_iterate(m, eta))
         m = m + l
     return out
+
+
+def product_iterate(m: np.ndarray, n_orth: int, offsets, eta: float):
+    """p = exp(-eta m) / Tr(exp(-eta m)) over the product cone
+    R^{n_orth}_+ (+) Q^{d_1+1} (+) ... (+) Q^{d_k+1} (Section 2.1: the Loewner
+    exponential and the trace of a direct sum act blockwise).
+
+    m holds the orthant coordinates first, then block j in
+    m[offsets[j]:offsets[j+1]] as its vector part followed by its scalar part
+    (offsets[0] = n_orth).  One shift, the largest eigenvalue over all blocks,
+    keeps the exponentials in range and cancels in the normalisation.
+    Returns (p, logC) with logC = ln Tr(exp(-eta m))."""
+    m = np.asarray(m, dtype=np.float64)
+    x = -eta * m
+    xo = x[:n_orth]
+    blocks = [(x[offsets[j]:offsets[j + 1] - 1], x[offsets[j + 1] - 1]) for j in range(len(offsets) - 1)]
+    lam = [float(np.max(xo))] if n_orth > 0 else []
+    for U, u0 in blocks:
+        l1, _, _ = eja.soc_spectral_blocks(U[None, :], np.array([u0]))
+        lam.append(float(l1[0]))
+    shift = max(lam)
+    p = np.empty_like(x)
+    tr = 0.0
+    if n_orth > 0:
+        e = eja.orthant_exp(xo, shift)
+        p[:n_orth] = e
+        tr += float(np.sum(e))
+    for j, (U, u0) in enumerate(blocks):
+        W, s = eja.soc_exp_blocks(U[None, :], np.array([u0]), shift)
+        p[offsets[j]:offsets[j + 1] - 1] = W[0]
+        p[offsets[j + 1] - 1] = s[0]
+        tr += float(eja.soc_trace_blocks(s)[0])
+    return p / tr, shift + float(np.log(tr))
