@@ -419,6 +419,27 @@ void scp_mwu_batch_destroy(scp_mwu_batch *b);
 const char *scp_mwu_batch_last_error(const scp_mwu_batch *b);
 
 /*
+ * The SCMWU iterate over a general product cone (eq.(SCMWU); Section 2.1:
+ * the Loewner exponential and the trace of a direct sum act blockwise):
+ * p = exp(-eta m) / Tr(exp(-eta m)) on K = R^{n_orth}_+ (+) Q^{d_1+1} (+) ...
+ * (+) Q^{d_k+1}, in the Jordan algebra whose identity is (0; sqrt2) on each
+ * Lorentz block (eigenvalues (x0 +- ||xbar||)/sqrt2, trace sqrt2 x0).
+ * m (device, binary64): the cumulative loss; the orthant coordinates first,
+ *   then block j in [offsets[j], offsets[j+1]) as its vector part (d_j
+ *   values) followed by its scalar part.
+ * offsets (host, nblocks + 1 values; may be NULL when nblocks = 0):
+ *   offsets[0] = n_orth, each block at least 2 long (d_j >= 1).
+ * p (device, binary64, same layout and length as m; caller-owned; may not
+ *   alias m): the normalised iterate, trace one.
+ * log_trace (host, may be NULL): ln Tr(exp(-eta m)).
+ * Enqueued on stream (a hipStream_t; NULL = default) and waited for.
+ * E_INVAL (NULL m or p, n_orth < 0, nblocks < 0, an empty cone, eta not a
+ * positive finite number, bad offsets), E_NOMEM, E_HIP.
+ */
+int scp_mwu_product_exp(const double *m, int64_t n_orth, const int64_t *offsets, int64_t nblocks,
+                        double eta, double *p, double *log_trace, void *stream);
+
+/*
  * Round n FP32 values to BF16 (nearest, ties to even; NaN stays NaN) on the
  * device: src (device, n floats) -> dst (device, n uint16).  The storage
  * conversion init uses; exported so callers can build BF16 inputs.

@@ -27,7 +27,7 @@ OUTCOME_NAMES = {0: "running", 1: "separated", 2: "beat_alpha", 3: "stabilized",
                  4: "t_reached", 5: "numeric"}
 
 # symbols the header declares (checked by the CPU test suite)
-EXPORTS = ("scp_mwu_init", "scp_mwu_step", "scp_mwu_solve", "scp_mwu_backward",
+EXPORTS = ("scp_mwu_init", "scp_mwu_step", "scp_mwu_solve", "scp_mwu_backward", "scp_mwu_product_exp",
            "scp_mwu_get_state", "scp_mwu_set_state", "scp_mwu_get_vector", "scp_mwu_get_D",
            "scp_mwu_destroy", "scp_mwu_last_error", "scp_mwu_strerror", "scp_mwu_cast_bf16",
            "scp_mwu_time_passes", "scp_mwu_read_reference", "scp_mwu_quantize_fp8",
@@ -136,6 +136,7 @@ def load() -> ctypes.CDLL:
         "scp_mwu_step": (i32, [vp, f64, i64, i32, i32, P(scp_mwu_stepinfo)]),
         "scp_mwu_solve": (i32, [vp, P(scp_mwu_result), P(f64)]),
         "scp_mwu_backward": (i32, [vp, f64, P(ctypes.c_float), P(f64)]),
+        "scp_mwu_product_exp": (i32, [vp, i64, P(i64), i64, f64, vp, P(f64), vp]),
         "scp_mwu_get_state": (i32, [vp, P(f64), P(i64)]),
         "scp_mwu_set_state": (i32, [vp, f64, i64, i64, P(f64)]),
         "scp_mwu_get_vector": (i32, [vp, i32, P(f64)]),
@@ -206,6 +207,17 @@ def scp_mwu_backward(ctx, grad_value: float, grad_points_ptr: int) -> float:
     _check(load().scp_mwu_backward(ctx, grad_value, ctypes.cast(grad_points_ptr, ctypes.POINTER(ctypes.c_float)),
                                    ctypes.byref(value)), ctx)
     return value.value
+
+
+def scp_mwu_product_exp(m_ptr: int, n_orth: int, offsets, eta: float, p_ptr: int, stream: int = 0) -> float:
+    """p = exp(-eta m) / Tr(...) over R^{n_orth}_+ (+) Lorentz blocks at `offsets`; returns ln Tr."""
+    k = max(len(offsets) - 1, 0)
+    off = (ctypes.c_int64 * max(len(offsets), 1))(*offsets) if offsets else None
+    lt = ctypes.c_double()
+    code = load().scp_mwu_product_exp(m_ptr, int(n_orth), off, k, float(eta), p_ptr, ctypes.byref(lt), stream)
+    if code != SCP_MWU_OK:
+        raise ScpMwuError(code, "scp_mwu_product_exp: " + load().scp_mwu_strerror(code).decode())
+    return lt.value
 
 
 def scp_mwu_get_state(ctx, d: int, svm: bool):

@@ -252,6 +252,28 @@ class MWUBatch:
         return L.scp_mwu_batch_time_iters(self.b, int(k))
 
 
+def product_exp(m, n_orth: int, dims, eta: float, out=None):
+    """The SCMWU iterate exp(-eta m) / Tr(...) over R^{n_orth}_+ (+) Q^{d+1} for
+    each d in dims, m a float64 device vector (orthant coordinates, then each
+    block's vector part and scalar part).  Returns (p, ln Tr)."""
+    import torch
+    L.load()
+    if not m.is_cuda or m.dtype != torch.float64 or m.dim() != 1 or not m.is_contiguous():
+        raise ValueError("m must be a contiguous float64 device vector")
+    offsets = [int(n_orth)]
+    for d in dims:
+        offsets.append(offsets[-1] + int(d) + 1)
+    if offsets[-1] != m.numel():
+        raise ValueError("m's length does not match n_orth and dims")
+    if out is None:
+        out = torch.empty_like(m)
+    stream = torch.cuda.current_stream(m.device).cuda_stream
+    with torch.cuda.device(m.device):
+        lt = L.scp_mwu_product_exp(m.data_ptr(), int(n_orth), offsets if dims else [], float(eta),
+                                   out.data_ptr(), stream)
+    return out, lt
+
+
 def _radius_function():
     import torch
 

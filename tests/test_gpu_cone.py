@@ -1,0 +1,91 @@
+"""GPU parity of the product-cone SCMWU iterate (scp_mwu_product_exp) against
+the oracle's scmwu.product_iterate.
+
+Tolerance: both sides are binary64; the kernel differs by summation order
+(the trace over up to ~1e6 terms, ||xbar|| over a block) and by the exp/log
+implementations (a few ulp).  An eigenvalue of size L then moves by a few
+2^-53 L, and its exponential by that much relative, so elements agree to
+1e-14 (1 + L_max) relative to the largest element and ln Tr to
+1e-14 (1 + L_max) absolute (L_max the largest |eigenvalue| of -eta m)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import scmwu
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = 1e-12
+
+
+def layout(n_orth, dims):
+    offs = [n_orth]
+    for d in dims:
+        offs.append(offs[-1] + d + 1)
+    return offs
+
+
+def run(m, n_orth, dims, eta):
+    import torch
+    import paper_2405_09157_amd as scp
+    p, lt = scp.product_exp(torch.from_numpy(m).cuda(), n_orth, dims, eta)
+    return p.cpu().numpy(), lt
+
+
+CASES = {
+    "orthant": (1000, []),
+    "soc_equal": (0, [3] * 50),
+    "mixed": (7, [1, 2, 3, 5, 64, 65, 200]),
+    "one_big_block": (0, [5000]),
+    "many_small": (3, [2] * 10000),
+    "large_orthant": (300_000, [8] * 100),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("scale", [1.0, 300.0])
+def test_product_exp_vs_oracle(name, scale):
+    n_orth, dims = CASES[name]
+    offs = layout(n_orth, dims)
+    rng = np.random.default_rng(list(CASES).index(name))
+    m = rng.standard_normal(offs[-1]) * scale
+    eta = 0.37
+    p, lt = run(m, n_orth, dims, eta)
+    p0, lt0 = scmwu.product_iterate(m, n_orth, offs, eta)
+    lam = [eta * float(np.abs(m[:n_orth]).max())] if n_orth else []
+    for j in range(len(dims)):
+        lam.append(eta * (abs(m[offs[j + 1] - 1]) + float(np.linalg.norm(m[offs[j]:offs[j + 1] - 1]))) / math.sqrt(2))
+    tol = 1e-14 * (1.0 + max(lam))
+    assert np.abs(p - p0).max() <= tol * np.abs(p0).max()
+    assert abs(lt - lt0) <= tol
+    tr = p[:n_orth].sum() + sum(math.sqrt(2) * p[offs[j + 1] - 1] for j in range(len(dims)))
+    assert abs(tr - 1.0) <= 1e-12
+
+
+def test_zero_vector_parts():
+    n_orth, dims = 2, [3, 4]
+    offs = layout(n_orth, dims)
+    m = np.zeros(offs[-1])
+    m[offs[1] - 1], m[offs[2] - 1] = 1.5, -0.5
+    p, lt = run(m, n_orth, dims, 1.0)
+    p0, lt0 = scmwu.product_iterate(m, n_orth, offs, 1.0)
+    assert np.abs(p - p0).max() <= TIGHT and abs(lt - lt0) <= TIGHT
+    assert np.all(p[offs[0]:offs[1] - 1] == 0.0) and np.all(p[offs[1]:offs[2] - 1] == 0.0)
+
+
+def test_product_exp_errors():
+    import torch
+    import paper_2405_09157_amd as scp
+    from paper_2405_09157_amd import _lib
+    m = torch.zeros(10, dtype=torch.float64, device="cuda")
+    p = torch.empty_like(m)
+    for offs, n0, eta in (([3, 4, 10], 3, 1.0),     # a block of length 1
+                          ([2, 6, 10], 3, 1.0),     # offsets[0] != n_orth
+                          ([3, 10], 3, 0.0),        # eta <= 0
+                          ([3, 10], 3, float("inf"))):
+        with pytest.raises(scp.ScpMwuError) as e:
+            _lib.scp_mwu_product_exp(m.data_ptr(), n0, offs, eta, p.data_ptr())
+        assert e.value.code == scp.SCP_MWU_E_INVAL
+    with pytest.raises(scp.ScpMwuError):
+        _lib.scp_mwu_product_exp(m.data_ptr(), 0, [], 1.0, p.data_ptr())   # empty cone
