@@ -221,9 +221,10 @@ GRAD = dict(name="ses_grad_200k_d64_T2000", n=200_000, d=64, T=2000, seed=0)
 
 def gradient(reps=3):
     """Reverse pass of the radius after T fixed-alpha iterations (FP32 points
-    N(0, I), alpha = 2D/3): wall time of scp_mwu_backward (forward with
-    stored running sums, per-segment recomputation, reverse iterations) and,
-    beside it, T forward iterations of the streaming pass at the same alpha."""
+    N(0, I), alpha = 2D/3): wall time of scp_mwu_backward with running sums
+    kept every 50 iterations (forward, per-segment recomputation, reverse
+    iterations), of the same call keeping the whole tape, and, beside them,
+    T forward iterations of the streaming pass at the same alpha."""
     import numpy as np
     import torch
     import paper_2405_09157_amd as scp
@@ -242,6 +243,13 @@ def gradient(reps=3):
             t0 = time.perf_counter()
             m.backward(1.0, out)
             times.append(time.perf_counter() - t0)
+        m.backward(1.0, out, checkpoint_every=0)       # warm-up of the whole-tape mode
+        times_full = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            m.backward(1.0, out, checkpoint_every=0)
+            times_full.append(time.perf_counter() - t0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         m.step(alpha, g["T"], g["T"], reset=True)
@@ -252,6 +260,8 @@ def gradient(reps=3):
                 storage="f32", radius=R, backward_s=round(bwd, 4),
                 reverse_iters_per_s=round(g["T"] / bwd, 1),
                 forward_s=round(fwd, 4), backward_over_forward=round(bwd / fwd, 2),
+                whole_tape=dict(backward_s=round(min(times_full), 4),
+                                reverse_iters_per_s=round(g["T"] / min(times_full), 1)),
                 grad_abs_sum=float(out.abs().sum()))
 
 

@@ -238,9 +238,13 @@ int scp_mwu_solve(scp_mwu_ctx *ctx, scp_mwu_result *res, double *y);
  * kappa_t = eta (t - 1) / (3D) and D = max_i ||v1 - v_i|| recomputed from the
  * points, and returns R = max_i ||v_i - ubar_T|| (the Section 5 monitor at the
  * final mean); R is differentiable where both maxima are attained once.
- * The call recomputes the forward iterations, keeping the running sum every
- * 50 iterations, then walks each 50-iteration segment back after recomputing
- * it: three streaming passes over the points per iteration.
+ * The call runs the forward iterations once, then walks them back segment by
+ * segment.  checkpoint_every = K in 1 .. 50 keeps the running sum every K
+ * iterations and recomputes each K-iteration segment before walking it back
+ * (three streaming passes over the points per iteration; device workspace
+ * about (T/K + 2K) d + 2 K n + n d binary64 values); checkpoint_every = 0
+ * keeps the whole tape of the forward run, 2d + 4 numbers per iteration (two
+ * passes per iteration; about 2 T d + 100 n + n d values).
  * Requires: an SES context on points without radii, streamed as F32 or F64
  * (no BF16/FP8 storage), d <= 512, and a current test (scp_mwu_step with
  * reset, any k >= 0): its alpha and T define the map, which always runs all
@@ -250,11 +254,13 @@ int scp_mwu_solve(scp_mwu_ctx *ctx, scp_mwu_result *res, double *y);
  * grad_points: device, n x d FP32, row stride d, owned by the caller;
  *   overwritten.
  * value (host, may be NULL): receives R as the recomputed forward found it.
- * Errors: E_INVAL (NULL grad_points, non-finite grad_value), E_UNSUPPORTED
+ * Errors: E_INVAL (NULL grad_points, non-finite grad_value, checkpoint_every
+ * outside 0 .. 50), E_UNSUPPORTED
  * (SVM, radii, BF16/FP8 storage, d > 512), E_STATE (no test started),
  * E_NOMEM, E_HIP.  Blocks until the result is written.
  */
-int scp_mwu_backward(scp_mwu_ctx *ctx, double grad_value, float *grad_points, double *value);
+int scp_mwu_backward(scp_mwu_ctx *ctx, double grad_value, float *grad_points, double *value,
+                     int32_t checkpoint_every);
 
 /*
  * Inspect or replace the running sums of the current test (checkpoint /

@@ -135,7 +135,7 @@ def load() -> ctypes.CDLL:
         "scp_mwu_init": (i32, [P(scp_mwu_desc), P(vp)]),
         "scp_mwu_step": (i32, [vp, f64, i64, i32, i32, P(scp_mwu_stepinfo)]),
         "scp_mwu_solve": (i32, [vp, P(scp_mwu_result), P(f64)]),
-        "scp_mwu_backward": (i32, [vp, f64, P(ctypes.c_float), P(f64)]),
+        "scp_mwu_backward": (i32, [vp, f64, P(ctypes.c_float), P(f64), i32]),
         "scp_mwu_product_exp": (i32, [vp, i64, P(i64), i64, f64, vp, P(f64), vp]),
         "scp_mwu_get_state": (i32, [vp, P(f64), P(i64)]),
         "scp_mwu_set_state": (i32, [vp, f64, i64, i64, P(f64)]),
@@ -201,11 +201,11 @@ def scp_mwu_solve(ctx, d: int):
     return code, res, list(y)
 
 
-def scp_mwu_backward(ctx, grad_value: float, grad_points_ptr: int) -> float:
+def scp_mwu_backward(ctx, grad_value: float, grad_points_ptr: int, checkpoint_every: int = 50) -> float:
     """grad_value * dR/dV into the device buffer at grad_points_ptr; returns R."""
     value = ctypes.c_double()
     _check(load().scp_mwu_backward(ctx, grad_value, ctypes.cast(grad_points_ptr, ctypes.POINTER(ctypes.c_float)),
-                                   ctypes.byref(value)), ctx)
+                                   ctypes.byref(value), int(checkpoint_every)), ctx)
     return value.value
 
 

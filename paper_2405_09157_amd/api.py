@@ -121,17 +121,19 @@ class MWU:
         """(pass-kernel ms, whole-iteration ms): HIP-event means over k further iterations."""
         return L.scp_mwu_time_passes(self.ctx, int(k))
 
-    def backward(self, grad_value: float = 1.0, out=None):
+    def backward(self, grad_value: float = 1.0, out=None, checkpoint_every: int = 50):
         """(R, grad_value * dR/dV) of the T-iteration map at the current
         test's alpha and T: R = max_i ||v_i - ubar_T||, the gradient an
-        n x d float32 device tensor (written into `out` when given)."""
+        n x d float32 device tensor (written into `out` when given).
+        checkpoint_every: K in 1..50 keeps the running sum every K iterations
+        and recomputes segments; 0 keeps the whole tape."""
         import torch
         if out is None:
             out = torch.empty(self.n, self.d, dtype=torch.float32, device=self.points.device)
         if out.dtype != torch.float32 or out.shape != (self.n, self.d) or not out.is_contiguous():
             raise ValueError("out must be a contiguous float32 n x d tensor")
         with torch.cuda.device(self.points.device):
-            R = L.scp_mwu_backward(self.ctx, float(grad_value), out.data_ptr())
+            R = L.scp_mwu_backward(self.ctx, float(grad_value), out.data_ptr(), int(checkpoint_every))
         return R, out
 
     def eta(self, T: int) -> float:

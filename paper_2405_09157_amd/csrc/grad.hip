@@ -1,7 +1,8 @@
 // Reverse pass of the SES radius after T fixed-alpha iterations: the adjoint
 // recursion through the unrolled iterations (Section 4.1 split, eq.(ses_oracle),
-// Section 2.1 SOC exponential), with the running sum stored every kSegment
-// iterations and each segment recomputed forward before it is reversed.
+// Section 2.1 SOC exponential), with the running sum stored every K <= 50
+// iterations and each segment recomputed forward before it is reversed, or
+// with the whole tape (O(d) numbers per iteration) kept from one forward run.
 //
 // Per iteration t (reverse order), with lambda the adjoint of S_t:
 //   lambda_W = alpha (I - What What^T) lambda / ||W_t||
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(kEpi) void fwd_epi(Buffers b, int slot, int64_t t, 
     const double cn = S / tt;
     b.tc[(int64_t)(slot + 1) * d + col] = cn;
     q += (v1c - cn) * (v1c - cn);
-    if (write_ck && t % kSegment == 0) b.ck[(t / kSegment) * d + col] = S;
+    if (write_ck && t % b.seg == 0) b.ck[(t / b.seg) * d + col] = S;
   }
   q = bsum<kEpi>(q, s_r);
   if (tid == 0) {
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(kBlk) void seg_init(Buffers b, int64_t t0) {
   const int tid = threadIdx.x, d = (int)b.d;
   double q = 0.0;
   for (int col = tid; col < d; col += kBlk) {
-    const double S = b.ck[(t0 / kSegment) * d + col];
+    const double S = b.ck[(t0 / b.seg) * d + col];
     const double v1c = xval<P>(b, b.v1, col);
     const double cn = t0 > 0 ? S / (double)t0 : v1c;
     b.S[col] = S;
@@ -624,49 +625,64 @@ hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
   init_kernel<P><<<1, kBlk, 0, s>>>(b);
   far_pass<P, ROWS ? 1 : PER><<<G, kBlk, 0, s>>>(b, b.ubar, b.v1);
   far_final<<<1, kW, 0, s>>>(b, 1);
-  const int64_t nseg = (T + kSegment - 1) / kSegment;
-  // forward, storing S every kSegment iterations
+  const int64_t K = b.seg, nseg = (T + K - 1) / K;
+  // the tape of the segment starting after iteration t0: with the whole tape
+  // kept, slot j of that segment is iteration t0 + 1 + j of one long tape
+  auto at = [&](int64_t t0) {
+    Buffers x = b;
+    if (b.full) {
+      x.tc = b.tc + t0 * b.d;
+      x.tw = b.tw + t0 * b.d;
+      x.ts = b.ts + t0 * 4;
+    }
+    return x;
+  };
+  // forward, storing S every K iterations (and, with the whole tape, every slot)
   for (int64_t sg = 0; sg < nseg; ++sg) {
-    const int64_t t0 = sg * kSegment, t1 = std::min<int64_t>(t0 + kSegment, T);
-    seg_init<P><<<1, kBlk, 0, s>>>(b, t0);
+    const int64_t t0 = sg * K, t1 = std::min<int64_t>(t0 + K, T);
+    const Buffers bx = at(t0);
+    if (!b.full || sg == 0) seg_init<P><<<1, kBlk, 0, s>>>(bx, t0);
     for (int64_t t = t0 + 1; t <= t1; ++t) {
       const int slot = (int)(t - t0 - 1);
       if constexpr (ROWS)
-        fwd_rows<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+        fwd_rows<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
       else
-        fwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
-      fwd_epi<P><<<1, kEpi, 0, s>>>(b, slot, t, 1);
+        fwd_pass<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
+      fwd_epi<P><<<1, kEpi, 0, s>>>(bx, slot, t, 1);
     }
   }
   mean_kernel<<<1, kBlk, 0, s>>>(b);
   far_pass<P, ROWS ? 1 : PER><<<G, kBlk, 0, s>>>(b, b.ubar, -1);
   far_final<<<1, kW, 0, s>>>(b, 0);
   lambda_init<P><<<1, kBlk, 0, s>>>(b, gv);
-  // reverse, one segment at a time: recompute its tape, then walk it back
+  // reverse, one segment at a time: recompute its tape (unless kept), then walk it back
   for (int64_t sg = nseg - 1; sg >= 0; --sg) {
-    const int64_t t0 = sg * kSegment, t1 = std::min<int64_t>(t0 + kSegment, T);
-    seg_init<P><<<1, kBlk, 0, s>>>(b, t0);
-    for (int64_t t = t0 + 1; t <= t1; ++t) {
-      const int slot = (int)(t - t0 - 1);
-      if constexpr (ROWS)
-        fwd_rows<P, PER><<<G, kBlk, 0, s>>>(b, slot);
-      else
-        fwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
-      fwd_epi<P><<<1, kEpi, 0, s>>>(b, slot, t, 0);
+    const int64_t t0 = sg * K, t1 = std::min<int64_t>(t0 + K, T);
+    const Buffers bx = at(t0);
+    if (!b.full) {
+      seg_init<P><<<1, kBlk, 0, s>>>(bx, t0);
+      for (int64_t t = t0 + 1; t <= t1; ++t) {
+        const int slot = (int)(t - t0 - 1);
+        if constexpr (ROWS)
+          fwd_rows<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
+        else
+          fwd_pass<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
+        fwd_epi<P><<<1, kEpi, 0, s>>>(bx, slot, t, 0);
+      }
     }
     for (int64_t t = t1; t > t0; --t) {
       const int slot = (int)(t - t0 - 1);
       if (t >= 2) {
         if constexpr (ROWS)
-          bwd_rows<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+          bwd_rows<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
         else
-          bwd_pass<P, PER><<<G, kBlk, 0, s>>>(b, slot);
+          bwd_pass<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
       }
-      bwd_epi<<<1, kEpi, 0, s>>>(b, slot, t);
+      bwd_epi<<<1, kEpi, 0, s>>>(bx, slot, t);
     }
     const int jlo = t0 == 0 ? 1 : 0, jhi = (int)(t1 - t0);  // slots of t >= 2
     if (jhi > jlo)
-      seg_contract<P><<<dim3(G, (unsigned)((b.d + kW - 1) / kW)), kBlk, 0, s>>>(b, jlo, jhi);
+      seg_contract<P><<<dim3(G, (unsigned)((b.d + kW - 1) / kW)), kBlk, 0, s>>>(bx, jlo, jhi);
   }
   final_kernel<P><<<1, kBlk, 0, s>>>(b, gv);
   round_kernel<<<G, kBlk, 0, s>>>(b.gacc, b.grad, b.n * b.d);
@@ -686,7 +702,8 @@ hipError_t run_per(const Buffers &b, double gv, hipStream_t s) {
 }
 
 hipError_t run_backward(const Buffers &b, double gv, hipStream_t s) {
-  if (b.d < 1 || b.d > kMaxCols || b.n < 2 || b.T < 1 || b.grid < 1) return hipErrorInvalidValue;
+  if (b.d < 1 || b.d > kMaxCols || b.n < 2 || b.T < 1 || b.grid < 1 || b.seg < 1 || b.seg > kSegment)
+    return hipErrorInvalidValue;
   return b.dtype == 1 ? run_per<double>(b, gv, s) : run_per<float>(b, gv, s);
 }
 

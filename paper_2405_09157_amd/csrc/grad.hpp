@@ -15,7 +15,7 @@
 namespace scpmwu {
 namespace grad {
 
-constexpr int kSegment = 50;  // iterations between stored running sums
+constexpr int kSegment = 50;  // the longest segment (iterations between stored running sums)
 
 // Device buffers of one reverse pass (allocated by the host for one call).
 struct Buffers {
@@ -24,16 +24,17 @@ struct Buffers {
   const void *X;
   double alpha, eta;     // kappa_t = eta (t - 1) / (3D), D recomputed on the device
   int grid;
-  // running sum and its checkpoints S_{k * kSegment}
+  int seg;           // segment length K (1 .. kSegment)
+  int full;          // 1: the tape holds all T iterations (no recomputation)
+  // running sum and its checkpoints S_{j K}
   double *S, *ck;
-  // tape of one segment, slot j = iteration t0 + 1 + j:
-  //   tc: c_t (kSegment + 1 slots), tw: W_t/||W_t|| (kSegment slots),
-  //   ts: {kappa_t, s_t, ||W_t||, 0} (kSegment + 1 slots)
+  // tape of one segment (K slots; all T with `full`), slot j = iteration t0 + 1 + j:
+  //   tc: c_t (one slot more), tw: W_t/||W_t||, ts: {kappa_t, s_t, ||W_t||, 0} (one slot more)
   double *tc, *tw, *ts;
   double *part;      // grid x (d + 2) per-workgroup partial sums
   double *lam;       // adjoint of S_t
-  double *lw;        // lambda_W of each slot of the segment (kSegment x d)
-  double *sa, *sb;   // a_i and beta_i of each slot and row (kSegment x n each)
+  double *lw;        // lambda_W of each slot of the segment (K x d)
+  double *sa, *sb;   // a_i and beta_i of each slot and row (K x n each)
   double *gv1;       // accumulated adjoint of v1 from u(t) = v1 + ...
   double *ubar;      // ubar_T
   double *misc;      // [0] adjoint of D, [1] R, [2] D (recomputed), [3..4] scratch
@@ -43,7 +44,7 @@ struct Buffers {
 };
 
 // Sizes of the buffers (in doubles) for given d, T.
-inline int64_t ck_count(int64_t T) { return T / kSegment + 2; }
+inline int64_t ck_count(int64_t T, int64_t K) { return T / K + 2; }
 
 // Launch the whole reverse pass (forward with checkpoints, reverse segments,
 // the terms of R and D) on stream s.  grad_value scales the result.

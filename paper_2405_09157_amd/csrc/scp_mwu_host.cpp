@@ -584,10 +584,13 @@ int scp_mwu_get_vector(scp_mwu_ctx *c, int32_t which, double *y) {
   return SCP_MWU_OK;
 }
 
-int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points, double *value) {
+int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points, double *value,
+                     int32_t checkpoint_every) {
   if (!c) return SCP_MWU_E_INVAL;
   if (!grad_points) return c->fail(SCP_MWU_E_INVAL, "grad_points is NULL");
   if (!std::isfinite(grad_value)) return c->fail(SCP_MWU_E_INVAL, "grad_value is not finite");
+  if (checkpoint_every < 0 || checkpoint_every > grad::kSegment)
+    return c->fail(SCP_MWU_E_INVAL, "checkpoint_every must be 0 (keep the whole tape) or 1 .. 50");
   if (c->problem != kSES || c->radii)
     return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: SES on point sets only");
   if (c->dtype != kF32 && c->dtype != kF64)
@@ -610,8 +613,11 @@ int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points, doub
   b.eta = c->eta;
   // four workgroups per CU, at least 64 rows per workgroup
   b.grid = (int)std::max<int64_t>(1, std::min<int64_t>(4 * (int64_t)std::max(cus, 1), (c->n + 63) / 64));
-  const int64_t d = c->d, K = grad::kSegment;
-  const int64_t sizes[] = {d, grad::ck_count(c->T) * d, (K + 1) * d, K * d, (K + 1) * 4,
+  const bool full = checkpoint_every == 0;
+  b.full = full ? 1 : 0;
+  b.seg = full ? grad::kSegment : checkpoint_every;
+  const int64_t d = c->d, K = b.seg, L = full ? c->T : K;  // tape slots
+  const int64_t sizes[] = {d, grad::ck_count(c->T, K) * d, (L + 1) * d, L * d, (L + 1) * 4,
                            (int64_t)b.grid * (d + 2), d, K * d, d, d, 8, K * c->n, K * c->n, 2, c->n * d};
   int64_t total = 0;
   for (int64_t v : sizes) total += (v + 31) / 32 * 32;

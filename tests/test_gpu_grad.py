@@ -49,11 +49,11 @@ def points(n, d, seed, dtype):
     return t, V.astype(np.float64)
 
 
-def gpu_grad(X, alpha, T, v1=0, gv=1.0):
+def gpu_grad(X, alpha, T, v1=0, gv=1.0, checkpoint_every=50):
     import paper_2405_09157_amd as scp
     with scp.MWU(X, "ses", v1=v1, flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP) as m:
         m.step(alpha, T, 0, reset=True)
-        R, g = m.backward(gv)
+        R, g = m.backward(gv, checkpoint_every=checkpoint_every)
         return R, g.cpu().double().numpy()
 
 
@@ -63,6 +63,21 @@ def test_backward_vs_oracle(case):
     X, V = points(n, d, seed, dtype)
     alpha = 2.0 * oses.setup(V, None, v1).D / 3.0
     R, G = gpu_grad(X, alpha, T, v1)
+    R0, G0 = ses_grad.radius_grad(V, alpha, T, v1)
+    assert abs(R - R0) <= TIGHT * R0
+    assert np.abs(G - G0).max() <= GRAD_TOL * np.abs(G0).max()
+
+
+@pytest.mark.parametrize("case", [(200, 5, 123, 1, 0, "f32"), (2000, 64, 60, 2, 0, "f32"), (300, 100, 77, 5, 2, "f64")],
+                         ids=lambda c: "n%d_d%d_T%d" % c[:3])
+@pytest.mark.parametrize("every", [0, 1, 7, 50])
+def test_backward_checkpoint_modes(case, every):
+    """The whole tape (0) and running sums every K = 1, 7, 50 iterations with
+    recomputed segments give the oracle's gradient."""
+    n, d, T, seed, v1, dtype = case
+    X, V = points(n, d, seed, dtype)
+    alpha = 2.0 * oses.setup(V, None, v1).D / 3.0
+    R, G = gpu_grad(X, alpha, T, v1, checkpoint_every=every)
     R0, G0 = ses_grad.radius_grad(V, alpha, T, v1)
     assert abs(R - R0) <= TIGHT * R0
     assert np.abs(G - G0).max() <= GRAD_TOL * np.abs(G0).max()
@@ -99,6 +114,10 @@ def test_backward_errors():
         with pytest.raises(scp.ScpMwuError) as e:
             scp.scp_mwu_backward(m.ctx, float("nan"), out.data_ptr())
         assert e.value.code == scp.SCP_MWU_E_INVAL
+        for every in (-1, 51):
+            with pytest.raises(scp.ScpMwuError) as e:
+                scp.scp_mwu_backward(m.ctx, 1.0, out.data_ptr(), every)
+            assert e.value.code == scp.SCP_MWU_E_INVAL
     with scp.MWU(X, "ses", storage="bf16") as m:
         m.step(1.0, 10, 0, reset=True)
         with pytest.raises(scp.ScpMwuError) as e:
