@@ -314,7 +314,33 @@ __device__ __forceinline__ double gsum16(double v) {
   return v;
 }
 
-template <typename P, int CPL>
+// The CPL columns of row i a lane holds (its centre values for a row past n
+// or a column past d).  V4: float points, CPL = 4, d and the row stride
+// multiples of 4 and a 16-byte aligned base, so one 16-byte load per row.
+template <typename P, int CPL, bool V4>
+__device__ __forceinline__ void load_cols(const Buffers &b, int64_t i, int cl, const double *cr, double *x) {
+  const int d = (int)b.d;
+  if constexpr (V4) {
+    if (i < b.n && cl * 4 < d) {
+      const float4 v = *(const float4 *)((const float *)b.X + i * b.ld + cl * 4);
+      x[0] = v.x;
+      x[1] = v.y;
+      x[2] = v.z;
+      x[3] = v.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] = cr[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const int col = cl * CPL + j;
+      x[j] = (i < b.n && col < d) ? xval<P>(b, i, col) : cr[j];
+    }
+  }
+}
+
+template <typename P, int CPL, bool V4>
 __global__ __launch_bounds__(kBlk) void fwd_rows(Buffers b, int slot) {
   __shared__ double red[kNW * kRPW][kLPR * CPL];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
@@ -333,14 +359,7 @@ __global__ __launch_bounds__(kBlk) void fwd_rows(Buffers b, int slot) {
     for (int64_t wb = ((int64_t)blockIdx.x * kNW + w) * kRPW; wb < b.n; wb += kRB * wstride) {
       double x[kRB][CPL];
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
-        const int64_t i = wb + r * wstride + rg;
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-          const int col = cl * CPL + j;
-          x[r][j] = (i < b.n && col < d) ? xval<P>(b, i, col) : cr[j];
-        }
-      }
+      for (int r = 0; r < kRB; ++r) load_cols<P, CPL, V4>(b, wb + r * wstride + rg, cl, cr, x[r]);
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         const int64_t i = wb + r * wstride + rg;
@@ -372,7 +391,7 @@ __global__ __launch_bounds__(kBlk) void fwd_rows(Buffers b, int slot) {
   }
 }
 
-template <typename P, int CPL>
+template <typename P, int CPL, bool V4>
 __global__ __launch_bounds__(kBlk) void bwd_rows(Buffers b, int slot) {
   __shared__ double red[kNW * kRPW][kLPR * CPL];
   __shared__ double s_lw[kMaxCols], s_r[kNW], s_a[kNW], s_k[kNW];
@@ -397,14 +416,7 @@ __global__ __launch_bounds__(kBlk) void bwd_rows(Buffers b, int slot) {
     for (int64_t wb = ((int64_t)blockIdx.x * kNW + w) * kRPW; wb < b.n; wb += kRB * wstride) {
       double x[kRB][CPL];
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
-        const int64_t i = wb + r * wstride + rg;
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-          const int col = cl * CPL + j;
-          x[r][j] = (i < b.n && col < d) ? xval<P>(b, i, col) : cr[j];
-        }
-      }
+      for (int r = 0; r < kRB; ++r) load_cols<P, CPL, V4>(b, wb + r * wstride + rg, cl, cr, x[r]);
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         const int64_t i = wb + r * wstride + rg;
@@ -616,7 +628,7 @@ __global__ __launch_bounds__(kBlk) void round_kernel(const double *src, float *d
     dst[k] = (float)src[k];
 }
 
-template <typename P, int PER, bool ROWS>
+template <typename P, int PER, bool ROWS, bool V4 = false>
 hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
   const int G = b.grid;
   const int64_t T = b.T;
@@ -645,7 +657,7 @@ hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
     for (int64_t t = t0 + 1; t <= t1; ++t) {
       const int slot = (int)(t - t0 - 1);
       if constexpr (ROWS)
-        fwd_rows<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
+        fwd_rows<P, PER, V4><<<G, kBlk, 0, s>>>(bx, slot);
       else
         fwd_pass<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
       fwd_epi<P><<<1, kEpi, 0, s>>>(bx, slot, t, 1);
@@ -664,7 +676,7 @@ hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
       for (int64_t t = t0 + 1; t <= t1; ++t) {
         const int slot = (int)(t - t0 - 1);
         if constexpr (ROWS)
-          fwd_rows<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
+          fwd_rows<P, PER, V4><<<G, kBlk, 0, s>>>(bx, slot);
         else
           fwd_pass<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
         fwd_epi<P><<<1, kEpi, 0, s>>>(bx, slot, t, 0);
@@ -674,7 +686,7 @@ hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
       const int slot = (int)(t - t0 - 1);
       if (t >= 2) {
         if constexpr (ROWS)
-          bwd_rows<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
+          bwd_rows<P, PER, V4><<<G, kBlk, 0, s>>>(bx, slot);
         else
           bwd_pass<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
       }
@@ -694,7 +706,11 @@ hipError_t run_per(const Buffers &b, double gv, hipStream_t s) {
   // d <= 64: 16 lanes per row with 1, 2 or 4 columns each; else 64 lanes per row
   if (b.d <= 16) return run_typed<P, 1, true>(b, gv, s);
   if (b.d <= 32) return run_typed<P, 2, true>(b, gv, s);
-  if (b.d <= 64) return run_typed<P, 4, true>(b, gv, s);
+  if (b.d <= 64) {
+    if constexpr (sizeof(P) == 4)
+      if (b.d % 4 == 0 && b.ld % 4 == 0 && ((uintptr_t)b.X & 15) == 0) return run_typed<P, 4, true, true>(b, gv, s);
+    return run_typed<P, 4, true>(b, gv, s);
+  }
   const int64_t per = (b.d + kW - 1) / kW;
   if (per <= 2) return run_typed<P, 2, false>(b, gv, s);
   if (per <= 4) return run_typed<P, 4, false>(b, gv, s);

@@ -83,6 +83,25 @@ def test_backward_checkpoint_modes(case, every):
     assert np.abs(G - G0).max() <= GRAD_TOL * np.abs(G0).max()
 
 
+@pytest.mark.parametrize("width,first", [(68, 0), (66, 0), (68, 1)], ids=["ld68", "ld66", "ld68_offset1"])
+def test_backward_strided_points(width, first):
+    """Points as a view of a wider matrix (row stride 68 or 66, first column
+    0 or 1): 16-byte row loads only where the stride and the base allow."""
+    import torch
+    n, d, T = 700, 64, 40
+    V = synth.ses_uniform(n, d, 21).astype(np.float32)
+    big = np.full((n, width), np.nan, dtype=np.float32)
+    big[:, first:first + d] = V
+    Xb = torch.from_numpy(big).cuda()
+    X = Xb[:, first:first + d]
+    V64 = V.astype(np.float64)
+    alpha = 2.0 * oses.setup(V64).D / 3.0
+    R, G = gpu_grad(X, alpha, T, checkpoint_every=0)
+    R0, G0 = ses_grad.radius_grad(V64, alpha, T)
+    assert abs(R - R0) <= TIGHT * R0
+    assert np.abs(G - G0).max() <= GRAD_TOL * np.abs(G0).max()
+
+
 def test_backward_scales_with_grad_value_and_leaves_the_test():
     import paper_2405_09157_amd as scp
     X, V = points(400, 7, 12, "f32")
