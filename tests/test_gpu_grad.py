@@ -102,6 +102,23 @@ def test_backward_strided_points(width, first):
     assert np.abs(G - G0).max() <= GRAD_TOL * np.abs(G0).max()
 
 
+@pytest.mark.parametrize("n,d,T", [(2, 3, 5), (2, 1, 60), (10, 2, 1), (10, 2, 2), (40, 3, 50), (40, 3, 51), (40, 3, 100)])
+@pytest.mark.parametrize("every", [0, 50])
+def test_backward_edges(n, d, T, every):
+    """Two points, one column, T = 1 (only u(1) = v1), T = 2 (one reverse
+    pass), and T at, just past and twice the 50-iteration segment.  With two
+    points every u(t) lies on the segment from v1 towards v2 at distance alpha,
+    so R = alpha (T - 1)/T does not depend on the points and the gradient is
+    zero up to the rounding of its O(1) terms (the unit vector of R's own
+    term): the bar is taken against max(max|g|, 1)."""
+    X, V = points(n, d, 30 + n + T, "f32")
+    alpha = 2.0 * oses.setup(V).D / 3.0
+    R, G = gpu_grad(X, alpha, T, checkpoint_every=every)
+    R0, G0 = ses_grad.radius_grad(V, alpha, T)
+    assert abs(R - R0) <= TIGHT * R0
+    assert np.abs(G - G0).max() <= GRAD_TOL * max(np.abs(G0).max(), 1.0)
+
+
 def test_backward_scales_with_grad_value_and_leaves_the_test():
     import paper_2405_09157_amd as scp
     X, V = points(400, 7, 12, "f32")
