@@ -477,29 +477,44 @@ __global__ __launch_bounds__(kBlk) void bwd_rows(Buffers b, int slot) {
 
 // ---- the rows' share of a walked-back segment, slots [jlo, jhi):
 // grad_i += sum_j a_{j,i} lambda_W(j) + beta_{j,i} (v_i - c(j)).  A workgroup
-// holds the segment's lambda_W and c for its 64 columns in LDS; each wave
-// takes one row at a time, a lane one column.
+// holds the segment's lambda_W and c for its 64 columns in LDS and stages the
+// coefficients of kCR rows at a time (coalesced loads along the rows); each
+// wave then takes one of those rows at a time, a lane one column.
+constexpr int kCR = 16;
+
 template <typename P>
 __global__ __launch_bounds__(kBlk) void seg_contract(Buffers b, int jlo, int jhi) {
   __shared__ double s_l[kSegment][kW], s_c[kSegment][kW];
+  __shared__ double s_a[kSegment][kCR], s_b[kSegment][kCR];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
   const int col = blockIdx.y * kW + lane;
-  for (int k = threadIdx.x; k < (jhi - jlo) * kW; k += kBlk) {
+  const int nj = jhi - jlo;
+  for (int k = threadIdx.x; k < nj * kW; k += kBlk) {
     const int j = jlo + k / kW, cc = blockIdx.y * kW + (k % kW);
     s_l[j][k % kW] = cc < d ? b.lw[(int64_t)j * d + cc] : 0.0;
     s_c[j][k % kW] = cc < d ? b.tc[(int64_t)j * d + cc] : 0.0;
   }
-  __syncthreads();
-  if (col >= d) return;
-  for (int64_t i = (int64_t)blockIdx.x * kNW + w; i < b.n; i += (int64_t)gridDim.x * kNW) {
-    const double x = xval<P>(b, i, col);
-    double acc = 0.0;
-#pragma unroll 5
-    for (int j = jlo; j < jhi; ++j) {
-      const double a = b.sa[(int64_t)j * b.n + i], be = b.sb[(int64_t)j * b.n + i];
-      acc += a * s_l[j][lane] + be * (x - s_c[j][lane]);
+  const int64_t nsteps = (b.n + kCR - 1) / kCR;
+  for (int64_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
+    const int64_t i0 = st * kCR;
+    __syncthreads();  // the previous rows' readers are done
+    for (int k = threadIdx.x; k < nj * kCR; k += kBlk) {
+      const int j = jlo + k / kCR, r = k % kCR;
+      const int64_t i = i0 + r;
+      s_a[j][r] = i < b.n ? b.sa[(int64_t)j * b.n + i] : 0.0;
+      s_b[j][r] = i < b.n ? b.sb[(int64_t)j * b.n + i] : 0.0;
     }
-    b.gacc[i * b.d + col] += acc;
+    __syncthreads();
+    if (col < d) {
+      for (int r = w; r < kCR; r += kNW) {
+        const int64_t i = i0 + r;
+        if (i >= b.n) break;
+        const double x = xval<P>(b, i, col);
+        double acc = 0.0;
+        for (int j = jlo; j < jhi; ++j) acc += s_a[j][r] * s_l[j][lane] + s_b[j][r] * (x - s_c[j][lane]);
+        b.gacc[i * b.d + col] += acc;
+      }
+    }
   }
 }
 
