@@ -265,6 +265,36 @@ def gradient(reps=3):
                 grad_abs_sum=float(out.abs().sum()))
 
 
+PRODUCT = dict(name="product_cone_orthant1e7_1e5x64", n_orth=10_000_000, blocks=100_000, d=64, seed=0, eta=0.05)
+
+
+def product_cone(reps=20):
+    """SCMWU iterate over R^{1e7}_+ (+) 1e5 Lorentz blocks Q^{65} (16.5 M binary64
+    values): wall time of scp_mwu_product_exp (three launches and the ln Tr
+    readback) and the rate of its algorithmic bytes (m read twice, p written,
+    then read and written once more: 5 x 8 bytes per value)."""
+    import numpy as np
+    import torch
+    import paper_2405_09157_amd as scp
+    c = PRODUCT
+    total = c["n_orth"] + c["blocks"] * (c["d"] + 1)
+    g = torch.Generator(device="cuda").manual_seed(c["seed"])
+    m = torch.randn(total, dtype=torch.float64, device="cuda", generator=g)
+    p = torch.empty_like(m)
+    dims = [c["d"]] * c["blocks"]
+    scp.product_exp(m, c["n_orth"], dims, c["eta"], out=p)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        scp.product_exp(m, c["n_orth"], dims, c["eta"], out=p)
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    nbytes = 5 * 8 * total
+    return dict(workload=c["name"], values=total, ms=round(t * 1e3, 4), algorithmic_bytes=nbytes,
+                GBs=round(nbytes / t / 1e9, 1), hbm_frac=round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4))
+
+
 def _oracle_iters(V64, threads, warm, timed, budget_s):
     """Median seconds per FP64 oracle iteration of the benchmarked alpha-test."""
     from threadpoolctl import threadpool_limits
@@ -316,6 +346,7 @@ def main(argv=None):
     ap.add_argument("--batch-solve", default="f32",
                     help="storage types of the batched eps solves: comma list of f32, bf16, or none")
     ap.add_argument("--no-grad", action="store_true", help="skip the reverse-pass workload")
+    ap.add_argument("--no-cone", action="store_true", help="skip the product-cone iterate")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain copy of the matrix (counter calibration)")
     a = ap.parse_args(argv)
@@ -372,6 +403,9 @@ def main(argv=None):
     grad = None if a.no_grad else gradient()
     if grad:
         print(f"# gradient: {grad}", file=sys.stderr, flush=True)
+    cone = None if a.no_cone else product_cone()
+    if cone:
+        print(f"# product cone: {cone}", file=sys.stderr, flush=True)
     cpu = None if a.no_cpu else cpu_baseline(V)
     if cpu:
         print(f"# cpu: {cpu}", file=sys.stderr, flush=True)
@@ -409,6 +443,8 @@ def main(argv=None):
         line["batched"] = batch
     if grad:
         line["gradient"] = grad
+    if cone:
+        line["product_cone"] = cone
     if probe:
         line["copy_reference"] = probe
     print(json.dumps(line), flush=True)

@@ -210,11 +210,14 @@ def scp_mwu_backward(ctx, grad_value: float, grad_points_ptr: int, checkpoint_ev
 
 
 def scp_mwu_product_exp(m_ptr: int, n_orth: int, offsets, eta: float, p_ptr: int, stream: int = 0) -> float:
-    """p = exp(-eta m) / Tr(...) over R^{n_orth}_+ (+) Lorentz blocks at `offsets`; returns ln Tr."""
+    """p = exp(-eta m) / Tr(...) over R^{n_orth}_+ (+) Lorentz blocks at `offsets`
+    (a sequence or an int64 numpy array of nblocks + 1 values); returns ln Tr."""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.int64) if len(offsets) else None
     k = max(len(offsets) - 1, 0)
-    off = (ctypes.c_int64 * max(len(offsets), 1))(*offsets) if offsets else None
+    ptr = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if off is not None else None
     lt = ctypes.c_double()
-    code = load().scp_mwu_product_exp(m_ptr, int(n_orth), off, k, float(eta), p_ptr, ctypes.byref(lt), stream)
+    code = load().scp_mwu_product_exp(m_ptr, int(n_orth), ptr, k, float(eta), p_ptr, ctypes.byref(lt), stream)
     if code != SCP_MWU_OK:
         raise ScpMwuError(code, "scp_mwu_product_exp: " + load().scp_mwu_strerror(code).decode())
     return lt.value

@@ -262,16 +262,19 @@ def product_exp(m, n_orth: int, dims, eta: float, out=None):
     L.load()
     if not m.is_cuda or m.dtype != torch.float64 or m.dim() != 1 or not m.is_contiguous():
         raise ValueError("m must be a contiguous float64 device vector")
-    offsets = [int(n_orth)]
-    for d in dims:
-        offsets.append(offsets[-1] + int(d) + 1)
+    import numpy as np
+    dims = np.asarray(dims, dtype=np.int64).reshape(-1)
+    offsets = np.empty(dims.size + 1, dtype=np.int64)
+    offsets[0] = int(n_orth)
+    np.cumsum(dims + 1, out=offsets[1:])
+    offsets[1:] += int(n_orth)
     if offsets[-1] != m.numel():
         raise ValueError("m's length does not match n_orth and dims")
     if out is None:
         out = torch.empty_like(m)
     stream = torch.cuda.current_stream(m.device).cuda_stream
     with torch.cuda.device(m.device):
-        lt = L.scp_mwu_product_exp(m.data_ptr(), int(n_orth), offsets if dims else [], float(eta),
+        lt = L.scp_mwu_product_exp(m.data_ptr(), int(n_orth), offsets if dims.size else [], float(eta),
                                    out.data_ptr(), stream)
     return out, lt
 

@@ -135,7 +135,7 @@ extern "C" int scp_mwu_product_exp(const double *m, int64_t n_orth, const int64_
   const int G = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4 * (int64_t)std::max(cus, 1)));
   void *mem = nullptr;
   const size_t nbytes = sizeof(double) * (2 * (size_t)G + 2) + sizeof(int64_t) * (size_t)(nblocks + 1);
-  if (hipMalloc(&mem, nbytes) != hipSuccess) return SCP_MWU_E_NOMEM;
+  if (hipMallocAsync(&mem, nbytes, s) != hipSuccess) return SCP_MWU_E_NOMEM;  // stream-ordered: no device-wide sync
   Args a{};
   a.m = m;
   a.p = p;
@@ -158,8 +158,8 @@ extern "C" int scp_mwu_product_exp(const double *m, int64_t n_orth, const int64_
   }
   double out[2] = {0.0, 0.0};
   if (!rc && hipMemcpyAsync(out, a.out, sizeof(out), hipMemcpyDeviceToHost, s) != hipSuccess) rc = SCP_MWU_E_HIP;
+  if (hipFreeAsync(mem, s) != hipSuccess && !rc) rc = SCP_MWU_E_HIP;
   if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = SCP_MWU_E_HIP;
-  hipFree(mem);
   if (!rc && log_trace) *log_trace = out[1];
   return rc;
 }
