@@ -45,8 +45,9 @@ Readings (listed with reasons in the design notes):
 
 Pins: tests/test_oracle_ses_grad.py (central finite differences of the
 forward map ``radius`` on small inputs, translation invariance sum_i dR/dv_i = 0,
-rotation invariance sum_i (v_i g_i^T - g_i v_i^T) = 0, and the forward map's
-trajectory against ``ses.ftp`` with early exits off).
+rotation invariance sum_i (v_i g_i^T - g_i v_i^T) = 0, the forward map's
+trajectory against ``ses.ftp`` with early exits off, and, loosely, the optimal
+radius's gradient from the dual weights of Welzl's ball as T grows).
 """
 from __future__ import annotations
 

@@ -72,3 +72,34 @@ def test_forward_is_the_alpha_test_without_exits():
     assert abs(res.f_traj[-1] - ses.monitor(P, fw.S[res.t_done] / res.t_done)) <= 1e-12
     if res.outcome == ses.T_REACHED:
         assert abs(fw.R - res.f_traj[-1]) <= 1e-12 * fw.R
+
+
+def danskin_gradient(V):
+    """dR*/dv_i = pi_i (v_i - c*)/R* for the smallest enclosing ball (c*, R*)
+    (Welzl) with pi the optimal dual weights: the convex combination of the
+    points on the sphere that equals c* (the dual of eq.(ses_qp))."""
+    from oracle import exact
+    c, R = exact.welzl(V)
+    act = np.flatnonzero(np.abs(np.linalg.norm(V - c, axis=1) - R) <= 1e-9 * R)
+    A = np.vstack([V[act].T, np.ones(act.size)])
+    pi_a = np.linalg.lstsq(A, np.append(c, 1.0), rcond=None)[0]
+    assert np.all(pi_a >= -1e-9) and np.abs(A @ pi_a - np.append(c, 1.0)).max() < 1e-9
+    pi = np.zeros(V.shape[0])
+    pi[act] = pi_a
+    return R, pi[:, None] * (V - c) / R
+
+
+def test_gradient_approaches_the_dual_weight_gradient():
+    """At alpha just above R* and growing T, ubar_T approaches the centre and
+    the adjoint approaches the optimal value's gradient (Danskin on the dual):
+    the gap shrinks with T, and is a small fraction of the gradient once R is
+    within a fraction of a percent of R* (a loose check: the unrolled map
+    still carries O(gap) terms off the support)."""
+    V = synth.ses_uniform(60, 2, 3)
+    Rs, Gd = danskin_gradient(V)
+    errs = []
+    for T in (2000, 8000):
+        R, G = ses_grad.radius_grad(V, 1.001 * Rs, T)
+        errs.append(np.abs(G - Gd).max())
+    assert R / Rs - 1.0 < 3e-3
+    assert errs[1] < errs[0] and errs[1] <= 0.2 * np.abs(Gd).max()
