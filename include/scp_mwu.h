@@ -245,8 +245,9 @@ int scp_mwu_solve(scp_mwu_ctx *ctx, scp_mwu_result *res, double *y);
  * about (T/K + 2K) d + 2 K n + n d binary64 values); checkpoint_every = 0
  * keeps the whole tape of the forward run, 2d + 4 numbers per iteration (two
  * passes per iteration; about 2 T d + 100 n + n d values).
- * Requires: an SES context on points without radii, streamed as F32 or F64
- * (no BF16/FP8 storage), d <= 512, and a current test (scp_mwu_step with
+ * Requires: an SES context on points without radii, streamed as F32, F64 or
+ * BF16 (the gradient is then with respect to the stored BF16 values; no FP8
+ * storage), d <= 512, and a current test (scp_mwu_step with
  * reset, any k >= 0): its alpha and T define the map, which always runs all
  * T iterations, also where the test itself stopped earlier (a separation
  * or a Section 5 exit).  The test's state is left unchanged.
@@ -256,7 +257,7 @@ int scp_mwu_solve(scp_mwu_ctx *ctx, scp_mwu_result *res, double *y);
  * value (host, may be NULL): receives R as the recomputed forward found it.
  * Errors: E_INVAL (NULL grad_points, non-finite grad_value, checkpoint_every
  * outside 0 .. 50), E_UNSUPPORTED
- * (SVM, radii, BF16/FP8 storage, d > 512), E_STATE (no test started),
+ * (SVM, radii, FP8 storage, d > 512), E_STATE (no test started),
  * E_NOMEM, E_HIP.  Blocks until the result is written.
  */
 int scp_mwu_backward(scp_mwu_ctx *ctx, double grad_value, float *grad_points, double *value,

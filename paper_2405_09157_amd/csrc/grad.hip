@@ -16,7 +16,8 @@
 //
 // Lanes run over the columns of a row (d <= 512: PER <= 8 columns per lane);
 // each wave takes rows kRB at a time (all loads issued before the arithmetic)
-// and reduces a row's sums with a butterfly.  All arithmetic is binary64; the
+// and reduces a row's sums with a butterfly.  All arithmetic is binary64 on the
+// stored values (FP32, FP64 or BF16 points, widened exactly); the
 // gradient is accumulated in a binary64 workspace and rounded once to the
 // caller's FP32 buffer.
 #include <algorithm>
@@ -54,6 +55,12 @@ __device__ __forceinline__ double bsum(double v, double *s_r) {
 template <typename P>
 __device__ __forceinline__ double xval(const Buffers &b, int64_t i, int col) {
   return (double)((const P *)b.X)[i * b.ld + col];
+}
+// BF16 storage: the stored value, exactly (the upper half of a binary32)
+template <>
+__device__ __forceinline__ double xval<uint16_t>(const Buffers &b, int64_t i, int col) {
+  const uint16_t h = ((const uint16_t *)b.X)[i * b.ld + col];
+  return (double)__uint_as_float((uint32_t)h << 16);
 }
 
 // dst[c] = sum over the grid's partial rows of column c, c < ncol, by the NT
@@ -735,7 +742,9 @@ hipError_t run_per(const Buffers &b, double gv, hipStream_t s) {
 hipError_t run_backward(const Buffers &b, double gv, hipStream_t s) {
   if (b.d < 1 || b.d > kMaxCols || b.n < 2 || b.T < 1 || b.grid < 1 || b.seg < 1 || b.seg > kSegment)
     return hipErrorInvalidValue;
-  return b.dtype == 1 ? run_per<double>(b, gv, s) : run_per<float>(b, gv, s);
+  if (b.dtype == 1) return run_per<double>(b, gv, s);
+  if (b.dtype == 2) return run_per<uint16_t>(b, gv, s);
+  return run_per<float>(b, gv, s);
 }
 
 }  // namespace grad

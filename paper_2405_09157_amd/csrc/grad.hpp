@@ -20,7 +20,7 @@ constexpr int kSegment = 50;  // the longest segment (iterations between stored 
 // Device buffers of one reverse pass (allocated by the host for one call).
 struct Buffers {
   int64_t n, d, ld, v1, T;
-  int dtype;         // 0: float points, 1: double points
+  int dtype;         // 0: float points, 1: double points, 2: BF16 points
   const void *X;
   double alpha, eta;     // kappa_t = eta (t - 1) / (3D), D recomputed on the device
   int grid;

@@ -593,8 +593,8 @@ int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points, doub
     return c->fail(SCP_MWU_E_INVAL, "checkpoint_every must be 0 (keep the whole tape) or 1 .. 50");
   if (c->problem != kSES || c->radii)
     return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: SES on point sets only");
-  if (c->dtype != kF32 && c->dtype != kF64)
-    return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: points streamed as F32 or F64 only (no BF16/FP8 storage)");
+  if (c->dtype != kF32 && c->dtype != kF64 && c->dtype != kBF16)
+    return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: points streamed as F32, F64 or BF16 only (no FP8 storage)");
   if (c->d > 512) return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: d > 512");
   if (!c->active) return c->fail(SCP_MWU_E_STATE, "backward before any test");
   int rc = SCP_MWU_OK;
@@ -607,7 +607,7 @@ int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points, doub
   b.ld = c->ld;
   b.v1 = c->v1;
   b.T = c->T;
-  b.dtype = c->dtype == kF64 ? 1 : 0;
+  b.dtype = c->dtype == kF64 ? 1 : (c->dtype == kBF16 ? 2 : 0);
   b.X = c->X;
   b.alpha = c->alpha;
   b.eta = c->eta;

@@ -119,6 +119,25 @@ def test_backward_edges(n, d, T, every):
     assert np.abs(G - G0).max() <= GRAD_TOL * max(np.abs(G0).max(), 1.0)
 
 
+@pytest.mark.parametrize("n,d,T", [(500, 5, 60), (2000, 64, 60), (400, 100, 30)])
+@pytest.mark.parametrize("every", [0, 50])
+def test_backward_bf16_storage(n, d, T, every):
+    """BF16 storage: the gradient with respect to the stored values, against
+    the oracle on those values (binary64 arithmetic on exact inputs: the
+    same bar as FP32 points)."""
+    import torch
+    import paper_2405_09157_amd as scp
+    V32 = synth.ses_uniform(n, d, 40 + d).astype(np.float32)
+    Vs = synth.bf16_to_f32(synth.bf16_round(V32)).astype(np.float64)
+    alpha = 2.0 * oses.setup(Vs).D / 3.0
+    with scp.MWU(torch.from_numpy(V32).cuda(), "ses", storage="bf16", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP) as m:
+        m.step(alpha, T, 0, reset=True)
+        R, g = m.backward(1.0, checkpoint_every=every)
+    R0, G0 = ses_grad.radius_grad(Vs, alpha, T)
+    assert abs(R - R0) <= TIGHT * R0
+    assert np.abs(g.cpu().double().numpy() - G0).max() <= GRAD_TOL * np.abs(G0).max()
+
+
 def test_backward_scales_with_grad_value_and_leaves_the_test():
     import paper_2405_09157_amd as scp
     X, V = points(400, 7, 12, "f32")
@@ -154,7 +173,7 @@ def test_backward_errors():
             with pytest.raises(scp.ScpMwuError) as e:
                 scp.scp_mwu_backward(m.ctx, 1.0, out.data_ptr(), every)
             assert e.value.code == scp.SCP_MWU_E_INVAL
-    with scp.MWU(X, "ses", storage="bf16") as m:
+    with scp.MWU(X, "ses", storage="fp8") as m:
         m.step(1.0, 10, 0, reset=True)
         with pytest.raises(scp.ScpMwuError) as e:
             scp.scp_mwu_backward(m.ctx, 1.0, out.data_ptr())
