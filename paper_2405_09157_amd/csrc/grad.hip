@@ -588,10 +588,11 @@ __global__ __launch_bounds__(kBlk) void far_pass(Buffers b, const double *center
 }
 
 __global__ __launch_bounds__(kW) void far_final(Buffers b, int which) {
-  if (threadIdx.x != 0) return;
+  __shared__ double s_v[kW];
+  __shared__ int64_t s_i[kW];
   double best = -1.0;
   int64_t bi = -1;
-  for (int g = 0; g < b.grid; ++g) {
+  for (int g = threadIdx.x; g < b.grid; g += kW) {  // each lane a strided share of the partials
     const double v = b.part[2 * g];
     const int64_t i = (int64_t)b.part[2 * g + 1];
     if (i >= 0 && (v > best || (v == best && i < bi))) {
@@ -599,6 +600,15 @@ __global__ __launch_bounds__(kW) void far_final(Buffers b, int which) {
       bi = i;
     }
   }
+  s_v[threadIdx.x] = best;
+  s_i[threadIdx.x] = bi;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int q = 1; q < kW; ++q)  // the largest distance, ties to the smallest row
+    if (s_i[q] >= 0 && (s_v[q] > best || (s_v[q] == best && (bi < 0 || s_i[q] < bi)))) {
+      best = s_v[q];
+      bi = s_i[q];
+    }
   b.misc[which == 0 ? 1 : 2] = sqrt(best);
   b.idx[which] = bi;
 }
