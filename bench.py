@@ -145,9 +145,12 @@ def solve_kway(X, k):
 
 
 def solve(X, storage):
+    """eps = 1e-3 solve with the Section 5 exits and weight certificates (the
+    dual lower bound of eq.(ses_qp) from the pass's weights, taken once per
+    graph chunk): wall time, iterations, tests, radius and certified bounds."""
     import torch
     import paper_2405_09157_amd as scp
-    m = scp.MWU(X, "ses", eps=1e-3, storage=storage, chunk=64)
+    m = scp.MWU(X, "ses", eps=1e-3, storage=storage, chunk=64, flags=scp.SCP_MWU_FLAG_CERTIFICATES)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = m.solve()
@@ -270,9 +273,11 @@ PRODUCT = dict(name="product_cone_orthant1e7_1e5x64", n_orth=10_000_000, blocks=
 
 def product_cone(reps=20):
     """SCMWU iterate over R^{1e7}_+ (+) 1e5 Lorentz blocks Q^{65} (16.5 M binary64
-    values): wall time of scp_mwu_product_exp (three launches and the ln Tr
-    readback) and the rate of its algorithmic bytes (m read twice, p written,
-    then read and written once more: 5 x 8 bytes per value)."""
+    values) through one validated ProductCone handle: HIP-event time of the
+    three launches of an iterate (enqueued back to back, no host work between
+    them), the wall time of one call that also reads ln Tr back, and the rate
+    of the algorithmic bytes (m read twice, p written, then read and written
+    once more: 5 x 8 bytes per value)."""
     import numpy as np
     import torch
     import paper_2405_09157_amd as scp
@@ -282,17 +287,25 @@ def product_cone(reps=20):
     m = torch.randn(total, dtype=torch.float64, device="cuda", generator=g)
     p = torch.empty_like(m)
     dims = [c["d"]] * c["blocks"]
-    scp.product_exp(m, c["n_orth"], dims, c["eta"], out=p)
-    times = []
-    for _ in range(reps):
+    with scp.ProductCone(c["n_orth"], dims) as pc:
+        pc.exp(m, c["eta"], out=p)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pc.exp(m, c["eta"], out=p, log_trace=False)
+        e1.record()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        scp.product_exp(m, c["n_orth"], dims, c["eta"], out=p)
-        times.append(time.perf_counter() - t0)
-    t = float(np.median(times))
+        ms = e0.elapsed_time(e1) / reps
+        walls = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pc.exp(m, c["eta"], out=p)
+            walls.append(time.perf_counter() - t0)
     nbytes = 5 * 8 * total
-    return dict(workload=c["name"], values=total, ms=round(t * 1e3, 4), algorithmic_bytes=nbytes,
-                GBs=round(nbytes / t / 1e9, 1), hbm_frac=round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4))
+    return dict(workload=c["name"], values=total, kernels_ms=round(ms, 4), algorithmic_bytes=nbytes,
+                GBs=round(nbytes / (ms * 1e-3) / 1e9, 1), hbm_frac=round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                wall_ms_with_readback=round(float(np.median(walls)) * 1e3, 4))
 
 
 def _oracle_iters(V64, threads, warm, timed, budget_s):
@@ -388,9 +401,18 @@ def main(argv=None):
         print(f"# solve f32: {sol['f32']}", file=sys.stderr, flush=True)
         for k in narrow:
             sol[k] = solve(X, k)
-            sol[k]["radius_rel_to_f32"] = sol[k]["radius"] / sol["f32"]["radius"] - 1.0
+            rel = sol[k]["radius"] / sol["f32"]["radius"] - 1.0
+            sol[k]["radius_rel_to_f32"] = rel
             print(f"# solve {k}: {sol[k]}", file=sys.stderr, flush=True)
-            sol[f"{k}_over_f32_solve_rate"] = sol[k]["solves_per_s"] / sol["f32"]["solves_per_s"]
+            # a solve-rate ratio is at equal accuracy only when the radii agree
+            # within 1e-3 or both certified gaps are within eps
+            equal = abs(rel) <= 1e-3 or (sol[k]["cert_gap"] <= 1e-3 and sol["f32"]["cert_gap"] <= 1e-3)
+            sol[f"{k}_over_f32_solve_rate"] = dict(
+                ratio=round(sol[k]["solves_per_s"] / sol["f32"]["solves_per_s"], 4), equal_accuracy=bool(equal),
+                note="radius within 1e-3 of the FP32 solve's (or both certified gaps <= eps)" if equal else
+                     "NOT at equal accuracy: the two solves took different search paths")
+            # the same comparison at equal iteration counts: the iteration rates
+            sol[f"{k}_over_f32_iteration_rate"] = round(f32["ms_per_step"] / res[k]["ms_per_step"], 4)
         kway = [solve_kway(X, k) for k in (2, 4)]
         for r in kway:
             r["over_f32_solve_rate"] = round(r["solves_per_s"] / sol["f32"]["solves_per_s"], 3)

@@ -253,10 +253,11 @@ int scp_mwu_solve(scp_mwu_ctx *ctx, scp_mwu_result *res, double *y);
  * or a Section 5 exit).  The test's state is left unchanged.
  * grad_value: the upstream scalar dL/dR; the output is grad_value * dR/dV.
  * grad_points: device, n x d FP32, row stride d, owned by the caller;
- *   overwritten.
+ *   overwritten.  NULL: only the forward iterations run and only *value is
+ *   written (the map's value without its gradient).
  * value (host, may be NULL): receives R as the recomputed forward found it.
- * Errors: E_INVAL (NULL grad_points, non-finite grad_value, checkpoint_every
- * outside 0 .. 50), E_UNSUPPORTED
+ * Errors: E_INVAL (grad_points and value both NULL, non-finite grad_value,
+ * checkpoint_every outside 0 .. 50), E_UNSUPPORTED
  * (SVM, radii, FP8 storage, d > 512), E_STATE (no test started),
  * E_NOMEM, E_HIP.  Blocks until the result is written.
  */
@@ -431,20 +432,36 @@ const char *scp_mwu_batch_last_error(const scp_mwu_batch *b);
  * p = exp(-eta m) / Tr(exp(-eta m)) on K = R^{n_orth}_+ (+) Q^{d_1+1} (+) ...
  * (+) Q^{d_k+1}, in the Jordan algebra whose identity is (0; sqrt2) on each
  * Lorentz block (eigenvalues (x0 +- ||xbar||)/sqrt2, trace sqrt2 x0).
- * m (device, binary64): the cumulative loss; the orthant coordinates first,
- *   then block j in [offsets[j], offsets[j+1]) as its vector part (d_j
- *   values) followed by its scalar part.
- * offsets (host, nblocks + 1 values; may be NULL when nblocks = 0):
- *   offsets[0] = n_orth, each block at least 2 long (d_j >= 1).
- * p (device, binary64, same layout and length as m; caller-owned; may not
- *   alias m): the normalised iterate, trace one.
- * log_trace (host, may be NULL): ln Tr(exp(-eta m)).
- * Enqueued on stream (a hipStream_t; NULL = default) and waited for.
- * E_INVAL (NULL m or p, n_orth < 0, nblocks < 0, an empty cone, eta not a
- * positive finite number, bad offsets), E_NOMEM, E_HIP.
+ *
+ * A vector of the cone has len binary64 values: the orthant coordinates
+ * first, then block j in [offsets[j], offsets[j+1]) as its vector part (d_j
+ * values) followed by its scalar part.
+ *
+ * scp_mwu_product_init validates a layout once and keeps it on the device:
+ *   offsets (host, nblocks + 1 values; may be NULL when nblocks = 0):
+ *   offsets[0] = n_orth, each block at least 2 long (d_j >= 1), and
+ *   offsets[nblocks] = len (len = n_orth without blocks).  The layout's
+ *   workspace (a few doubles per workgroup plus the offsets) is owned by
+ *   the handle; its launches go on stream (a hipStream_t; NULL = default).
+ *   E_INVAL (out NULL, n_orth < 0, nblocks < 0, an empty cone, len < 1,
+ *   offsets inconsistent with n_orth or len), E_NOMEM, E_HIP.  Synchronous.
+ * scp_mwu_product_exp enqueues the three launches of one iterate:
+ *   m (device, len binary64): the cumulative loss;
+ *   p (device, len binary64, caller-owned, not aliasing m): the normalised
+ *   iterate, trace one;
+ *   log_trace (host, may be NULL): ln Tr(exp(-eta m)); when given, the call
+ *   waits for the stream to read it, otherwise it returns once the launches
+ *   are enqueued.  E_INVAL (NULL handle, m or p, m == p, eta not a positive
+ *   finite number), E_HIP.  Calls on one handle are ordered by its stream;
+ *   overlapping calls on different streams may not share a handle.
+ * scp_mwu_product_destroy waits for the handle's stream and frees it (NULL
+ *   is a no-op).
  */
-int scp_mwu_product_exp(const double *m, int64_t n_orth, const int64_t *offsets, int64_t nblocks,
-                        double eta, double *p, double *log_trace, void *stream);
+typedef struct scp_mwu_product scp_mwu_product;
+int scp_mwu_product_init(int64_t n_orth, const int64_t *offsets, int64_t nblocks, int64_t len, void *stream,
+                         scp_mwu_product **out);
+int scp_mwu_product_exp(scp_mwu_product *pc, const double *m, double eta, double *p, double *log_trace);
+void scp_mwu_product_destroy(scp_mwu_product *pc);
 
 /*
  * Round n FP32 values to BF16 (nearest, ties to even; NaN stays NaN) on the

@@ -21,7 +21,7 @@ from ._lib import (  # noqa: F401  (re-exported C-ABI names)
     SCP_MWU_PROBLEM_SES, SCP_MWU_PROBLEM_SVM, ScpMwuError, load, scp_mwu_backward,
     scp_mwu_cast_bf16, scp_mwu_desc, scp_mwu_destroy, scp_mwu_get_D, scp_mwu_get_state,
     scp_mwu_get_vector, scp_mwu_init, scp_mwu_result, scp_mwu_set_state, scp_mwu_solve,
-    scp_mwu_quantize_fp8, scp_mwu_product_exp, scp_mwu_read_reference, scp_mwu_step, scp_mwu_stepinfo, scp_mwu_strerror, scp_mwu_time_passes,
+    scp_mwu_quantize_fp8, scp_mwu_product_exp, scp_mwu_product_init, scp_mwu_product_destroy, scp_mwu_read_reference, scp_mwu_step, scp_mwu_stepinfo, scp_mwu_strerror, scp_mwu_time_passes,
     scp_mwu_batch_desc, scp_mwu_batch_destroy, scp_mwu_batch_get_D, scp_mwu_batch_get_vector, scp_mwu_batch_init,
     scp_mwu_batch_solve, scp_mwu_batch_solve_kway, scp_mwu_batch_step, scp_mwu_batch_time_iters)
-from .api import MWU, MWUBatch, autotune_rows_per_group, product_exp, ses_radius  # noqa: F401
+from .api import MWU, MWUBatch, ProductCone, autotune_rows_per_group, product_exp, ses_radius  # noqa: F401

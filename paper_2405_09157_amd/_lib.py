@@ -27,7 +27,8 @@ OUTCOME_NAMES = {0: "running", 1: "separated", 2: "beat_alpha", 3: "stabilized",
                  4: "t_reached", 5: "numeric"}
 
 # symbols the header declares (checked by the CPU test suite)
-EXPORTS = ("scp_mwu_init", "scp_mwu_step", "scp_mwu_solve", "scp_mwu_backward", "scp_mwu_product_exp",
+EXPORTS = ("scp_mwu_init", "scp_mwu_step", "scp_mwu_solve", "scp_mwu_backward", "scp_mwu_product_init",
+           "scp_mwu_product_exp", "scp_mwu_product_destroy",
            "scp_mwu_get_state", "scp_mwu_set_state", "scp_mwu_get_vector", "scp_mwu_get_D",
            "scp_mwu_destroy", "scp_mwu_last_error", "scp_mwu_strerror", "scp_mwu_cast_bf16",
            "scp_mwu_time_passes", "scp_mwu_read_reference", "scp_mwu_quantize_fp8",
@@ -136,7 +137,9 @@ def load() -> ctypes.CDLL:
         "scp_mwu_step": (i32, [vp, f64, i64, i32, i32, P(scp_mwu_stepinfo)]),
         "scp_mwu_solve": (i32, [vp, P(scp_mwu_result), P(f64)]),
         "scp_mwu_backward": (i32, [vp, f64, P(ctypes.c_float), P(f64), i32]),
-        "scp_mwu_product_exp": (i32, [vp, i64, P(i64), i64, f64, vp, P(f64), vp]),
+        "scp_mwu_product_init": (i32, [i64, P(i64), i64, i64, vp, P(vp)]),
+        "scp_mwu_product_exp": (i32, [vp, vp, f64, vp, P(f64)]),
+        "scp_mwu_product_destroy": (None, [vp]),
         "scp_mwu_get_state": (i32, [vp, P(f64), P(i64)]),
         "scp_mwu_set_state": (i32, [vp, f64, i64, i64, P(f64)]),
         "scp_mwu_get_vector": (i32, [vp, i32, P(f64)]),
@@ -201,26 +204,42 @@ def scp_mwu_solve(ctx, d: int):
     return code, res, list(y)
 
 
-def scp_mwu_backward(ctx, grad_value: float, grad_points_ptr: int, checkpoint_every: int = 50) -> float:
-    """grad_value * dR/dV into the device buffer at grad_points_ptr; returns R."""
+def scp_mwu_backward(ctx, grad_value: float, grad_points_ptr, checkpoint_every: int = 50) -> float:
+    """grad_value * dR/dV into the device buffer at grad_points_ptr (None: the
+    forward map only); returns R."""
     value = ctypes.c_double()
-    _check(load().scp_mwu_backward(ctx, grad_value, ctypes.cast(grad_points_ptr, ctypes.POINTER(ctypes.c_float)),
-                                   ctypes.byref(value), int(checkpoint_every)), ctx)
+    gp = ctypes.cast(grad_points_ptr, ctypes.POINTER(ctypes.c_float)) if grad_points_ptr else None
+    _check(load().scp_mwu_backward(ctx, grad_value, gp, ctypes.byref(value), int(checkpoint_every)), ctx)
     return value.value
 
 
-def scp_mwu_product_exp(m_ptr: int, n_orth: int, offsets, eta: float, p_ptr: int, stream: int = 0) -> float:
-    """p = exp(-eta m) / Tr(...) over R^{n_orth}_+ (+) Lorentz blocks at `offsets`
-    (a sequence or an int64 numpy array of nblocks + 1 values); returns ln Tr."""
+def scp_mwu_product_init(n_orth: int, offsets, length: int, stream: int = 0) -> ctypes.c_void_p:
+    """Handle of the product-cone layout R^{n_orth}_+ (+) Lorentz blocks at
+    `offsets` (a sequence or an int64 numpy array of nblocks + 1 values, empty
+    without blocks) over vectors of `length` values."""
     import numpy as np
     off = np.ascontiguousarray(offsets, dtype=np.int64) if len(offsets) else None
     k = max(len(offsets) - 1, 0)
     ptr = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if off is not None else None
+    h = ctypes.c_void_p()
+    code = load().scp_mwu_product_init(int(n_orth), ptr, k, int(length), stream, ctypes.byref(h))
+    if code != SCP_MWU_OK:
+        raise ScpMwuError(code, "scp_mwu_product_init: " + load().scp_mwu_strerror(code).decode())
+    return h
+
+
+def scp_mwu_product_exp(handle, m_ptr: int, eta: float, p_ptr: int, want_log_trace: bool = True):
+    """p = exp(-eta m) / Tr(...) on the handle's layout; returns ln Tr (waiting
+    for the stream) or None (launches only enqueued)."""
     lt = ctypes.c_double()
-    code = load().scp_mwu_product_exp(m_ptr, int(n_orth), ptr, k, float(eta), p_ptr, ctypes.byref(lt), stream)
+    code = load().scp_mwu_product_exp(handle, m_ptr, float(eta), p_ptr, ctypes.byref(lt) if want_log_trace else None)
     if code != SCP_MWU_OK:
         raise ScpMwuError(code, "scp_mwu_product_exp: " + load().scp_mwu_strerror(code).decode())
-    return lt.value
+    return lt.value if want_log_trace else None
+
+
+def scp_mwu_product_destroy(handle) -> None:
+    load().scp_mwu_product_destroy(handle)
 
 
 def scp_mwu_get_state(ctx, d: int, svm: bool):

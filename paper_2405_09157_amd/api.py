@@ -5,8 +5,6 @@ kept alive by this object) and every step runs in ``libscpmwu.so``.
 """
 from __future__ import annotations
 
-import math
-
 from . import _lib as L
 
 _DTYPES = None
@@ -71,7 +69,6 @@ class MWU:
         with torch.cuda.device(points.device):
             self.ctx = L.scp_mwu_init(desc)
         self.D = L.scp_mwu_get_D(self.ctx)
-        self.r = 2 * (self.n - 1) if not self.svm else self.n
 
     # -- lifetime
     def close(self):
@@ -136,8 +133,12 @@ class MWU:
             R = L.scp_mwu_backward(self.ctx, float(grad_value), out.data_ptr(), int(checkpoint_every))
         return R, out
 
-    def eta(self, T: int) -> float:
-        return math.sqrt(math.log(self.r) / T)
+    def radius(self, checkpoint_every: int = 50) -> float:
+        """R of the T-iteration map at the current test's alpha and T (the
+        forward iterations of backward() without the reverse pass)."""
+        import torch
+        with torch.cuda.device(self.points.device):
+            return L.scp_mwu_backward(self.ctx, 1.0, None, int(checkpoint_every))
 
 
 class MWUBatch:
@@ -254,29 +255,76 @@ class MWUBatch:
         return L.scp_mwu_batch_time_iters(self.b, int(k))
 
 
+class ProductCone:
+    """A product cone R^{n_orth}_+ (+) Q^{d+1} for each d in dims, validated once
+    (its block offsets resident on the device, its workspace owned by the
+    library); exp() computes the SCMWU iterate exp(-eta m) / Tr(...) of a
+    float64 device vector m laid out as the orthant coordinates, then each
+    block's vector part and scalar part."""
+
+    def __init__(self, n_orth: int, dims, device=None, stream=None):
+        import numpy as np
+        import torch
+        L.load()
+        dims = np.asarray(dims, dtype=np.int64).reshape(-1)
+        offsets = np.empty(dims.size + 1, dtype=np.int64)
+        offsets[0] = int(n_orth)
+        np.cumsum(dims + 1, out=offsets[1:])
+        offsets[1:] += int(n_orth)
+        self.n_orth, self.nblocks = int(n_orth), int(dims.size)
+        self.length = int(offsets[-1])
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        with torch.cuda.device(self.device):
+            self.handle = L.scp_mwu_product_init(self.n_orth, offsets if dims.size else [], self.length,
+                                                 stream.cuda_stream)
+
+    def exp(self, m, eta: float, out=None, log_trace: bool = True):
+        """(p, ln Tr); with log_trace=False the launches are only enqueued on
+        the stream and ln Tr is None."""
+        import torch
+        if (not m.is_cuda or m.dtype != torch.float64 or m.dim() != 1 or not m.is_contiguous()
+                or m.numel() != self.length):
+            raise ValueError("m must be a contiguous float64 device vector of the cone's length")
+        if out is None:
+            out = torch.empty_like(m)
+        if out.shape != m.shape or out.dtype != m.dtype or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 vector of m's length")
+        with torch.cuda.device(m.device):
+            lt = L.scp_mwu_product_exp(self.handle, m.data_ptr(), float(eta), out.data_ptr(), log_trace)
+        return out, lt
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.scp_mwu_product_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def product_exp(m, n_orth: int, dims, eta: float, out=None):
-    """The SCMWU iterate exp(-eta m) / Tr(...) over R^{n_orth}_+ (+) Q^{d+1} for
-    each d in dims, m a float64 device vector (orthant coordinates, then each
-    block's vector part and scalar part).  Returns (p, ln Tr)."""
+    """One-off SCMWU iterate exp(-eta m) / Tr(...) over R^{n_orth}_+ (+) Q^{d+1}
+    for each d in dims (a ProductCone made and released for the call).
+    Returns (p, ln Tr)."""
     import torch
-    L.load()
-    if not m.is_cuda or m.dtype != torch.float64 or m.dim() != 1 or not m.is_contiguous():
-        raise ValueError("m must be a contiguous float64 device vector")
-    import numpy as np
-    dims = np.asarray(dims, dtype=np.int64).reshape(-1)
-    offsets = np.empty(dims.size + 1, dtype=np.int64)
-    offsets[0] = int(n_orth)
-    np.cumsum(dims + 1, out=offsets[1:])
-    offsets[1:] += int(n_orth)
-    if offsets[-1] != m.numel():
-        raise ValueError("m's length does not match n_orth and dims")
-    if out is None:
-        out = torch.empty_like(m)
-    stream = torch.cuda.current_stream(m.device).cuda_stream
-    with torch.cuda.device(m.device):
-        lt = L.scp_mwu_product_exp(m.data_ptr(), int(n_orth), offsets if dims.size else [], float(eta),
-                                   out.data_ptr(), stream)
-    return out, lt
+    if not m.is_cuda or m.dtype != torch.float64 or m.dim() != 1:
+        raise ValueError("m must be a float64 device vector")
+    with ProductCone(n_orth, dims, device=m.device) as pc:
+        if m.numel() != pc.length:
+            raise ValueError("m's length does not match n_orth and dims")
+        return pc.exp(m, eta, out)
 
 
 def _radius_function():
@@ -285,17 +333,27 @@ def _radius_function():
     class _Radius(torch.autograd.Function):
         @staticmethod
         def forward(ctx, points, alpha, T):
-            with MWU(points.detach(), "ses", flags=L.SCP_MWU_FLAG_NO_EARLY_STOP) as m:
-                m.step(alpha, T, 0, reset=True)   # starts the test that fixes alpha and T
-                R, g = m.backward(1.0)
-            ctx.save_for_backward(g)
+            m = MWU(points.detach(), "ses", flags=L.SCP_MWU_FLAG_NO_EARLY_STOP)
+            m.step(alpha, T, 0, reset=True)       # starts the test that fixes alpha and T
+            R = m.radius()                        # the forward map only
+            if ctx.needs_input_grad[0]:            # the points require grad and grad mode is on
+                ctx.mwu = m                       # the reverse pass runs in backward()
+            else:
+                m.close()
+                ctx.mwu = None
             ctx.points_dtype = points.dtype
             return torch.tensor(R, dtype=torch.float64, device=points.device)
 
         @staticmethod
         def backward(ctx, grad_out):
-            (g,) = ctx.saved_tensors
-            return (g * grad_out.to(g.dtype)).to(ctx.points_dtype), None, None
+            m, ctx.mwu = ctx.mwu, None
+            if m is None:
+                raise RuntimeError("ses_radius: backward through a forward run without gradients")
+            try:
+                _, g = m.backward(float(grad_out))
+            finally:
+                m.close()
+            return g.to(ctx.points_dtype), None, None
 
     return _Radius
 
@@ -306,8 +364,8 @@ _RADIUS = None
 def ses_radius(points, alpha: float, T: int):
     """R = max_i ||v_i - ubar_T|| after T fixed-alpha SES iterations on the
     points (float32 or float64 device tensor, n x d) as a differentiable
-    torch scalar (float64).  The forward call also computes dR/dV (one
-    reverse pass), which backward scales by the incoming gradient."""
+    torch scalar (float64).  The forward call runs the T iterations only; the
+    reverse pass runs in backward, scaled by the incoming gradient."""
     global _RADIUS
     if _RADIUS is None:
         _RADIUS = _radius_function()

@@ -330,7 +330,7 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
     if (desc->n[k] < 2) return bad("instance " + std::to_string(k) + ": n < 2");
     if (desc->d[k] < 1 || desc->d[k] > kMaxD) return bad("instance " + std::to_string(k) + ": d outside [1, 512]");
     if (desc->offset[k] < 0) return bad("instance " + std::to_string(k) + ": negative offset");
-    if (desc->d[k] * 4 * 32 >= (int64_t)1 << 30) return bad("row too long");
+    if (desc->d[k] * 4 * 64 >= (int64_t)1 << 30) return bad("row too long");
     total = std::max(total, desc->offset[k] + desc->n[k] * desc->d[k]);
   }
 

@@ -117,49 +117,86 @@ __global__ __launch_bounds__(kBlk) void norm_kernel(Args a, int64_t total) {
 }  // namespace cone
 }  // namespace scpmwu
 
-extern "C" int scp_mwu_product_exp(const double *m, int64_t n_orth, const int64_t *offsets, int64_t nblocks,
-                                   double eta, double *p, double *log_trace, void *stream) {
+// A product-cone layout validated once: its block offsets resident on the
+// device, the workspace of the three launches, the stream they go on.
+struct scp_mwu_product {
+  int64_t n0 = 0, k = 0, len = 0;
+  int G = 0;
+  hipStream_t stream = nullptr;
+  void *mem = nullptr;  // 2G + 2 doubles (partials, shift, ln C), then k + 1 offsets
+};
+
+extern "C" int scp_mwu_product_init(int64_t n_orth, const int64_t *offsets, int64_t nblocks, int64_t len,
+                                    void *stream, scp_mwu_product **out) {
   using namespace scpmwu::cone;
-  if (!m || !p || n_orth < 0 || nblocks < 0 || n_orth + nblocks == 0 || !(eta > 0.0) || !std::isfinite(eta))
+  if (!out) return SCP_MWU_E_INVAL;
+  *out = nullptr;
+  if (n_orth < 0 || nblocks < 0 || n_orth + nblocks == 0 || len < 1) return SCP_MWU_E_INVAL;
+  if (nblocks > 0) {
+    if (!offsets || offsets[0] != n_orth) return SCP_MWU_E_INVAL;
+    for (int64_t b = 0; b < nblocks; ++b)
+      if (offsets[b + 1] - offsets[b] < 2) return SCP_MWU_E_INVAL;
+    if (offsets[nblocks] != len) return SCP_MWU_E_INVAL;
+  } else if (n_orth != len) {
     return SCP_MWU_E_INVAL;
-  if (nblocks > 0 && !offsets) return SCP_MWU_E_INVAL;
-  if (nblocks > 0 && offsets[0] != n_orth) return SCP_MWU_E_INVAL;
-  for (int64_t b = 0; b < nblocks; ++b)
-    if (offsets[b + 1] - offsets[b] < 2) return SCP_MWU_E_INVAL;
-  const int64_t total = nblocks > 0 ? offsets[nblocks] : n_orth;
-  hipStream_t s = (hipStream_t)stream;
+  }
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return SCP_MWU_E_HIP;
+  auto *pc = new scp_mwu_product();
+  pc->n0 = n_orth;
+  pc->k = nblocks;
+  pc->len = len;
+  pc->stream = (hipStream_t)stream;
   const int64_t want = std::max<int64_t>((n_orth + kBlk - 1) / kBlk, (nblocks + kNW - 1) / kNW);
-  const int G = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4 * (int64_t)std::max(cus, 1)));
-  void *mem = nullptr;
-  const size_t nbytes = sizeof(double) * (2 * (size_t)G + 2) + sizeof(int64_t) * (size_t)(nblocks + 1);
-  if (hipMallocAsync(&mem, nbytes, s) != hipSuccess) return SCP_MWU_E_NOMEM;  // stream-ordered: no device-wide sync
+  pc->G = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4 * (int64_t)std::max(cus, 1)));
+  const size_t nbytes = sizeof(double) * (2 * (size_t)pc->G + 2) + sizeof(int64_t) * (size_t)(nblocks + 1);
+  if (hipMalloc(&pc->mem, nbytes) != hipSuccess) {
+    delete pc;
+    return SCP_MWU_E_NOMEM;
+  }
+  if (nblocks > 0) {
+    int64_t *doff = (int64_t *)((double *)pc->mem + 2 * (size_t)pc->G + 2);
+    if (hipMemcpy(doff, offsets, sizeof(int64_t) * (size_t)(nblocks + 1), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(pc->mem);
+      delete pc;
+      return SCP_MWU_E_HIP;
+    }
+  }
+  *out = pc;
+  return SCP_MWU_OK;
+}
+
+extern "C" int scp_mwu_product_exp(scp_mwu_product *pc, const double *m, double eta, double *p, double *log_trace) {
+  using namespace scpmwu::cone;
+  if (!pc || !m || !p || m == p || !(eta > 0.0) || !std::isfinite(eta)) return SCP_MWU_E_INVAL;
+  const hipStream_t s = pc->stream;
   Args a{};
   a.m = m;
   a.p = p;
-  a.n0 = n_orth;
-  a.k = nblocks;
+  a.n0 = pc->n0;
+  a.k = pc->k;
   a.eta = eta;
-  a.part_max = (double *)mem;
-  a.part_tr = a.part_max + G;
-  a.out = a.part_tr + G;
-  int64_t *doff = (int64_t *)(a.out + 2);
-  a.off = doff;
-  int rc = SCP_MWU_OK;
-  if (nblocks > 0 && hipMemcpyAsync(doff, offsets, sizeof(int64_t) * (nblocks + 1), hipMemcpyHostToDevice, s) != hipSuccess)
-    rc = SCP_MWU_E_HIP;
-  if (!rc) {
-    max_kernel<<<G, kBlk, 0, s>>>(a);
-    exp_kernel<<<G, kBlk, 0, s>>>(a);
-    norm_kernel<<<G, kBlk, 0, s>>>(a, total);
-    if (hipGetLastError() != hipSuccess) rc = SCP_MWU_E_HIP;
-  }
-  double out[2] = {0.0, 0.0};
-  if (!rc && hipMemcpyAsync(out, a.out, sizeof(out), hipMemcpyDeviceToHost, s) != hipSuccess) rc = SCP_MWU_E_HIP;
-  if (hipFreeAsync(mem, s) != hipSuccess && !rc) rc = SCP_MWU_E_HIP;
-  if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = SCP_MWU_E_HIP;
-  if (!rc && log_trace) *log_trace = out[1];
-  return rc;
+  a.part_max = (double *)pc->mem;
+  a.part_tr = a.part_max + pc->G;
+  a.out = a.part_tr + pc->G;
+  a.off = pc->k > 0 ? (const int64_t *)(a.out + 2) : nullptr;
+  max_kernel<<<pc->G, kBlk, 0, s>>>(a);
+  exp_kernel<<<pc->G, kBlk, 0, s>>>(a);
+  norm_kernel<<<pc->G, kBlk, 0, s>>>(a, pc->len);
+  if (hipGetLastError() != hipSuccess) return SCP_MWU_E_HIP;
+  if (!log_trace) return SCP_MWU_OK;
+  double lt = 0.0;
+  if (hipMemcpyAsync(&lt, a.out + 1, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return SCP_MWU_E_HIP;
+  *log_trace = lt;
+  return SCP_MWU_OK;
+}
+
+extern "C" void scp_mwu_product_destroy(scp_mwu_product *pc) {
+  if (!pc) return;
+  (void)hipStreamSynchronize(pc->stream);
+  (void)hipFree(pc->mem);
+  delete pc;
 }

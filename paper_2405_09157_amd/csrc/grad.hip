@@ -664,8 +664,10 @@ template <typename P, int PER, bool ROWS, bool V4 = false>
 hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
   const int G = b.grid;
   const int64_t T = b.T;
-  hipError_t e = hipMemsetAsync(b.gacc, 0, (size_t)b.n * b.d * sizeof(double), s);
-  if (e != hipSuccess) return e;
+  if (b.grad) {
+    hipError_t e = hipMemsetAsync(b.gacc, 0, (size_t)b.n * b.d * sizeof(double), s);
+    if (e != hipSuccess) return e;
+  }
   init_kernel<P><<<1, kBlk, 0, s>>>(b);
   far_pass<P, ROWS ? 1 : PER><<<G, kBlk, 0, s>>>(b, b.ubar, b.v1);
   far_final<<<1, kW, 0, s>>>(b, 1);
@@ -698,6 +700,7 @@ hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
   mean_kernel<<<1, kBlk, 0, s>>>(b);
   far_pass<P, ROWS ? 1 : PER><<<G, kBlk, 0, s>>>(b, b.ubar, -1);
   far_final<<<1, kW, 0, s>>>(b, 0);
+  if (!b.grad) return hipGetLastError();  // the map's value only
   lambda_init<P><<<1, kBlk, 0, s>>>(b, gv);
   // reverse, one segment at a time: recompute its tape (unless kept), then walk it back
   for (int64_t sg = nseg - 1; sg >= 0; --sg) {

@@ -180,6 +180,10 @@ int build_graph(scp_mwu_ctx *c) {
 }
 
 // Run up to k passes of the current test; stop early once it has ended.
+// Whole chunks replay the captured graph and the state is read after each
+// (a test that ended stops the loop); fewer than `chunk` passes are enqueued
+// back to back and the state is read once: a pass whose test has ended does
+// nothing, so passes past the end cost only their launch.
 int run_iters(scp_mwu_ctx *c, int64_t k) {
   int rc;
   const bool cert = (c->flags & SCP_MWU_FLAG_CERTIFICATES) && c->problem == kSES;
@@ -191,9 +195,10 @@ int run_iters(scp_mwu_ctx *c, int64_t k) {
       if (rc) return rc;
       k -= c->chunk;
     } else {
-      rc = c->hip(pass(c, cert && k == 1, c->stream), "pass launch");
-      if (rc) return rc;
-      k -= 1;
+      for (; k > 0; --k) {
+        rc = c->hip(pass(c, cert && k == 1, c->stream), "pass launch");
+        if (rc) return rc;
+      }
     }
     rc = read_state(c);
     if (rc) return rc;
@@ -317,8 +322,11 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   const int64_t ld = desc->ld ? desc->ld : desc->d;
   if (ld < desc->d) return bad("ld < d");
   if ((uintptr_t)desc->points % elem_size(desc->dtype)) return bad("points misaligned");
-  // a batch of 32 rows is addressed with 32-bit byte offsets
-  if (ld * (int64_t)elem_size(desc->dtype) * 32 >= (int64_t)1 << 30) return bad("row stride too large");
+  // a batch of up to 64 rows is addressed with 32-bit lane byte offsets, and a
+  // column past d gets the offset 2^30 (plus up to 60 rows of steps): both the
+  // batch's byte range and that offset stay below 2^31, and the range stays
+  // below 2^30 so that the invalid offset always falls outside it
+  if (ld * (int64_t)elem_size(desc->dtype) * 64 >= (int64_t)1 << 30) return bad("row stride too large");
   if (desc->problem == SCP_MWU_PROBLEM_SVM) {
     if (desc->n_pos < 1 || desc->n_pos > desc->n - 1) return bad("n_pos outside [1, n-1]");
     if (desc->radii) return bad("radii given for SVM");
@@ -587,7 +595,7 @@ int scp_mwu_get_vector(scp_mwu_ctx *c, int32_t which, double *y) {
 int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points, double *value,
                      int32_t checkpoint_every) {
   if (!c) return SCP_MWU_E_INVAL;
-  if (!grad_points) return c->fail(SCP_MWU_E_INVAL, "grad_points is NULL");
+  if (!grad_points && !value) return c->fail(SCP_MWU_E_INVAL, "grad_points and value are both NULL");
   if (!std::isfinite(grad_value)) return c->fail(SCP_MWU_E_INVAL, "grad_value is not finite");
   if (checkpoint_every < 0 || checkpoint_every > grad::kSegment)
     return c->fail(SCP_MWU_E_INVAL, "checkpoint_every must be 0 (keep the whole tape) or 1 .. 50");
@@ -617,8 +625,10 @@ int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points, doub
   b.full = full ? 1 : 0;
   b.seg = full ? grad::kSegment : checkpoint_every;
   const int64_t d = c->d, K = b.seg, L = full ? c->T : K;  // tape slots
+  // the value alone needs neither the per-row coefficients nor the accumulator
+  const int64_t rows = grad_points ? c->n : 0;
   const int64_t sizes[] = {d, grad::ck_count(c->T, K) * d, (L + 1) * d, L * d, (L + 1) * 4,
-                           (int64_t)b.grid * (d + 2), d, K * d, d, d, 8, K * c->n, K * c->n, 2, c->n * d};
+                           (int64_t)b.grid * (d + 2), d, K * d, d, d, 8, K * rows, K * rows, 2, rows * d};
   int64_t total = 0;
   for (int64_t v : sizes) total += (v + 31) / 32 * 32;
   void *mem = nullptr;

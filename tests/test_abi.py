@@ -68,3 +68,31 @@ def test_product_path_has_no_oracle_or_fallback():
             if fn.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "oracle" not in re.sub(r"#.*|//.*", "", text).lower().replace("oracle_program", ""), fn
+
+
+def test_init_rejects_row_strides_past_the_lane_offset_range():
+    """A pass batch spans up to 64 rows addressed by 32-bit lane offsets, and a
+    column past d reads through the out-of-range offset 2^30: init must reject
+    a row stride whose 64-row span reaches 2^30 bytes (checked before any
+    device call, so this runs without a GPU)."""
+    from paper_2405_09157_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libscpmwu.so not built (run __graft_entry__.build())")
+    lib = _lib.load()
+
+    def init_with(ld, dtype):
+        desc = _lib.scp_mwu_desc()
+        desc.struct_size = ctypes.sizeof(_lib.scp_mwu_desc)
+        desc.problem, desc.dtype, desc.n, desc.d, desc.ld = _lib.SCP_MWU_PROBLEM_SES, dtype, 1000, 3, ld
+        desc.points = 4096                    # never dereferenced: validation fails first
+        desc.v1_index = 1000                  # invalid, checked after the stride: no device work either way
+        ctx = ctypes.c_void_p()
+        return lib.scp_mwu_init(ctypes.byref(desc), ctypes.byref(ctx)), lib.scp_mwu_last_error(None)
+
+    for dtype, es in ((_lib.SCP_MWU_F32, 4), (_lib.SCP_MWU_F64, 8), (_lib.SCP_MWU_BF16, 2)):
+        ld = (1 << 30) // (64 * es)           # 64 rows span exactly 2^30 bytes
+        rc, msg = init_with(ld, dtype)
+        assert rc == _lib.SCP_MWU_E_INVAL and b"row stride" in msg, (dtype, rc, msg)
+        # one element less passes the stride check and fails on v1_index
+        rc, msg = init_with(ld - 1, dtype)
+        assert rc == _lib.SCP_MWU_E_INVAL and b"v1_index" in msg, (dtype, rc, msg)

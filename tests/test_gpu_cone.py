@@ -80,12 +80,48 @@ def test_product_exp_errors():
     from paper_2405_09157_amd import _lib
     m = torch.zeros(10, dtype=torch.float64, device="cuda")
     p = torch.empty_like(m)
-    for offs, n0, eta in (([3, 4, 10], 3, 1.0),     # a block of length 1
-                          ([2, 6, 10], 3, 1.0),     # offsets[0] != n_orth
-                          ([3, 10], 3, 0.0),        # eta <= 0
-                          ([3, 10], 3, float("inf"))):
+    for offs, n0, length in (([3, 4, 10], 3, 10),     # a block of length 1
+                             ([2, 6, 10], 3, 10),     # offsets[0] != n_orth
+                             ([3, 10], 3, 12),        # offsets[nblocks] != length
+                             ([], 5, 10),             # orthant only, n_orth != length
+                             ([], 0, 0)):             # empty cone
         with pytest.raises(scp.ScpMwuError) as e:
-            _lib.scp_mwu_product_exp(m.data_ptr(), n0, offs, eta, p.data_ptr())
+            _lib.scp_mwu_product_init(n0, offs, length)
         assert e.value.code == scp.SCP_MWU_E_INVAL
-    with pytest.raises(scp.ScpMwuError):
-        _lib.scp_mwu_product_exp(m.data_ptr(), 0, [], 1.0, p.data_ptr())   # empty cone
+    h = _lib.scp_mwu_product_init(3, [3, 10], 10)
+    try:
+        for eta in (0.0, -1.0, float("inf"), float("nan")):
+            with pytest.raises(scp.ScpMwuError) as e:
+                _lib.scp_mwu_product_exp(h, m.data_ptr(), eta, p.data_ptr())
+            assert e.value.code == scp.SCP_MWU_E_INVAL
+        with pytest.raises(scp.ScpMwuError):
+            _lib.scp_mwu_product_exp(h, m.data_ptr(), 1.0, m.data_ptr())   # p aliases m
+    finally:
+        _lib.scp_mwu_product_destroy(h)
+    with pytest.raises(ValueError):
+        scp.ProductCone(3, [6]).exp(torch.zeros(11, dtype=torch.float64, device="cuda"), 1.0)
+
+
+def test_product_cone_handle_reused():
+    """One handle, many iterates (no host work per call beyond the launches):
+    each equals the oracle's, and enqueued calls without the ln Tr readback
+    leave the same p as a call that reads it."""
+    import torch
+    import paper_2405_09157_amd as scp
+    n_orth, dims = 50, [4, 1, 30, 7] * 25
+    offs = layout(n_orth, dims)
+    rng = np.random.default_rng(11)
+    with scp.ProductCone(n_orth, dims) as pc:
+        for rep in range(3):
+            m = rng.standard_normal(offs[-1]) * (1.0 + 50.0 * rep)
+            md = torch.from_numpy(m).cuda()
+            p_async, none = pc.exp(md, 0.5, log_trace=False)
+            assert none is None
+            p, lt = pc.exp(md, 0.5)
+            p0, lt0 = scmwu.product_iterate(m, n_orth, offs, 0.5)
+            torch.cuda.synchronize()
+            assert torch.equal(p, p_async)
+            lam = 0.5 * float(np.abs(m).max()) * 8.0
+            tol = 1e-14 * (1.0 + lam)
+            assert np.abs(p.cpu().numpy() - p0).max() <= tol * np.abs(p0).max()
+            assert abs(lt - lt0) <= tol

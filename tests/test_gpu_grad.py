@@ -219,3 +219,26 @@ def test_autograd_function():
     assert abs(float(R.detach()) - R0) <= TIGHT * R0
     assert Xg.grad.dtype == torch.float32
     assert np.abs(Xg.grad.cpu().double().numpy() - 3.0 * G0).max() <= GRAD_TOL * 3.0 * np.abs(G0).max()
+
+
+def test_radius_alone_and_autograd_without_gradients():
+    """grad_points = NULL runs the forward map only: the same R as the full
+    call; ses_radius under no_grad (or on points without requires_grad) runs
+    no reverse pass and keeps no context."""
+    import torch
+    import paper_2405_09157_amd as scp
+    X, V = points(400, 5, 16, "f32")
+    alpha = 2.0 * oses.setup(V).D / 3.0
+    with scp.MWU(X, "ses", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP) as m:
+        m.step(alpha, 80, 0, reset=True)
+        R_only = m.radius()
+        R_full, _ = m.backward(1.0)
+        assert m.radius(checkpoint_every=0) == R_only
+    assert R_only == R_full
+    R0, _ = ses_grad.radius_grad(V, alpha, 80)
+    assert abs(R_only - R0) <= TIGHT * R0
+    with torch.no_grad():
+        R = scp.ses_radius(X.clone().requires_grad_(True), alpha, 80)
+    assert float(R) == R_only and not R.requires_grad
+    R = scp.ses_radius(X, alpha, 80)                 # X does not require grad
+    assert float(R) == R_only and not R.requires_grad

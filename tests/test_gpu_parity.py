@@ -215,17 +215,99 @@ def test_ses_end_to_end_small_config(seed):
     assert bool(out["converged"]) == ref.converged
 
 
-def test_ses_bf16_vs_original_points():
+def _enclosing_alpha(V):
+    """An enclosing radius (>= OPT): the sphere about the centroid through the
+    farthest point, widened by 5 %, so that a test at it cannot separate."""
+    return 1.05 * float(np.max(np.linalg.norm(V - V.mean(0), axis=1)))
+
+
+@pytest.mark.parametrize("n,d,seed,format_allows", [(10000, 100, 5, True), (4000, 3, 6, False)])
+def test_ses_bf16_fixed_schedule_vs_original_points(n, d, seed, format_allows):
+    """BF16 storage against the oracle on the ORIGINAL points, search path
+    pinned (fixed alpha, fixed T, no early exit): the final mean ubar(T) (in
+    units of alpha) and its monitor value f(T) (relative).
+
+    The error splits into the format's own effect and the kernel's.  The
+    format's: rounding to BF16 moves each coordinate by at most 2^-9 of its
+    magnitude, so every point by at most 2^-9 ||v_i||, and f (1-Lipschitz in
+    the points and in the mean) by at most 2^-9 max ||v_i|| plus the move of
+    the mean; the oracle run on the stored values measures it exactly.  The
+    kernel's: against the oracle on the stored values, within BF16_STEP.  So
+    the result against the original points must be within the sum.  In
+    d = 100 (N(0, I) rows) the rounding errors of a row largely cancel in its
+    distance and the format allows the RESULT_BF16 = 1e-3 bar, which is then
+    asserted; in d = 3 one coordinate carries most of a distance and the
+    format alone moves f by up to 2^-9 ~ 2e-3 (measured 2.7e-3 with the
+    mean's move), above that bar."""
     import torch
-    V = synth.ses_uniform(2000, 3, 1).astype(np.float32)
-    ref = oses.solve(V.astype(np.float64), eps=1e-3)
-    m = mwu(dev(V, torch.float32), "ses", eps=1e-3, storage="bf16")
+    import paper_2405_09157_amd as scp
+    V = synth.ses_gaussian_outliers(n, d, seed).astype(np.float32)
+    V64 = V.astype(np.float64)
+    _, Vq = bf16_points(V)
+    alpha, T = _enclosing_alpha(V64), 400
+    res = {}
+    for name, pts in (("orig", V64), ("stored", Vq)):
+        P = oses.setup(pts)
+        r = oses.ftp(P, alpha, T, math.sqrt(math.log(P.r) / T), early_stop=False, record=True)
+        assert r.outcome == oses.T_REACHED
+        res[name] = (r.S / T, r.f_traj[-1])
+    m = mwu(dev(V, torch.float32), "ses", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP, storage="bf16")
+    info = m.step(alpha, T, T + 1, reset=True)     # T + 1 passes evaluate f(T)
+    ub = np.array(m.vector(0))
+    m.close()
+    assert info["outcome_name"] == "t_reached" and info["t"] == T
+    # the format's own effect, from the oracle alone
+    fu = np.linalg.norm(res["stored"][0] - res["orig"][0]) / alpha
+    ff = abs(res["stored"][1] - res["orig"][1]) / res["orig"][1]
+    assert ff <= 2.0 ** -9 * np.max(np.linalg.norm(V64, axis=1)) / res["orig"][1] + fu
+    du_o = np.linalg.norm(ub - res["orig"][0]) / alpha
+    df_o = abs(info["f_last"] - res["orig"][1]) / res["orig"][1]
+    du_q = np.linalg.norm(ub - res["stored"][0]) / alpha
+    df_q = abs(info["f_last"] - res["stored"][1]) / res["stored"][1]
+    print(f"bf16 fixed schedule n={n} d={d}: vs original du={du_o:.2e} df={df_o:.2e}; "
+          f"format alone du={fu:.2e} df={ff:.2e}; vs stored du={du_q:.2e} df={df_q:.2e}")
+    assert du_q <= BF16_STEP and df_q <= BF16_STEP
+    assert du_o <= fu + BF16_STEP and df_o <= ff + BF16_STEP
+    if format_allows:
+        assert fu <= 0.5 * RESULT_BF16 and ff <= 0.5 * RESULT_BF16
+        assert du_o <= RESULT_BF16 and df_o <= RESULT_BF16
+    else:
+        assert max(fu, ff) > RESULT_BF16       # the case the bar cannot apply to
+
+
+def test_ses_bf16_solve_vs_original_points():
+    """End to end: the eps-solve with BF16 storage against the oracle's solve
+    of the ORIGINAL points (N(0, I) with 1 % of the rows x5, the headline
+    workload's distribution at n = 4000, d = 100): the same number of tests,
+    the radius within RESULT_BF16 relative; the returned centre realises its
+    radius on the stored points and encloses the original points within
+    RESULT_BF16.  The centres themselves are not compared: the returned
+    centre is the mean of least f over the tests, and when a test ends a few
+    iterations apart on the two sides (2074 against 2070 iterations here) it
+    is another iterate; any centre whose f is the certified radius is a
+    correct output (the fixed-schedule test above compares the means)."""
+    import torch
+    V = synth.ses_gaussian_outliers(4000, 100, 7).astype(np.float32)
+    V64 = V.astype(np.float64)
+    _, Vq = bf16_points(V)
+    ref = oses.solve(V64, eps=1e-2)
+    m = mwu(dev(V, torch.float32), "ses", eps=1e-2, storage="bf16")
     out = m.solve()
     m.close()
-    assert abs(out["radius"] - ref.radius) / ref.radius <= RESULT_BF16 * 10  # see below
-    # BF16 keeps 8 significand bits: each coordinate moves by up to 2^-9 relative,
-    # so radii differ by up to ~2^-9 * max|v| / R (about 4e-3 here); the
-    # 1e-3 result bar is checked at scale on the large configuration.
+    c = np.array(out["center"])
+    dr = abs(out["radius"] - ref.radius) / ref.radius
+    dc = np.linalg.norm(c - ref.center) / ref.radius
+    print(f"bf16 solve: tests {out['tests']} / {len(ref.steps)}, iters {out['iters']} / {ref.iters}, "
+          f"radius {out['radius']:.9g} / {ref.radius:.9g} ({dr:.2e}), centre {dc:.2e}")
+    assert out["tests"] == len(ref.steps)
+    assert dr <= RESULT_BF16
+    # the radius is the kernel's f, whose distances carry binary32 per-element
+    # arithmetic with BF16 storage: <= 17 * 2^-24 relative on d^2 (16-column
+    # partials), plus 2^-24 |ubar| / f for the mean rounded to binary32
+    far_q = np.max(np.linalg.norm(Vq - c, axis=1))
+    assert abs(far_q - out["radius"]) <= 2e-6 * out["radius"]
+    far_o = np.max(np.linalg.norm(V64 - c, axis=1))
+    assert far_o <= out["radius"] * (1.0 + RESULT_BF16)
 
 
 def test_ses_state_roundtrip_and_resume():
