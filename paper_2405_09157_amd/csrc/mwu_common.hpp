@@ -98,6 +98,7 @@ struct DevState {
   int32_t early;   // Section 5 exits enabled
   int32_t degenerate;
   int32_t cert;    // a certificate was computed on the last pass
+  int32_t pending; // records of a fused pass wait for their epilogue
   // monitor
   double f_prev;   // f of the previous monitored iteration (-1: none)
   double f_best;
@@ -173,6 +174,9 @@ hipError_t launch_quantize_fp8(const float *src, int64_t n, int64_t d, int64_t l
 
 #define SCPMWU_DECLARE_TYPED(name)                                                              \
   hipError_t launch_pass_##name(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s); \
+  hipError_t launch_fused_##name(const LaunchCfg &c, const PassArgs &a, int cur, int64_t rec_stride,   \
+                                 hipStream_t s);                                                  \
+  hipError_t launch_flush_##name(bool cert, int grid, const PassArgs &a, hipStream_t s);          \
   hipError_t launch_epilogue_##name(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s); \
   hipError_t launch_monitor_##name(int grid, const PassArgs &a, const double *center,            \
                                    int64_t exclude, int mode, double *out, hipStream_t s);      \

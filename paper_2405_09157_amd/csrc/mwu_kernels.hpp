@@ -437,8 +437,32 @@ __device__ __forceinline__ int lane_col(int cl, int k) {
 // The SES pass of one problem, run by workgroup vb of the vg workgroups
 // assigned to it (its batches are b = vb * 8 + wave, strided by vg * 8; its
 // record goes to partials[vb]).
-template <typename T, int EPL, int VEC, bool CERT, int PFM>
-__device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg) {
+// What a pass needs from the state of its test: the status, the exponent
+// scale kappa = kscale * t, the carried shift bound, the candidate mean, and
+// where the workgroup records go.
+struct PassIn {
+  int32_t status;
+  double kappa, Gb;
+  const double *ybar;
+  double *rec;
+};
+
+// The pass reads its inputs through a prologue object: pre() runs before the
+// workgroup's first batch of rows is requested, post() once it is in flight
+// and returns the inputs (the fused kernel issues the previous pass's record
+// loads in pre() and runs that pass's epilogue in post()); the plain form
+// reads the state as it is.
+struct StatePrologue {
+  const PassArgs &a;
+  __device__ __forceinline__ void pre() {}
+  __device__ __forceinline__ PassIn post() {
+    const DevState *st = a.st;
+    return PassIn{st->status, st->kscale * (double)st->t, st->shift_bound, a.vec + kVecMean * a.d, a.partials};
+  }
+};
+
+template <typename T, int EPL, int VEC, bool CERT, int PFM, typename Pro>
+__device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg, Pro &prologue) {
   using Sh = PassShape<T, EPL, kSES, PFM>;
   constexpr int SB = Sh::SB, B = Sh::B;
   using Regs = typename Sh::Regs;
@@ -456,22 +480,29 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg)
   __shared__ double s_sc[kPassWaves][8];
   __shared__ double s_ctr[kG * EPL];  // the candidate (ubar or wbar), zero-padded
 
-  DevState *st = a.st;
-  const int32_t status0 = __builtin_amdgcn_readfirstlane(st->status);  // grid-uniform
-
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, cl = lane & 15;
   const int64_t n = a.n, ld = a.ld;
   const int d = (int)a.d;
   const T *__restrict__ X = reinterpret_cast<const T *>(a.X);
-  const double kappa = st->kscale * (double)st->t;
-  const double Gb = st->shift_bound;
-  const double *ybar = a.vec + kVecMean * d;
   const double *__restrict__ radii = a.radii;
   const int64_t v1 = a.v1;
-
-  for (int c = tid; c < kG * EPL; c += kPassBlock) s_ctr[c] = c < d ? ybar[c] : 0.0;
+  // set by the prologue (grid-uniform), read by the phases below
+  int32_t status0 = kRunning;
+  double kappa = 0.0, Gb = 0.0;
+  double *rec_base = nullptr;
+  auto start = [&]() {
+    const PassIn in = prologue.post();
+    status0 = __builtin_amdgcn_readfirstlane(in.status);
+    kappa = in.kappa;
+    Gb = in.Gb;
+    rec_base = in.rec;
+    for (int c = tid; c < kG * EPL; c += kPassBlock) s_ctr[c] = c < d ? in.ybar[c] : 0.0;
+    // status0 is the same for the whole grid: either every wave returns
+    // after this barrier or none does
+    __syncthreads();
+  };
   double wacc[EPL], cacc[CERT ? EPL : 1];
 #pragma unroll
   for (int k = 0; k < EPL; ++k) wacc[k] = 0.0;
@@ -618,9 +649,6 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg)
     wave_lds_sync();
   };
   const int64_t b0 = (int64_t)vb * kPassWaves + wave;
-  // status0 is the same for the whole grid: either every wave returns below
-  // (after this barrier) or none does
-  __syncthreads();
   if constexpr (PFM == kPrefetchRegs) {
     // two register batches, unrolled by two so that neither is copied: the
     // loads of the next batch are in flight while the current one is
@@ -629,7 +657,9 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg)
     // waits for the current batch never include the next one's loads.
     Regs xa, xb;
     int64_t b = b0;
+    prologue.pre();
     load_batch(xa, b);
+    start();
     if (status0 != kRunning) return;
     while (b < nb) {
       const int64_t b1 = b + GW;
@@ -642,11 +672,15 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg)
       b = b2;
     }
   } else {
+    // the first batch's loads go out before the prologue (a batch past the
+    // end reads zeros without touching memory)
     Regs xs;
+    prologue.pre();
+    load_batch(xs, b0);
+    start();
+    if (status0 != kRunning) return;
     for (int64_t b = b0; b < nb; b += GW) {
-      load_batch(xs, b);
-      // the first batch's loads go out before the state word is waited on
-      if (b == b0 && status0 != kRunning) return;
+      if (b != b0) load_batch(xs, b);
       process(xs, b);
     }
   }
@@ -679,7 +713,7 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg)
     s_sc[wave][6] = fall;
   }
   __syncthreads();
-  double *rec = a.partials + (int64_t)vb * pw;
+  double *rec = rec_base + (int64_t)vb * pw;
   const int dp = rec_dp(d);
   for (int c = tid; c < d; c += kPassBlock) rec[c] = sum_waves(s_vec, c);
   __syncthreads();
@@ -705,6 +739,12 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg)
       v = -INFINITY;
     rec[dp + tid] = v;
   }
+}
+
+template <typename T, int EPL, int VEC, bool CERT, int PFM>
+__device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg) {
+  StatePrologue pro{a};
+  ses_pass_body<T, EPL, VEC, CERT, PFM>(a, vb, vg, pro);
 }
 
 template <typename T, int EPL, int VEC, bool CERT, int PFM>
@@ -945,14 +985,18 @@ __device__ inline int monitor_rules(DevState &S, int64_t k, double f, bool bette
   return status;
 }
 
-constexpr int kPerLane = kMaxD / kWave;  // columns per lane in the one-wave epilogue
+// Columns per lane in the one-wave epilogue: PL = DMAX / 64 for records of
+// at most DMAX columns.
 
 // SES epilogue of pass k, one wave: ORACLE of eq.(ses_oracle), separation
 // test, running mean and the bound for the next pass's exponent shift.
-// S, y (mean), Sv (running sum), v1 are LDS copies; results go to global.
-__device__ inline void ses_epilogue(const PassArgs &a, DevState &S, const double *y, const double *Sv,
-                                    const double *v1, const double *comb, bool cert, bool centred) {
+// S (state), vout (the test's vectors, kNumVec x d) and v1 are LDS copies,
+// updated in place (a lane reads and writes only its own columns).
+template <int PL>
+__device__ inline void ses_epilogue(const PassArgs &a, DevState &S, double *vout, const double *v1,
+                                    const double *comb, bool cert, bool centred) {
   const int d = (int)a.d, lane = threadIdx.x & 63;
+  const double *y = vout + kVecMean * d, *Sv = vout + kVecS * d;
   const double *sc = comb + rec_dp(d);
   const int64_t k = S.t + 1;
   const double Bsum = sc[0], Esum = sc[1], Gsum = sc[2], BD2 = sc[3], Asum = sc[4];
@@ -963,7 +1007,7 @@ __device__ inline void ses_epilogue(const PassArgs &a, DevState &S, const double
   copy = __builtin_amdgcn_readfirstlane(copy);
   wave_lds_sync();
   if (copy)
-    for (int c = lane; c < d; c += kWave) a.vec[kVecBest * d + c] = y[c];
+    for (int c = lane; c < d; c += kWave) vout[kVecBest * d + c] = y[c];
   if (status != kRunning) {
     if (lane == 0) {
       S.status = status;
@@ -974,10 +1018,10 @@ __device__ inline void ses_epilogue(const PassArgs &a, DevState &S, const double
   // W = sum_i a_i (v_i - ubar) = sum a_i v_i - (sum a_i) ubar.  One
   // butterfly sums ||W||^2, (v1 - ubar).W and, with a certificate,
   // ||sum_i b_i (v_i - ubar)||^2.
-  double Wr[kPerLane], u[kPerLane];
+  double Wr[PL], u[PL];
   double p = 0.0, r = 0.0, cc = 0.0;
 #pragma unroll
-  for (int j = 0; j < kPerLane; ++j) {
+  for (int j = 0; j < PL; ++j) {
     const int c = lane + j * kWave;
     // the record holds sum a_i x_i, or (centred) sum a_i (x_i - fl32(ubar))
     Wr[j] = c < d ? comb[c] - Asum * (centred ? y[c] - (double)(float)y[c] : y[c]) : 0.0;
@@ -997,7 +1041,7 @@ __device__ inline void ses_epilogue(const PassArgs &a, DevState &S, const double
   const double nW = sqrt(p);
   const double alpha = S.alpha, g1 = S.gamma1;
 #pragma unroll
-  for (int j = 0; j < kPerLane; ++j) {
+  for (int j = 0; j < PL; ++j) {
     const int c = lane + j * kWave;
     u[j] = 0.0;
     if (c < d) u[j] = nW > 0.0 ? v1[c] + (alpha - g1) * (Wr[j] / nW) : v1[c];
@@ -1012,22 +1056,22 @@ __device__ inline void ses_epilogue(const PassArgs &a, DevState &S, const double
   const bool bad = !isfinite(obj) || !(Bsum > 0.0) || !isfinite(nW);
   const bool separated = obj < -S.tau * scale;
 #pragma unroll
-  for (int j = 0; j < kPerLane; ++j) {
+  for (int j = 0; j < PL; ++j) {
     const int c = lane + j * kWave;
-    if (c < d) a.vec[kVecLast * d + c] = u[j];
+    if (c < d) vout[kVecLast * d + c] = u[j];
   }
   double dl = 0.0;
   if (!bad && !separated) {
 #pragma unroll
-    for (int j = 0; j < kPerLane; ++j) {
+    for (int j = 0; j < PL; ++j) {
       const int c = lane + j * kWave;
       if (c < d) {
         const double sm = Sv[c] + u[j];
         const double yn = sm / (double)k;
         const double dd = yn - y[c];
         dl += dd * dd;
-        a.vec[kVecS * d + c] = sm;
-        a.vec[kVecMean * d + c] = yn;
+        vout[kVecS * d + c] = sm;
+        vout[kVecMean * d + c] = yn;
       }
     }
   }
@@ -1053,9 +1097,10 @@ __device__ inline void ses_epilogue(const PassArgs &a, DevState &S, const double
 
 // SVM epilogue of pass k, one wave: ORACLE of eq.(svm_oracle), separation
 // test, the polytope-distance certificate, running means, next slack bound.
-__device__ inline void svm_epilogue(const PassArgs &a, DevState &S, const double *wb, const double *Sv,
-                                    const double *comb) {
+template <int PL>
+__device__ inline void svm_epilogue(const PassArgs &a, DevState &S, double *vout, const double *comb) {
   const int d = (int)a.d, lane = threadIdx.x & 63;
+  const double *wb = vout + kVecMean * d, *Sv = vout + kVecS * d;
   const double *sc = comb + rec_dp(d);
   const double *AP = comb, *AQ = comb + rec_dp(d) + 8;
   const int64_t k = S.t + 1;
@@ -1071,7 +1116,7 @@ __device__ inline void svm_epilogue(const PassArgs &a, DevState &S, const double
   copy = __builtin_amdgcn_readfirstlane(copy);
   wave_lds_sync();
   if (copy)
-    for (int c = lane; c < d; c += kWave) a.vec[kVecBest * d + c] = wb[c];
+    for (int c = lane; c < d; c += kWave) vout[kVecBest * d + c] = wb[c];
   if (status != kRunning) {
     if (lane == 0) {
       S.status = status;
@@ -1099,20 +1144,20 @@ __device__ inline void svm_epilogue(const PassArgs &a, DevState &S, const double
   const double scale = nV + T1 * fabs(s1) + T2 * fabs(s2);
   const bool bad = !isfinite(obj) || !(T1 + T2 > 0.0);
   const bool separated = obj < -S.tau * scale;
-  double w[kPerLane];
+  double w[PL];
 #pragma unroll
-  for (int j = 0; j < kPerLane; ++j) {
+  for (int j = 0; j < PL; ++j) {
     const int c = lane + j * kWave;
     w[j] = 0.0;
     if (c < d) {
       w[j] = nV > 0.0 ? (AP[c] - AQ[c]) / nV : 0.0;
-      a.vec[kVecLast * d + c] = w[j];
+      vout[kVecLast * d + c] = w[j];
     }
   }
   double dl = 0.0, wn = 0.0;
   if (!bad && !separated) {
 #pragma unroll
-    for (int j = 0; j < kPerLane; ++j) {
+    for (int j = 0; j < PL; ++j) {
       const int c = lane + j * kWave;
       if (c < d) {
         const double sm = Sv[c] + w[j];
@@ -1120,8 +1165,8 @@ __device__ inline void svm_epilogue(const PassArgs &a, DevState &S, const double
         const double dd = yn - wb[c];
         dl += dd * dd;
         wn += yn * yn;
-        a.vec[kVecS * d + c] = sm;
-        a.vec[kVecMean * d + c] = yn;
+        vout[kVecS * d + c] = sm;
+        vout[kVecMean * d + c] = yn;
       }
     }
   }
@@ -1188,69 +1233,239 @@ __global__ __launch_bounds__(kBlock) void record_combine_kernel(const double *__
 static_assert(sizeof(DevState) % 8 == 0, "DevState is copied as 8-byte words");
 constexpr int kStateWords = (int)(sizeof(DevState) / 8);
 
-// One workgroup per iteration: every global read (records of the pass that
-// just ran, the state, the mean, the running sum, row v1) is issued at once
-// into LDS; the records are summed in a fixed transposed order; one wave then
-// runs the FP64 epilogue on the LDS copies and writes the state back.  The
-// kernel boundary after the pass makes every record visible: no fences.
-// NT threads: the one-problem epilogue uses kCombBlock, the batched one a
-// smaller block (its instances have few records).
-template <typename T, int PROB, bool CERT, int NT = kCombBlock>
-__device__ __forceinline__ void epilogue_body(const PassArgs &a, int P) {
-  // group partial sums (groups x ncols), or the column sums when a record has
-  // more column pairs than threads
-  __shared__ double s_acc[2 * NT > 2 * kMaxD + 8 ? 2 * NT : 2 * kMaxD + 8];
-  __shared__ double s_comb[2 * kMaxD + 8];
-  __shared__ double s_y[kMaxD], s_S[kMaxD], s_v1[kMaxD];
-  __shared__ DevState s_st;
-  const int d = (int)a.d;
-  const int tid = threadIdx.x;
+// Record groups of the fixed-order combine: column pairs are summed over
+// `groups` interleaved record subsets (record b in subset b mod groups, each
+// in increasing order), then the subset sums in subset order.  The order
+// depends on the record width only, so every kernel that combines a set of
+// records (the epilogue kernel, every workgroup of the fused pass) gets the
+// same bits.
+__host__ __device__ inline int comb_groups(int npairs) {
+  const int g = 1024 / (npairs > 0 ? npairs : 1);
+  return g < 1 ? 1 : (g > 8 ? 8 : g);
+}
+constexpr int kCombAcc = 2048;  // >= comb_groups(p) * 2p for every p
+
+// LDS image of one epilogue: the state, the test's vectors (S, mean, best,
+// last), row v1 and the combined record.
+template <int DMAX>
+struct EpiLDS {
+  DevState st;
+  double vout[kNumVec * DMAX];
+  double v1[DMAX];
+  double comb[2 * DMAX + 8];
+  double acc[kCombAcc];
+};
+
+// Fixed-order sum of P records (the maximum slots by max) into L.comb; all NT
+// threads call it.
+template <int PROB, bool CERT, int NT, int DMAX>
+__device__ __forceinline__ void combine_records(const double *__restrict__ rec, int P, int d, EpiLDS<DMAX> &L) {
   const int dp = rec_dp(d), pw = rec_width(d);
-  const int ncols = rec_read_cols<PROB, CERT>(d);  // the certificate half is read only with one
-  const int nsc = PROB == kSES ? 5 : 4;                      // summed scalars
+  const int ncols = rec_read_cols<PROB, CERT>(d);
+  const int nsc = PROB == kSES ? 5 : 4;  // summed scalars; the rest are maxima
   const int npairs = ncols / 2;
-  const int groups = npairs <= NT ? NT / npairs : 1;
-  // state, mean, running sum, row v1
-  if (tid < kStateWords) reinterpret_cast<double *>(&s_st)[tid] = reinterpret_cast<const double *>(a.st)[tid];
-  for (int c = tid; c < d; c += NT) {
-    s_y[c] = a.vec[kVecMean * d + c];
-    s_S[c] = a.vec[kVecS * d + c];
-    if (PROB == kSES) s_v1[c] = row_value<T>(a, a.v1, c);
-  }
-  for (int jp = tid; jp < npairs * groups; jp += NT) {
+  const int groups = comb_groups(npairs);
+  for (int jp = threadIdx.x; jp < npairs * groups; jp += NT) {
     const int j = jp % npairs, grp = jp / npairs;
     const int c0 = 2 * j;
     const bool m0 = c0 >= dp + nsc && c0 < dp + 8, m1 = c0 + 1 >= dp + nsc && c0 + 1 < dp + 8;
     double acc0 = m0 ? -INFINITY : 0.0, acc1 = m1 ? -INFINITY : 0.0;
-#pragma unroll 16
+#pragma unroll 8
     for (int b = grp; b < P; b += groups) {
-      const double2 v = *reinterpret_cast<const double2 *>(a.partials + (int64_t)b * pw + c0);
+      const double2 v = *reinterpret_cast<const double2 *>(rec + (int64_t)b * pw + c0);
       acc0 = m0 ? fmax(acc0, v.x) : acc0 + v.x;
       acc1 = m1 ? fmax(acc1, v.y) : acc1 + v.y;
     }
-    s_acc[grp * ncols + c0] = acc0;
-    s_acc[grp * ncols + c0 + 1] = acc1;
+    L.acc[grp * ncols + c0] = acc0;
+    L.acc[grp * ncols + c0 + 1] = acc1;
   }
   __syncthreads();
-  for (int c = tid; c < ncols; c += NT) {
+  for (int c = threadIdx.x; c < ncols; c += NT) {
     const bool mx = c >= dp + nsc && c < dp + 8;
     double r = mx ? -INFINITY : 0.0;
-    for (int g = 0; g < groups; ++g) r = mx ? fmax(r, s_acc[g * ncols + c]) : r + s_acc[g * ncols + c];
-    s_comb[c] = r;
+    for (int g = 0; g < groups; ++g) r = mx ? fmax(r, L.acc[g * ncols + c]) : r + L.acc[g * ncols + c];
+    L.comb[c] = r;
   }
   __syncthreads();
-  if (tid >= kWave || s_st.status != kRunning) return;
+}
+
+// The epilogue of the records `rec` (P of them) on the state st_in and the
+// vectors vec_in, into LDS: every read is issued at once, the records are
+// combined in the fixed order, and one wave runs the FP64 epilogue.  It runs
+// when the test is running and records are pending (`force`: the caller knows
+// they are, i.e. a pass kernel just ran; otherwise DevState::pending says so).
+// All NT threads call it; afterwards L.st and L.vout hold the new state and
+// vectors (unchanged when nothing ran).
+template <typename T, int PROB, bool CERT, int NT, int DMAX>
+__device__ __forceinline__ void epilogue_load(const PassArgs &a, const DevState *st_in, const double *vec_in,
+                                              EpiLDS<DMAX> &L) {
+  const int d = (int)a.d, tid = threadIdx.x;
+  if (tid < kStateWords) reinterpret_cast<double *>(&L.st)[tid] = reinterpret_cast<const double *>(st_in)[tid];
+  for (int c = tid; c < kNumVec * d; c += NT) L.vout[c] = vec_in[c];
   if (PROB == kSES)
-    ses_epilogue(a, s_st, s_y, s_S, s_v1, s_comb, CERT, sizeof(T) <= 2);
-  else
-    svm_epilogue(a, s_st, s_y, s_S, s_comb);
-  wave_lds_sync();
-  if (tid < kStateWords) reinterpret_cast<double *>(a.st)[tid] = reinterpret_cast<const double *>(&s_st)[tid];
+    for (int c = tid; c < d; c += NT) L.v1[c] = row_value<T>(a, a.v1, c);
+}
+
+template <typename T, int PROB, bool CERT, int NT, int DMAX>
+__device__ __forceinline__ void epilogue_tail(const PassArgs &a, EpiLDS<DMAX> &L) {
+  if (threadIdx.x < kWave) {
+    if (PROB == kSES)
+      ses_epilogue<DMAX / kWave>(a, L.st, L.vout, L.v1, L.comb, CERT, sizeof(T) <= 2);
+    else
+      svm_epilogue<DMAX / kWave>(a, L.st, L.vout, L.comb);
+  }
+  __syncthreads();
+}
+
+template <typename T, int PROB, bool CERT, int NT, int DMAX>
+__device__ __forceinline__ void epilogue_stage(const PassArgs &a, const DevState *st_in, const double *vec_in,
+                                               const double *rec, int P, bool force, EpiLDS<DMAX> &L) {
+  epilogue_load<T, PROB, CERT, NT, DMAX>(a, st_in, vec_in, L);
+  __syncthreads();
+  if (L.st.status != kRunning || !(force || L.st.pending)) return;  // uniform: read from LDS
+  combine_records<PROB, CERT, NT, DMAX>(rec, P, (int)a.d, L);
+  epilogue_tail<T, PROB, CERT, NT, DMAX>(a, L);
+}
+
+// Write L's state (with the given pending flag) and vectors to global memory.
+template <int NT, int DMAX>
+__device__ __forceinline__ void epilogue_store(EpiLDS<DMAX> &L, int d, int32_t pending, DevState *st_out,
+                                               double *vec_out) {
+  if (threadIdx.x == 0) L.st.pending = pending;
+  __syncthreads();
+  if (threadIdx.x < kStateWords)
+    reinterpret_cast<double *>(st_out)[threadIdx.x] = reinterpret_cast<const double *>(&L.st)[threadIdx.x];
+  for (int c = threadIdx.x; c < kNumVec * d; c += NT) vec_out[c] = L.vout[c];
+}
+
+// One workgroup per iteration (the batched epilogue: one per instance), in
+// place on a.st / a.vec.  The kernel boundary after the pass makes every
+// record visible: no fences.  force: records of a pass that just ran are
+// there (the unfused iteration); otherwise only pending records are applied
+// (the flush after fused passes).
+template <typename T, int PROB, bool CERT, int NT = kCombBlock>
+__device__ __forceinline__ void epilogue_body(const PassArgs &a, int P, bool force = true) {
+  __shared__ EpiLDS<kMaxD> L;
+  epilogue_stage<T, PROB, CERT, NT, kMaxD>(a, a.st, a.vec, a.partials, P, force, L);
+  epilogue_store<NT, kMaxD>(L, (int)a.d, 0, a.st, a.vec);
 }
 
 template <typename T, int PROB, bool CERT>
-__global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P) {
-  epilogue_body<T, PROB, CERT>(a, P);
+__global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P, int force) {
+  epilogue_body<T, PROB, CERT>(a, P, force != 0);
+}
+
+// ============================================== fused epilogue + SES pass
+// One MWU iteration in one launch: every workgroup first runs the epilogue of
+// the previous pass (its records, state and vectors in slot `cur` of two)
+// on its own, redundantly and in the same fixed order, so all workgroups
+// agree bit for bit on the new mean, shift bound and status; workgroup 0
+// writes the new state and vectors to slot 1 - cur, and the pass writes its
+// records to slot 1 - cur.  The previous kernel's boundary makes its records
+// visible; nobody writes what this launch reads.  Records are small
+// (d <= 128, a few hundred KB over all workgroups), so each workgroup reads
+// them from L2.
+//
+// Loads return in order, so the records are requested first (pre()): a
+// thread's first (column pair, record subset) item has all of its loads in
+// flight before the first batch of rows is requested, and the combine and
+// the FP64 tail run while those rows arrive from HBM.  Stale records (none
+// pending) are read harmlessly and ignored.  The item is summed in the order
+// combine_records uses, so the result is bitwise that of the epilogue kernel.
+constexpr int kFuseMaxD = 128;
+constexpr int kRecInFlight = 32;
+
+template <typename T, int NT, int DMAX>
+struct FusedPrologue {
+  const PassArgs &a;
+  int cur, P;
+  int64_t rec_stride;
+  EpiLDS<DMAX> &L;
+  double2 rv[kRecInFlight];
+  double sv, vv, v1v;  // a state word, a vector element, an element of row v1
+
+  static_assert(NT >= kNumVec * DMAX && NT >= kStateWords, "one thread per vector element and state word");
+
+  __device__ __forceinline__ int npairs() const { return rec_read_cols<kSES, false>((int)a.d) / 2; }
+
+  __device__ __forceinline__ void pre() {
+    const int d = (int)a.d, tid = threadIdx.x;
+    const int pw = rec_width(d), np = npairs(), groups = comb_groups(np);
+    const double *rec = a.partials + cur * rec_stride;
+    // state, vectors and row v1 into registers (written to LDS in post())
+    sv = tid < kStateWords ? reinterpret_cast<const double *>(a.st + cur)[tid] : 0.0;
+    vv = tid < kNumVec * d ? a.vec[cur * (int64_t)kNumVec * d + tid] : 0.0;
+    v1v = tid < d ? row_value<T>(a, a.v1, tid) : 0.0;
+    if (tid < np * groups) {
+      const int c0 = 2 * (tid % np), g0 = tid / np;
+#pragma unroll
+      for (int r = 0; r < kRecInFlight; ++r) {
+        const int b = g0 + r * groups;
+        rv[r] = b < P ? *reinterpret_cast<const double2 *>(rec + (int64_t)b * pw + c0) : make_double2(0.0, 0.0);
+      }
+    }
+  }
+
+  __device__ __forceinline__ PassIn post() {
+    const int d = (int)a.d, tid = threadIdx.x;
+    const int64_t vs = (int64_t)kNumVec * d;
+    const int dp = rec_dp(d), pw = rec_width(d);
+    const int np = npairs(), ncols = 2 * np, groups = comb_groups(np), items = np * groups;
+    constexpr int nsc = 5;
+    const double *rec = a.partials + cur * rec_stride;
+    if (tid < kStateWords) reinterpret_cast<double *>(&L.st)[tid] = sv;
+    if (tid < kNumVec * d) L.vout[tid] = vv;
+    if (tid < d) L.v1[tid] = v1v;
+    __syncthreads();
+    if (L.st.status == kRunning && L.st.pending) {  // uniform: read from LDS
+      for (int jp = tid; jp < items; jp += NT) {
+        const int j = jp % np, grp = jp / np;
+        const int c = 2 * j;
+        const bool m0 = c >= dp + nsc && c < dp + 8, m1 = c + 1 >= dp + nsc && c + 1 < dp + 8;
+        double acc0 = m0 ? -INFINITY : 0.0, acc1 = m1 ? -INFINITY : 0.0;
+        int b = grp;
+        if (jp == tid) {  // the item whose loads are in flight
+#pragma unroll
+          for (int r = 0; r < kRecInFlight; ++r) {
+            if (b < P) {
+              acc0 = m0 ? fmax(acc0, rv[r].x) : acc0 + rv[r].x;
+              acc1 = m1 ? fmax(acc1, rv[r].y) : acc1 + rv[r].y;
+            }
+            b += groups;
+          }
+        }
+        for (; b < P; b += groups) {
+          const double2 v = *reinterpret_cast<const double2 *>(rec + (int64_t)b * pw + c);
+          acc0 = m0 ? fmax(acc0, v.x) : acc0 + v.x;
+          acc1 = m1 ? fmax(acc1, v.y) : acc1 + v.y;
+        }
+        L.acc[grp * ncols + c] = acc0;
+        L.acc[grp * ncols + c + 1] = acc1;
+      }
+      __syncthreads();
+      for (int c = tid; c < ncols; c += NT) {
+        const bool mx = c >= dp + nsc && c < dp + 8;
+        double r = mx ? -INFINITY : 0.0;
+        for (int g = 0; g < groups; ++g) r = mx ? fmax(r, L.acc[g * ncols + c]) : r + L.acc[g * ncols + c];
+        L.comb[c] = r;
+      }
+      __syncthreads();
+      epilogue_tail<T, kSES, false, NT, DMAX>(a, L);
+    }
+    if (blockIdx.x == 0)
+      epilogue_store<NT, DMAX>(L, d, L.st.status == kRunning ? 1 : 0, a.st + (1 - cur), a.vec + (1 - cur) * vs);
+    return PassIn{L.st.status, L.st.kscale * (double)L.st.t, L.st.shift_bound, L.vout + kVecMean * d,
+                  a.partials + (1 - cur) * rec_stride};
+  }
+};
+
+template <typename T, int EPL, int VEC, bool CERT, int PFM>
+__global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
+void ses_fused_kernel(PassArgs a, int cur, int P, int64_t rec_stride) {
+  static_assert(kG * EPL <= kFuseMaxD, "fused pass: d <= 128");
+  __shared__ EpiLDS<kFuseMaxD> L;
+  FusedPrologue<T, kPassBlock, kFuseMaxD> pro{a, cur, P, rec_stride, L};
+  ses_pass_body<T, EPL, VEC, CERT, PFM>(a, (int)blockIdx.x, (int)gridDim.x, pro);
 }
 
 // ========================================================== monitor pass
@@ -1397,8 +1612,64 @@ hipError_t launch_epilogue_p(int grid, const PassArgs &a, hipStream_t s) {
     e.partials = l1;
     P = rec_groups(grid);
   }
-  hipLaunchKernelGGL((epilogue_kernel<T, PROB, CERT>), dim3(1), dim3(kCombBlock), 0, s, e, P);
+  hipLaunchKernelGGL((epilogue_kernel<T, PROB, CERT>), dim3(1), dim3(kCombBlock), 0, s, e, P, 1);
   return hipGetLastError();
+}
+
+// The flush after fused passes: the pending records of slot `cur` (if any)
+// applied in place.
+template <typename T>
+hipError_t launch_flush_typed(bool cert, int grid, const PassArgs &a, hipStream_t s) {
+  if (cert)
+    hipLaunchKernelGGL((epilogue_kernel<T, kSES, true>), dim3(1), dim3(kCombBlock), 0, s, a, grid, 0);
+  else
+    hipLaunchKernelGGL((epilogue_kernel<T, kSES, false>), dim3(1), dim3(kCombBlock), 0, s, a, grid, 0);
+  return hipGetLastError();
+}
+
+template <typename T, int EPL, int VEC, int PFM>
+hipError_t launch_fused_p(bool cert, int grid, const PassArgs &a, int cur, int64_t rec_stride, hipStream_t s) {
+  if constexpr (kG * EPL <= kFuseMaxD) {
+    if (cert)
+      hipLaunchKernelGGL((ses_fused_kernel<T, EPL, VEC, true, PFM>), dim3(grid), dim3(kPassBlock), 0, s, a, cur, grid,
+                         rec_stride);
+    else
+      hipLaunchKernelGGL((ses_fused_kernel<T, EPL, VEC, false, PFM>), dim3(grid), dim3(kPassBlock), 0, s, a, cur,
+                         grid, rec_stride);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int EPL, int VEC>
+hipError_t launch_fused_t(const LaunchCfg &c, const PassArgs &a, int cur, int64_t rec_stride, hipStream_t s) {
+  return c.pfm == kPrefetchRegs ? launch_fused_p<T, EPL, VEC, kPrefetchRegs>(c.cert, c.grid, a, cur, rec_stride, s)
+                                : launch_fused_p<T, EPL, VEC, kPrefetchNone>(c.cert, c.grid, a, cur, rec_stride, s);
+}
+
+template <typename T, int EPL>
+hipError_t launch_fused_v(const LaunchCfg &c, const PassArgs &a, int cur, int64_t rec_stride, hipStream_t s) {
+  constexpr int VF = (16 / (int)sizeof(T)) < EPL ? (16 / (int)sizeof(T)) : EPL;
+  if (c.vec == VF) return launch_fused_t<T, EPL, VF>(c, a, cur, rec_stride, s);
+  if constexpr (VF >= 4) {
+    if (c.vec == VF / 2) return launch_fused_t<T, EPL, VF / 2>(c, a, cur, rec_stride, s);
+  }
+  if constexpr (VF > 1) {
+    if (c.vec == 1) return launch_fused_t<T, EPL, 1>(c, a, cur, rec_stride, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_fused_typed(const LaunchCfg &c, const PassArgs &a, int cur, int64_t rec_stride, hipStream_t s) {
+  switch (c.epl) {
+    case 1: return launch_fused_v<T, 1>(c, a, cur, rec_stride, s);
+    case 2: return launch_fused_v<T, 2>(c, a, cur, rec_stride, s);
+    case 4: return launch_fused_v<T, 4>(c, a, cur, rec_stride, s);
+    case 8: return launch_fused_v<T, 8>(c, a, cur, rec_stride, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>

@@ -26,6 +26,9 @@ namespace {
 thread_local std::string g_init_error;
 
 constexpr double kTau = 1e-12;  // relative tie tolerance of the separation test
+// Largest record set the fused pass reads in every workgroup (256 records of
+// d = 128 are 278 KB).
+constexpr int64_t kFuseRecBytes = 288 * 1024;
 
 size_t elem_size(int dt) { return dt == kFP8 ? 1 : (dt == kBF16 ? 2 : (dt == kF32 ? 4 : 8)); }
 
@@ -46,19 +49,26 @@ struct scp_mwu_ctx {
   // constants of the split
   double D = 0, gamma1 = 0, rho = 0, R = 0;
   int64_t r = 0;
-  // device workspace
-  DevState *st = nullptr;
-  double *vec = nullptr, *partials = nullptr, *mon = nullptr;
+  // device workspace: state, vectors and records in two slots (the fused
+  // pass reads one slot and writes the other); st, vec, partials and args
+  // view the current slot `cur`
+  DevState *st_base = nullptr, *st = nullptr;
+  double *vec_base = nullptr, *vec = nullptr, *part_base = nullptr, *partials = nullptr, *mon = nullptr;
+  int64_t rec_stride = 0;  // doubles per record slot
+  int cur = 0;
+  bool fused = false;      // SES with small records: epilogue fused into the next pass
   DevState *host_st = nullptr;  // pinned readback
   int grid = 0;
   LaunchCfg cfg{}, cfg_cert{};
-  PassArgs args{};
+  PassArgs args{}, base{};
   // current test
   bool active = false;
   double alpha = 0, eta = 0;
   int64_t T = 0;
-  // graphs: `chunk` passes, the last one optionally with certificates
-  hipGraphExec_t gexec = nullptr;
+  // graphs: `chunk` passes, the last one optionally with certificates (and
+  // the flush), one per starting slot; gend: the slot a graph ends in
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int gend[2] = {0, 0};
   std::string err;
 
   int fail(int code, const std::string &msg) {
@@ -73,6 +83,17 @@ struct scp_mwu_ctx {
 };
 
 namespace {
+
+// Make slot p current.
+void set_cur(scp_mwu_ctx *c, int p) {
+  c->cur = p;
+  c->st = c->st_base + p;
+  c->vec = c->vec_base + (int64_t)p * kNumVec * c->d;
+  c->partials = c->part_base + (int64_t)p * c->rec_stride;
+  c->args.st = c->st;
+  c->args.vec = c->vec;
+  c->args.partials = c->partials;
+}
 
 // The streaming pass kernel of one MWU iteration (no epilogue).
 hipError_t pass_kernel(scp_mwu_ctx *c, bool cert, hipStream_t s) {
@@ -96,8 +117,37 @@ hipError_t epilogue_kernel(scp_mwu_ctx *c, bool cert, hipStream_t s) {
   }
 }
 
-// One MWU iteration: streaming pass, then combine + epilogue.
+// The fused kernel: the epilogue of the pending records of slot cur, then
+// the pass, whose records and new state go to the other slot.
+hipError_t fused_kernel(scp_mwu_ctx *c, bool cert, hipStream_t s) {
+  const LaunchCfg &cfg = cert ? c->cfg_cert : c->cfg;
+  hipError_t e;
+  switch (c->dtype) {
+    case kF32: e = launch_fused_f32(cfg, c->base, c->cur, c->rec_stride, s); break;
+    case kBF16: e = launch_fused_bf16(cfg, c->base, c->cur, c->rec_stride, s); break;
+    case kFP8: e = launch_fused_fp8(cfg, c->base, c->cur, c->rec_stride, s); break;
+    default: e = launch_fused_f64(cfg, c->base, c->cur, c->rec_stride, s); break;
+  }
+  if (e == hipSuccess) set_cur(c, 1 - c->cur);
+  return e;
+}
+
+// The pending records of the current slot applied (fused mode; the records
+// of a certificate pass need cert).
+hipError_t flush(scp_mwu_ctx *c, bool cert, hipStream_t s) {
+  if (!c->fused) return hipSuccess;
+  switch (c->dtype) {
+    case kF32: return launch_flush_f32(cert, c->grid, c->args, s);
+    case kBF16: return launch_flush_bf16(cert, c->grid, c->args, s);
+    case kFP8: return launch_flush_fp8(cert, c->grid, c->args, s);
+    default: return launch_flush_f64(cert, c->grid, c->args, s);
+  }
+}
+
+// One MWU iteration: streaming pass, then combine + epilogue (in fused mode
+// the epilogue runs at the start of the next pass or in the flush).
 hipError_t pass(scp_mwu_ctx *c, bool cert, hipStream_t s) {
+  if (c->fused) return fused_kernel(c, cert, s);
   hipError_t e = pass_kernel(c, cert, s);
   if (e != hipSuccess) return e;
   return epilogue_kernel(c, cert, s);
@@ -145,6 +195,7 @@ int start_test(scp_mwu_ctx *c, double alpha, int64_t T, bool early) {
   p.gamma1 = c->gamma1;
   p.patience = c->patience;
   p.early = early ? 1 : 0;
+  set_cur(c, 0);
   hipError_t e;
   switch (c->dtype) {
     case kF32: e = launch_init_f32(c->args, p, c->problem, c->stream); break;
@@ -161,8 +212,12 @@ int start_test(scp_mwu_ctx *c, double alpha, int64_t T, bool early) {
   return SCP_MWU_OK;
 }
 
+// The graph of `chunk` passes starting in the current slot (then the flush
+// of the last pass's records); capture launches nothing, so the slot is
+// restored afterwards and the graph's end slot kept.
 int build_graph(scp_mwu_ctx *c) {
-  if (c->gexec) return SCP_MWU_OK;
+  const int p0 = c->cur;
+  if (c->gexec[p0]) return SCP_MWU_OK;
   hipGraph_t g = nullptr;
   int rc = c->hip(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
   if (rc) return rc;
@@ -170,11 +225,14 @@ int build_graph(scp_mwu_ctx *c) {
   hipError_t e = hipSuccess;
   for (int k = 0; k < c->chunk && e == hipSuccess; ++k)
     e = pass(c, cert && k == c->chunk - 1, c->cap_stream);
+  if (e == hipSuccess) e = flush(c, cert, c->cap_stream);
+  c->gend[p0] = c->cur;
+  set_cur(c, p0);
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess) return c->hip(e, "capture pass");
   rc = c->hip(e2, "end capture");
   if (rc) return rc;
-  e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&c->gexec[p0], g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   return c->hip(e, "graph instantiate");
 }
@@ -191,14 +249,17 @@ int run_iters(scp_mwu_ctx *c, int64_t k) {
     if (k >= c->chunk && c->chunk > 1) {
       rc = build_graph(c);
       if (rc) return rc;
-      rc = c->hip(hipGraphLaunch(c->gexec, c->stream), "graph launch");
+      rc = c->hip(hipGraphLaunch(c->gexec[c->cur], c->stream), "graph launch");
       if (rc) return rc;
+      set_cur(c, c->gend[c->cur]);
       k -= c->chunk;
     } else {
       for (; k > 0; --k) {
         rc = c->hip(pass(c, cert && k == 1, c->stream), "pass launch");
         if (rc) return rc;
       }
+      rc = c->hip(flush(c, cert, c->stream), "flush launch");
+      if (rc) return rc;
     }
     rc = read_state(c);
     if (rc) return rc;
@@ -286,11 +347,12 @@ const char *scp_mwu_last_error(const scp_mwu_ctx *ctx) {
 void scp_mwu_destroy(scp_mwu_ctx *c) {
   if (!c) return;
   hipStreamSynchronize(c->stream);
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  for (auto &g : c->gexec)
+    if (g) hipGraphExecDestroy(g);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
-  hipFree(c->st);
-  hipFree(c->vec);
-  hipFree(c->partials);
+  hipFree(c->st_base);
+  hipFree(c->vec_base);
+  hipFree(c->part_base);
   hipFree(c->mon);
   hipFree(c->owned);
   hipFree(c->owned_scales);
@@ -411,9 +473,16 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   c->cfg_cert = LaunchCfg{grid, epl, vec, true, pfm};
 
   const int pw = partial_width((int)c->d);
-  if (hipMalloc(&c->st, sizeof(DevState)) != hipSuccess ||
-      hipMalloc(&c->vec, sizeof(double) * kNumVec * c->d) != hipSuccess ||
-      hipMalloc(&c->partials, sizeof(double) * (size_t)(grid + rec_groups(grid)) * pw) != hipSuccess ||
+  // fused epilogue for SES when every workgroup can read all records from
+  // L2 cheaply: d <= 128 and at most kFuseRecBytes of records
+  c->fused = c->problem == kSES && kG * epl <= 128 &&
+             (int64_t)grid * (((c->d + 1) & ~1) + 8) * 8 <= kFuseRecBytes;
+  if (const char *fe = getenv("SCPMWU_FUSED"))
+    if (fe[0] == '0') c->fused = false;
+  c->rec_stride = (int64_t)(grid + rec_groups(grid)) * pw;
+  if (hipMalloc(&c->st_base, 2 * sizeof(DevState)) != hipSuccess ||
+      hipMalloc(&c->vec_base, 2 * sizeof(double) * kNumVec * c->d) != hipSuccess ||
+      hipMalloc(&c->part_base, 2 * sizeof(double) * (size_t)c->rec_stride) != hipSuccess ||
       hipMalloc(&c->mon, sizeof(double) * (size_t)grid * 4) != hipSuccess ||
       hipHostMalloc((void **)&c->host_st, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
     return fail(SCP_MWU_E_NOMEM, "workspace allocation");
@@ -427,10 +496,12 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   a.radii = c->radii;
   a.v1 = c->v1;
   a.n_pos = c->n_pos;
-  a.st = c->st;
-  a.vec = c->vec;
-  a.partials = c->partials;
   a.scales = c->owned_scales;
+  a.st = c->st_base;
+  a.vec = c->vec_base;
+  a.partials = c->part_base;
+  c->base = a;
+  set_cur(c, 0);
 
   // D (one streaming pass): SES distance from v1, SVM largest norm.
   c->r = c->problem == kSES ? 2 * (c->n - 1) : c->n;
@@ -470,18 +541,26 @@ int scp_mwu_time_passes(scp_mwu_ctx *c, int32_t k, double *ms_pass, double *ms_i
   if (!ms_pass || !ms_iter || k < 1)
     return c->fail(SCP_MWU_E_INVAL, "time_passes: k >= 1 and both outputs required");
   if (!c->active) return c->fail(SCP_MWU_E_STATE, "no test started");
-  // three events per iteration: before the pass, between pass and epilogue, after
+  // three events per iteration: before the pass, between pass and epilogue,
+  // after.  Fused mode: one kernel is the whole iteration (its epilogue part
+  // being the previous pass's), timed as both; the flush follows, untimed.
   std::vector<hipEvent_t> ev(3 * (size_t)k, nullptr);
   int rc = SCP_MWU_OK;
   for (auto &e : ev)
     if (!rc) rc = c->hip(hipEventCreate(&e), "event create");
   for (int32_t i = 0; i < k && !rc; ++i) {
     rc = c->hip(hipEventRecord(ev[3 * i], c->stream), "event record");
-    if (!rc) rc = c->hip(pass_kernel(c, false, c->stream), "pass launch");
-    if (!rc) rc = c->hip(hipEventRecord(ev[3 * i + 1], c->stream), "event record");
-    if (!rc) rc = c->hip(epilogue_kernel(c, false, c->stream), "epilogue launch");
+    if (c->fused) {
+      if (!rc) rc = c->hip(fused_kernel(c, false, c->stream), "pass launch");
+      if (!rc) rc = c->hip(hipEventRecord(ev[3 * i + 1], c->stream), "event record");
+    } else {
+      if (!rc) rc = c->hip(pass_kernel(c, false, c->stream), "pass launch");
+      if (!rc) rc = c->hip(hipEventRecord(ev[3 * i + 1], c->stream), "event record");
+      if (!rc) rc = c->hip(epilogue_kernel(c, false, c->stream), "epilogue launch");
+    }
     if (!rc) rc = c->hip(hipEventRecord(ev[3 * i + 2], c->stream), "event record");
   }
+  if (!rc) rc = c->hip(flush(c, false, c->stream), "flush launch");
   if (!rc) rc = c->hip(hipEventSynchronize(ev.back()), "event sync");
   double tp = 0.0, ti = 0.0;
   for (int32_t i = 0; i < k && !rc; ++i) {

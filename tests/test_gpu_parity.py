@@ -94,6 +94,27 @@ def ses_compare_steps(V_dev, V64, alpha, T, K, flags_noearly=True, radii=None, v
     return worst
 
 
+@pytest.mark.parametrize("n,d,grid,storage", [(50000, 64, 16, None), (40000, 100, 12, None), (30001, 100, 8, "bf16"),
+                                              (25000, 33, 8, None), (70000, 16, 24, "fp8")])
+def test_ses_step_parity_small_grids(n, d, grid, storage):
+    """Small grids (many rounds of batches per wave) through the fused pass:
+    step outputs match the oracle at the summation-order bar (BF16 and FP8 at
+    their step bar, on the stored values)."""
+    import torch
+    V = synth.ses_gaussian_outliers(n, d, seed=n + 3 * d).astype(np.float32)
+    if storage == "bf16":
+        _, V64 = bf16_points(V)
+        tol = BF16_STEP
+    elif storage == "fp8":
+        codes, scales = synth.fp8_rows(V)
+        V64 = synth.fp8_values(codes, scales)
+        tol = BF16_STEP
+    else:
+        V64, tol = V.astype(np.float64), TIGHT
+    P = oses.setup(V64)
+    ses_compare_steps(dev(V, torch.float32), V64, 0.8 * P.D, 2000, 25, tol=tol, grid=grid, storage=storage)
+
+
 @pytest.mark.parametrize("n,d", [(3000, 100), (1001, 3), (517, 64), (2000, 256), (300, 7), (64, 1), (2, 5)])
 def test_ses_step_parity_f32(n, d):
     import torch
