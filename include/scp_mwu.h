@@ -96,9 +96,15 @@ enum {
   SCP_MWU_FLAG_THEORY = 2,        /* solve with T = T_theory of the meta theorem
                                      (no cap) and no early exits: the certified
                                      (1 +- eps) guarantee, at its full cost */
-  SCP_MWU_FLAG_CERTIFICATES = 4   /* SES on points: also compute the weak-duality
+  SCP_MWU_FLAG_CERTIFICATES = 4,  /* SES on points: also compute the weak-duality
                                      lower bound of eq.(ses_qp) from the MWU weights
                                      on the last pass of every launch chunk */
+  SCP_MWU_FLAG_DETERMINISTIC = 8  /* results bitwise reproducible for a given grid:
+                                     the per-workgroup partial sums of a pass are
+                                     combined in a fixed order.  Without it, SES
+                                     with d <= 128 adds them with atomics into one
+                                     sum (faster; the sums then vary in their last
+                                     bits from run to run) */
 };
 
 /*

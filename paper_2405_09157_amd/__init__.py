@@ -17,7 +17,7 @@ from ._lib import (  # noqa: F401  (re-exported C-ABI names)
     EXPORTS, OUTCOME_NAMES, SCP_MWU_BF16, SCP_MWU_E_HIP, SCP_MWU_E_INFEASIBLE, SCP_MWU_E_INVAL,
     SCP_MWU_E_NOMEM, SCP_MWU_E_NUMERIC, SCP_MWU_E_STATE, SCP_MWU_E_UNSUPPORTED, SCP_MWU_F32, SCP_MWU_F64, SCP_MWU_FP8,
     SCP_MWU_OK, SCP_MWU_STOPPED,
-    SCP_MWU_FLAG_CERTIFICATES, SCP_MWU_FLAG_NO_EARLY_STOP, SCP_MWU_FLAG_THEORY,
+    SCP_MWU_FLAG_CERTIFICATES, SCP_MWU_FLAG_DETERMINISTIC, SCP_MWU_FLAG_NO_EARLY_STOP, SCP_MWU_FLAG_THEORY,
     SCP_MWU_PROBLEM_SES, SCP_MWU_PROBLEM_SVM, ScpMwuError, load, scp_mwu_backward,
     scp_mwu_cast_bf16, scp_mwu_desc, scp_mwu_destroy, scp_mwu_get_D, scp_mwu_get_state,
     scp_mwu_get_vector, scp_mwu_init, scp_mwu_result, scp_mwu_set_state, scp_mwu_solve,

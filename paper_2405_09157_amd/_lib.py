@@ -22,6 +22,7 @@ SCP_MWU_E_NUMERIC, SCP_MWU_E_INFEASIBLE, SCP_MWU_E_UNSUPPORTED = -5, -6, -7
 SCP_MWU_OUT_RUNNING, SCP_MWU_OUT_SEPARATED, SCP_MWU_OUT_BEAT = 0, 1, 2
 SCP_MWU_OUT_STABILIZED, SCP_MWU_OUT_T_REACHED, SCP_MWU_OUT_NUMERIC = 3, 4, 5
 SCP_MWU_FLAG_NO_EARLY_STOP, SCP_MWU_FLAG_THEORY, SCP_MWU_FLAG_CERTIFICATES = 1, 2, 4
+SCP_MWU_FLAG_DETERMINISTIC = 8
 
 OUTCOME_NAMES = {0: "running", 1: "separated", 2: "beat_alpha", 3: "stabilized",
                  4: "t_reached", 5: "numeric"}

@@ -172,11 +172,19 @@ hipError_t launch_read_reference(const void *buf, int64_t bytes, int grid, float
 hipError_t launch_quantize_fp8(const float *src, int64_t n, int64_t d, int64_t ld, uint8_t *codes, float *scales,
                                hipStream_t s);
 
+// Slots of a fused pass: state/vector/record slot `cur` is read and 1 - cur
+// written (rec_stride doubles per record slot); with global sums the pass
+// reads g_in, adds into g_out and clears g_zero (all nullptr: records).
+struct FusedSlots {
+  int cur;
+  int64_t rec_stride;
+  double *g_in, *g_out, *g_zero;
+};
+
 #define SCPMWU_DECLARE_TYPED(name)                                                              \
   hipError_t launch_pass_##name(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s); \
-  hipError_t launch_fused_##name(const LaunchCfg &c, const PassArgs &a, int cur, int64_t rec_stride,   \
-                                 hipStream_t s);                                                  \
-  hipError_t launch_flush_##name(bool cert, int grid, const PassArgs &a, hipStream_t s);          \
+  hipError_t launch_fused_##name(const LaunchCfg &c, const PassArgs &a, const FusedSlots &f, hipStream_t s); \
+  hipError_t launch_flush_##name(bool cert, int P, bool gmode, const PassArgs &a, hipStream_t s);  \
   hipError_t launch_epilogue_##name(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s); \
   hipError_t launch_monitor_##name(int grid, const PassArgs &a, const double *center,            \
                                    int64_t exclude, int mode, double *out, hipStream_t s);      \

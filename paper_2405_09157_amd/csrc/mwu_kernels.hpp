@@ -444,8 +444,29 @@ struct PassIn {
   int32_t status;
   double kappa, Gb;
   const double *ybar;
-  double *rec;
+  double *rec;   // records (one per workgroup), or the global sum (gsum)
+  bool gsum;     // add the workgroup's sums into rec with atomics
 };
+
+// Maxima kept in a global sum are combined by an unsigned integer atomic max
+// on an order-preserving key: non-negative doubles with the sign bit set,
+// negative ones complemented, so that the key order is the numeric order;
+// the zero key (never produced by a number) stands for "no value" (-inf).
+__device__ __forceinline__ unsigned long long max_key(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double from_max_key(unsigned long long k) {
+  if (k == 0ull) return -INFINITY;
+  const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+  return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ void gsum_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void gsum_max(double *p, double v) {
+  if (v == -INFINITY) return;  // the identity
+  __hip_atomic_fetch_max(reinterpret_cast<unsigned long long *>(p), max_key(v), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // The pass reads its inputs through a prologue object: pre() runs before the
 // workgroup's first batch of rows is requested, post() once it is in flight
@@ -457,7 +478,8 @@ struct StatePrologue {
   __device__ __forceinline__ void pre() {}
   __device__ __forceinline__ PassIn post() {
     const DevState *st = a.st;
-    return PassIn{st->status, st->kscale * (double)st->t, st->shift_bound, a.vec + kVecMean * a.d, a.partials};
+    return PassIn{st->status, st->kscale * (double)st->t, st->shift_bound, a.vec + kVecMean * a.d, a.partials,
+                  false};
   }
 };
 
@@ -492,12 +514,14 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
   int32_t status0 = kRunning;
   double kappa = 0.0, Gb = 0.0;
   double *rec_base = nullptr;
+  bool to_gsum = false;
   auto start = [&]() {
     const PassIn in = prologue.post();
     status0 = __builtin_amdgcn_readfirstlane(in.status);
     kappa = in.kappa;
     Gb = in.Gb;
     rec_base = in.rec;
+    to_gsum = in.gsum;
     for (int c = tid; c < kG * EPL; c += kPassBlock) s_ctr[c] = c < d ? in.ybar[c] : 0.0;
     // status0 is the same for the whole grid: either every wave returns
     // after this barrier or none does
@@ -521,10 +545,9 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
     voff[q] = c0 < d ? (int32_t)(((int64_t)g * ld + c0) * (int64_t)sizeof(T)) : kOffInvalid;
   }
   const int32_t step_bytes = (int32_t)(kRowsPerStep * ld * (int64_t)sizeof(T));
-  // rows of batch b into registers (rows >= n read as zeros)
-  auto load_batch = [&](Regs &xs, int64_t b) {
-    const int64_t r0 = b * B;
-    const int64_t rows = n - r0 < B ? n - r0 : B;
+  // rows [r0, r0 + rows) (rows <= B) into registers; the batch's other
+  // rows read as zeros without touching memory
+  auto load_rows = [&](Regs &xs, int64_t r0, int64_t rows) {
     const __amdgpu_buffer_rsrc_t rs = rows_rsrc<T>(X, r0, rows, ld, d);
 #pragma unroll
     for (int s = 0; s < SB; ++s)
@@ -534,9 +557,12 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
     xs.gi = radius_load(radii, r0, rows, lane);
     if constexpr (FP8) xs.sc = scale_load(a.scales, r0, rows, lane);
   };
-  // phases 1-3 on the batch b held in xs
-  auto process = [&](Regs &xs, int64_t b) {
+  auto load_batch = [&](Regs &xs, int64_t b) {
     const int64_t r0 = b * B;
+    load_rows(xs, r0, n - r0 < B ? n - r0 : B);
+  };
+  // phases 1-3 on the rows [r0, r0 + rows) held in xs
+  auto process_rows = [&](Regs &xs, int64_t r0, int64_t rows) {
     // re-read the candidate each batch: it stays out of registers in phases 2-3
     asm volatile("" ::: "memory");
     // binary32 storage types: the mean rounded to binary32, used by phases 1 and 3
@@ -581,7 +607,7 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
 #pragma unroll
       for (int c = 0; c < kG; ++c) dsq += s_part[wave][lane][c];
       const int64_t row = r0 + lane;
-      const bool valid = row < n;
+      const bool valid = lane < rows;
       const bool incl = valid && row != v1;
       const double di = sqrt(dsq);
       const double gi = xs.gi;  // 0 past n or without radii
@@ -648,6 +674,10 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
     }
     wave_lds_sync();
   };
+  auto process = [&](Regs &xs, int64_t b) {
+    const int64_t r0 = b * B;
+    process_rows(xs, r0, n - r0 < B ? n - r0 : B);
+  };
   const int64_t b0 = (int64_t)vb * kPassWaves + wave;
   if constexpr (PFM == kPrefetchRegs) {
     // two register batches, unrolled by two so that neither is copied: the
@@ -713,9 +743,16 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
     s_sc[wave][6] = fall;
   }
   __syncthreads();
-  double *rec = rec_base + (int64_t)vb * pw;
+  // the workgroup's record, or its sums added into the global sum
+  double *rec = to_gsum ? rec_base : rec_base + (int64_t)vb * pw;
   const int dp = rec_dp(d);
-  for (int c = tid; c < d; c += kPassBlock) rec[c] = sum_waves(s_vec, c);
+  for (int c = tid; c < d; c += kPassBlock) {
+    const double v = sum_waves(s_vec, c);
+    if (to_gsum)
+      gsum_add(rec + c, v);
+    else
+      rec[c] = v;
+  }
   __syncthreads();
   if (CERT) {
 #pragma unroll
@@ -727,7 +764,13 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
 #pragma unroll
       for (int k = 0; k < EPL; ++k) s_vec[wave][lane_col<VEC>(cl, k)] = cacc[k];
     __syncthreads();
-    for (int c = tid; c < d; c += kPassBlock) rec[dp + 8 + c] = sum_waves(s_vec, c);
+    for (int c = tid; c < d; c += kPassBlock) {
+      const double v = sum_waves(s_vec, c);
+      if (to_gsum)
+        gsum_add(rec + dp + 8 + c, v);
+      else
+        rec[dp + 8 + c] = v;
+    }
   }
   if (tid < 8) {
     double v;
@@ -737,7 +780,12 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
       v = max_waves(s_sc, tid);
     else
       v = -INFINITY;
-    rec[dp + tid] = v;
+    if (!to_gsum)
+      rec[dp + tid] = v;
+    else if (tid < 5)
+      gsum_add(rec + dp + tid, v);
+    else if (tid < 7)
+      gsum_max(rec + dp + tid, v);
   }
 }
 
@@ -1317,13 +1365,23 @@ __device__ __forceinline__ void epilogue_tail(const PassArgs &a, EpiLDS<DMAX> &L
   __syncthreads();
 }
 
+// gmode: rec is one global sum of a fused pass (SES), its maxima as keys.
 template <typename T, int PROB, bool CERT, int NT, int DMAX>
 __device__ __forceinline__ void epilogue_stage(const PassArgs &a, const DevState *st_in, const double *vec_in,
-                                               const double *rec, int P, bool force, EpiLDS<DMAX> &L) {
+                                               const double *rec, int P, bool force, EpiLDS<DMAX> &L,
+                                               bool gmode = false) {
   epilogue_load<T, PROB, CERT, NT, DMAX>(a, st_in, vec_in, L);
   __syncthreads();
   if (L.st.status != kRunning || !(force || L.st.pending)) return;  // uniform: read from LDS
-  combine_records<PROB, CERT, NT, DMAX>(rec, P, (int)a.d, L);
+  if (gmode) {
+    const int dp = rec_dp((int)a.d), ncols = rec_read_cols<PROB, CERT>((int)a.d);
+    for (int c = threadIdx.x; c < ncols; c += NT)
+      L.comb[c] = (c == dp + 5 || c == dp + 6)
+                      ? from_max_key((unsigned long long)__double_as_longlong(rec[c])) : rec[c];
+    __syncthreads();
+  } else {
+    combine_records<PROB, CERT, NT, DMAX>(rec, P, (int)a.d, L);
+  }
   epilogue_tail<T, PROB, CERT, NT, DMAX>(a, L);
 }
 
@@ -1344,15 +1402,15 @@ __device__ __forceinline__ void epilogue_store(EpiLDS<DMAX> &L, int d, int32_t p
 // there (the unfused iteration); otherwise only pending records are applied
 // (the flush after fused passes).
 template <typename T, int PROB, bool CERT, int NT = kCombBlock>
-__device__ __forceinline__ void epilogue_body(const PassArgs &a, int P, bool force = true) {
+__device__ __forceinline__ void epilogue_body(const PassArgs &a, int P, bool force = true, bool gmode = false) {
   __shared__ EpiLDS<kMaxD> L;
-  epilogue_stage<T, PROB, CERT, NT, kMaxD>(a, a.st, a.vec, a.partials, P, force, L);
+  epilogue_stage<T, PROB, CERT, NT, kMaxD>(a, a.st, a.vec, a.partials, P, force, L, gmode);
   epilogue_store<NT, kMaxD>(L, (int)a.d, 0, a.st, a.vec);
 }
 
 template <typename T, int PROB, bool CERT>
-__global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P, int force) {
-  epilogue_body<T, PROB, CERT>(a, P, force != 0);
+__global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P, int force, int gmode) {
+  epilogue_body<T, PROB, CERT>(a, P, force != 0, gmode != 0);
 }
 
 // ============================================== fused epilogue + SES pass
@@ -1375,13 +1433,19 @@ __global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P,
 constexpr int kFuseMaxD = 128;
 constexpr int kRecInFlight = 32;
 
+// With global sums (g_in != nullptr) the previous pass left one sum in g_in
+// instead of P records: each thread loads one of its columns, the pass adds
+// into g_out, and workgroup 0 clears g_zero (the slot the pass after next
+// adds into, last read by the previous pass) -- three slots in rotation.
 template <typename T, int NT, int DMAX>
 struct FusedPrologue {
   const PassArgs &a;
   int cur, P;
   int64_t rec_stride;
+  double *g_in, *g_out, *g_zero;
   EpiLDS<DMAX> &L;
   double2 rv[kRecInFlight];
+  double gv;           // gmode: a column of the global sum
   double sv, vv, v1v;  // a state word, a vector element, an element of row v1
 
   static_assert(NT >= kNumVec * DMAX && NT >= kStateWords, "one thread per vector element and state word");
@@ -1392,11 +1456,12 @@ struct FusedPrologue {
     const int d = (int)a.d, tid = threadIdx.x;
     const int pw = rec_width(d), np = npairs(), groups = comb_groups(np);
     const double *rec = a.partials + cur * rec_stride;
+    if (g_in != nullptr) gv = tid < 2 * np ? g_in[tid] : 0.0;
     // state, vectors and row v1 into registers (written to LDS in post())
     sv = tid < kStateWords ? reinterpret_cast<const double *>(a.st + cur)[tid] : 0.0;
     vv = tid < kNumVec * d ? a.vec[cur * (int64_t)kNumVec * d + tid] : 0.0;
     v1v = tid < d ? row_value<T>(a, a.v1, tid) : 0.0;
-    if (tid < np * groups) {
+    if (g_in == nullptr && tid < np * groups) {
       const int c0 = 2 * (tid % np), g0 = tid / np;
 #pragma unroll
       for (int r = 0; r < kRecInFlight; ++r) {
@@ -1416,8 +1481,14 @@ struct FusedPrologue {
     if (tid < kStateWords) reinterpret_cast<double *>(&L.st)[tid] = sv;
     if (tid < kNumVec * d) L.vout[tid] = vv;
     if (tid < d) L.v1[tid] = v1v;
+    if (g_in != nullptr && tid < ncols)
+      L.comb[tid] = (tid == dp + 5 || tid == dp + 6) ? from_max_key((unsigned long long)__double_as_longlong(gv)) : gv;
+    if (blockIdx.x == 0 && g_zero != nullptr)
+      for (int c = tid; c < pw; c += NT) g_zero[c] = 0.0;
     __syncthreads();
-    if (L.st.status == kRunning && L.st.pending) {  // uniform: read from LDS
+    if (L.st.status == kRunning && L.st.pending && g_in != nullptr) {
+      epilogue_tail<T, kSES, false, NT, DMAX>(a, L);
+    } else if (L.st.status == kRunning && L.st.pending) {  // uniform: read from LDS
       for (int jp = tid; jp < items; jp += NT) {
         const int j = jp % np, grp = jp / np;
         const int c = 2 * j;
@@ -1454,17 +1525,20 @@ struct FusedPrologue {
     }
     if (blockIdx.x == 0)
       epilogue_store<NT, DMAX>(L, d, L.st.status == kRunning ? 1 : 0, a.st + (1 - cur), a.vec + (1 - cur) * vs);
+    if (g_in != nullptr)
+      return PassIn{L.st.status, L.st.kscale * (double)L.st.t, L.st.shift_bound, L.vout + kVecMean * d, g_out, true};
     return PassIn{L.st.status, L.st.kscale * (double)L.st.t, L.st.shift_bound, L.vout + kVecMean * d,
-                  a.partials + (1 - cur) * rec_stride};
+                  a.partials + (1 - cur) * rec_stride, false};
   }
 };
 
 template <typename T, int EPL, int VEC, bool CERT, int PFM>
 __global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
-void ses_fused_kernel(PassArgs a, int cur, int P, int64_t rec_stride) {
+void ses_fused_kernel(PassArgs a, int cur, int P, int64_t rec_stride, double *g_in, double *g_out,
+                      double *g_zero) {
   static_assert(kG * EPL <= kFuseMaxD, "fused pass: d <= 128");
   __shared__ EpiLDS<kFuseMaxD> L;
-  FusedPrologue<T, kPassBlock, kFuseMaxD> pro{a, cur, P, rec_stride, L};
+  FusedPrologue<T, kPassBlock, kFuseMaxD> pro{a, cur, P, rec_stride, g_in, g_out, g_zero, L};
   ses_pass_body<T, EPL, VEC, CERT, PFM>(a, (int)blockIdx.x, (int)gridDim.x, pro);
 }
 
@@ -1612,30 +1686,30 @@ hipError_t launch_epilogue_p(int grid, const PassArgs &a, hipStream_t s) {
     e.partials = l1;
     P = rec_groups(grid);
   }
-  hipLaunchKernelGGL((epilogue_kernel<T, PROB, CERT>), dim3(1), dim3(kCombBlock), 0, s, e, P, 1);
+  hipLaunchKernelGGL((epilogue_kernel<T, PROB, CERT>), dim3(1), dim3(kCombBlock), 0, s, e, P, 1, 0);
   return hipGetLastError();
 }
 
-// The flush after fused passes: the pending records of slot `cur` (if any)
-// applied in place.
+// The flush after fused passes: the pending records (or global sum, gmode)
+// in a.partials applied in place on a.st / a.vec.
 template <typename T>
-hipError_t launch_flush_typed(bool cert, int grid, const PassArgs &a, hipStream_t s) {
+hipError_t launch_flush_typed(bool cert, int P, bool gmode, const PassArgs &a, hipStream_t s) {
   if (cert)
-    hipLaunchKernelGGL((epilogue_kernel<T, kSES, true>), dim3(1), dim3(kCombBlock), 0, s, a, grid, 0);
+    hipLaunchKernelGGL((epilogue_kernel<T, kSES, true>), dim3(1), dim3(kCombBlock), 0, s, a, P, 0, gmode ? 1 : 0);
   else
-    hipLaunchKernelGGL((epilogue_kernel<T, kSES, false>), dim3(1), dim3(kCombBlock), 0, s, a, grid, 0);
+    hipLaunchKernelGGL((epilogue_kernel<T, kSES, false>), dim3(1), dim3(kCombBlock), 0, s, a, P, 0, gmode ? 1 : 0);
   return hipGetLastError();
 }
 
 template <typename T, int EPL, int VEC, int PFM>
-hipError_t launch_fused_p(bool cert, int grid, const PassArgs &a, int cur, int64_t rec_stride, hipStream_t s) {
+hipError_t launch_fused_p(bool cert, int grid, const PassArgs &a, const FusedSlots &f, hipStream_t s) {
   if constexpr (kG * EPL <= kFuseMaxD) {
     if (cert)
-      hipLaunchKernelGGL((ses_fused_kernel<T, EPL, VEC, true, PFM>), dim3(grid), dim3(kPassBlock), 0, s, a, cur, grid,
-                         rec_stride);
+      hipLaunchKernelGGL((ses_fused_kernel<T, EPL, VEC, true, PFM>), dim3(grid), dim3(kPassBlock), 0, s, a, f.cur, grid,
+                         f.rec_stride, f.g_in, f.g_out, f.g_zero);
     else
-      hipLaunchKernelGGL((ses_fused_kernel<T, EPL, VEC, false, PFM>), dim3(grid), dim3(kPassBlock), 0, s, a, cur,
-                         grid, rec_stride);
+      hipLaunchKernelGGL((ses_fused_kernel<T, EPL, VEC, false, PFM>), dim3(grid), dim3(kPassBlock), 0, s, a, f.cur,
+                         grid, f.rec_stride, f.g_in, f.g_out, f.g_zero);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -1643,31 +1717,31 @@ hipError_t launch_fused_p(bool cert, int grid, const PassArgs &a, int cur, int64
 }
 
 template <typename T, int EPL, int VEC>
-hipError_t launch_fused_t(const LaunchCfg &c, const PassArgs &a, int cur, int64_t rec_stride, hipStream_t s) {
-  return c.pfm == kPrefetchRegs ? launch_fused_p<T, EPL, VEC, kPrefetchRegs>(c.cert, c.grid, a, cur, rec_stride, s)
-                                : launch_fused_p<T, EPL, VEC, kPrefetchNone>(c.cert, c.grid, a, cur, rec_stride, s);
+hipError_t launch_fused_t(const LaunchCfg &c, const PassArgs &a, const FusedSlots &f, hipStream_t s) {
+  return c.pfm == kPrefetchRegs ? launch_fused_p<T, EPL, VEC, kPrefetchRegs>(c.cert, c.grid, a, f, s)
+                                : launch_fused_p<T, EPL, VEC, kPrefetchNone>(c.cert, c.grid, a, f, s);
 }
 
 template <typename T, int EPL>
-hipError_t launch_fused_v(const LaunchCfg &c, const PassArgs &a, int cur, int64_t rec_stride, hipStream_t s) {
+hipError_t launch_fused_v(const LaunchCfg &c, const PassArgs &a, const FusedSlots &f, hipStream_t s) {
   constexpr int VF = (16 / (int)sizeof(T)) < EPL ? (16 / (int)sizeof(T)) : EPL;
-  if (c.vec == VF) return launch_fused_t<T, EPL, VF>(c, a, cur, rec_stride, s);
+  if (c.vec == VF) return launch_fused_t<T, EPL, VF>(c, a, f, s);
   if constexpr (VF >= 4) {
-    if (c.vec == VF / 2) return launch_fused_t<T, EPL, VF / 2>(c, a, cur, rec_stride, s);
+    if (c.vec == VF / 2) return launch_fused_t<T, EPL, VF / 2>(c, a, f, s);
   }
   if constexpr (VF > 1) {
-    if (c.vec == 1) return launch_fused_t<T, EPL, 1>(c, a, cur, rec_stride, s);
+    if (c.vec == 1) return launch_fused_t<T, EPL, 1>(c, a, f, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_fused_typed(const LaunchCfg &c, const PassArgs &a, int cur, int64_t rec_stride, hipStream_t s) {
+hipError_t launch_fused_typed(const LaunchCfg &c, const PassArgs &a, const FusedSlots &f, hipStream_t s) {
   switch (c.epl) {
-    case 1: return launch_fused_v<T, 1>(c, a, cur, rec_stride, s);
-    case 2: return launch_fused_v<T, 2>(c, a, cur, rec_stride, s);
-    case 4: return launch_fused_v<T, 4>(c, a, cur, rec_stride, s);
-    case 8: return launch_fused_v<T, 8>(c, a, cur, rec_stride, s);
+    case 1: return launch_fused_v<T, 1>(c, a, f, s);
+    case 2: return launch_fused_v<T, 2>(c, a, f, s);
+    case 4: return launch_fused_v<T, 4>(c, a, f, s);
+    case 8: return launch_fused_v<T, 8>(c, a, f, s);
     default: return hipErrorInvalidValue;
   }
 }

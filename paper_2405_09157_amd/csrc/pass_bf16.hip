@@ -6,11 +6,11 @@ namespace scpmwu {
 hipError_t launch_pass_bf16(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
   return launch_pass_typed<uint16_t>(problem, c, a, s);
 }
-hipError_t launch_fused_bf16(const LaunchCfg &c, const PassArgs &a, int cur, int64_t rec_stride, hipStream_t s) {
-  return launch_fused_typed<uint16_t>(c, a, cur, rec_stride, s);
+hipError_t launch_fused_bf16(const LaunchCfg &c, const PassArgs &a, const FusedSlots &f, hipStream_t s) {
+  return launch_fused_typed<uint16_t>(c, a, f, s);
 }
-hipError_t launch_flush_bf16(bool cert, int grid, const PassArgs &a, hipStream_t s) {
-  return launch_flush_typed<uint16_t>(cert, grid, a, s);
+hipError_t launch_flush_bf16(bool cert, int P, bool gmode, const PassArgs &a, hipStream_t s) {
+  return launch_flush_typed<uint16_t>(cert, P, gmode, a, s);
 }
 hipError_t launch_epilogue_bf16(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
   return launch_epilogue_typed<uint16_t>(problem, c.cert, c.grid, a, s);

@@ -6,11 +6,11 @@ namespace scpmwu {
 hipError_t launch_pass_f32(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
   return launch_pass_typed<float>(problem, c, a, s);
 }
-hipError_t launch_fused_f32(const LaunchCfg &c, const PassArgs &a, int cur, int64_t rec_stride, hipStream_t s) {
-  return launch_fused_typed<float>(c, a, cur, rec_stride, s);
+hipError_t launch_fused_f32(const LaunchCfg &c, const PassArgs &a, const FusedSlots &f, hipStream_t s) {
+  return launch_fused_typed<float>(c, a, f, s);
 }
-hipError_t launch_flush_f32(bool cert, int grid, const PassArgs &a, hipStream_t s) {
-  return launch_flush_typed<float>(cert, grid, a, s);
+hipError_t launch_flush_f32(bool cert, int P, bool gmode, const PassArgs &a, hipStream_t s) {
+  return launch_flush_typed<float>(cert, P, gmode, a, s);
 }
 hipError_t launch_epilogue_f32(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
   return launch_epilogue_typed<float>(problem, c.cert, c.grid, a, s);

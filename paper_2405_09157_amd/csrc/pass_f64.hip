@@ -6,11 +6,11 @@ namespace scpmwu {
 hipError_t launch_pass_f64(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
   return launch_pass_typed<double>(problem, c, a, s);
 }
-hipError_t launch_fused_f64(const LaunchCfg &c, const PassArgs &a, int cur, int64_t rec_stride, hipStream_t s) {
-  return launch_fused_typed<double>(c, a, cur, rec_stride, s);
+hipError_t launch_fused_f64(const LaunchCfg &c, const PassArgs &a, const FusedSlots &f, hipStream_t s) {
+  return launch_fused_typed<double>(c, a, f, s);
 }
-hipError_t launch_flush_f64(bool cert, int grid, const PassArgs &a, hipStream_t s) {
-  return launch_flush_typed<double>(cert, grid, a, s);
+hipError_t launch_flush_f64(bool cert, int P, bool gmode, const PassArgs &a, hipStream_t s) {
+  return launch_flush_typed<double>(cert, P, gmode, a, s);
 }
 hipError_t launch_epilogue_f64(int problem, const LaunchCfg &c, const PassArgs &a, hipStream_t s) {
   return launch_epilogue_typed<double>(problem, c.cert, c.grid, a, s);

@@ -57,6 +57,12 @@ struct scp_mwu_ctx {
   int64_t rec_stride = 0;  // doubles per record slot
   int cur = 0;
   bool fused = false;      // SES with small records: epilogue fused into the next pass
+  // fused passes without SCP_MWU_FLAG_DETERMINISTIC add their sums into one
+  // of three global sums (atomics) instead of writing per-workgroup records
+  bool gmode = false;
+  double *g_base = nullptr;
+  int64_t g_stride = 0;    // doubles per global-sum slot
+  int g_cur = 0;           // the slot holding the last pass's sums
   DevState *host_st = nullptr;  // pinned readback
   int grid = 0;
   LaunchCfg cfg{}, cfg_cert{};
@@ -67,8 +73,8 @@ struct scp_mwu_ctx {
   int64_t T = 0;
   // graphs: `chunk` passes, the last one optionally with certificates (and
   // the flush), one per starting slot; gend: the slot a graph ends in
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  int gend[2] = {0, 0};
+  hipGraphExec_t gexec[2][3] = {};
+  int gend[2][3] = {}, gend_g[2][3] = {};
   std::string err;
 
   int fail(int code, const std::string &msg) {
@@ -119,16 +125,27 @@ hipError_t epilogue_kernel(scp_mwu_ctx *c, bool cert, hipStream_t s) {
 
 // The fused kernel: the epilogue of the pending records of slot cur, then
 // the pass, whose records and new state go to the other slot.
+double *gslot(const scp_mwu_ctx *c, int k) { return c->g_base + (int64_t)(k % 3) * c->g_stride; }
+
 hipError_t fused_kernel(scp_mwu_ctx *c, bool cert, hipStream_t s) {
   const LaunchCfg &cfg = cert ? c->cfg_cert : c->cfg;
+  FusedSlots f{c->cur, c->rec_stride, nullptr, nullptr, nullptr};
+  if (c->gmode) {
+    f.g_in = gslot(c, c->g_cur);
+    f.g_out = gslot(c, c->g_cur + 1);
+    f.g_zero = gslot(c, c->g_cur + 2);
+  }
   hipError_t e;
   switch (c->dtype) {
-    case kF32: e = launch_fused_f32(cfg, c->base, c->cur, c->rec_stride, s); break;
-    case kBF16: e = launch_fused_bf16(cfg, c->base, c->cur, c->rec_stride, s); break;
-    case kFP8: e = launch_fused_fp8(cfg, c->base, c->cur, c->rec_stride, s); break;
-    default: e = launch_fused_f64(cfg, c->base, c->cur, c->rec_stride, s); break;
+    case kF32: e = launch_fused_f32(cfg, c->base, f, s); break;
+    case kBF16: e = launch_fused_bf16(cfg, c->base, f, s); break;
+    case kFP8: e = launch_fused_fp8(cfg, c->base, f, s); break;
+    default: e = launch_fused_f64(cfg, c->base, f, s); break;
   }
-  if (e == hipSuccess) set_cur(c, 1 - c->cur);
+  if (e == hipSuccess) {
+    set_cur(c, 1 - c->cur);
+    if (c->gmode) c->g_cur = (c->g_cur + 1) % 3;
+  }
   return e;
 }
 
@@ -136,11 +153,17 @@ hipError_t fused_kernel(scp_mwu_ctx *c, bool cert, hipStream_t s) {
 // of a certificate pass need cert).
 hipError_t flush(scp_mwu_ctx *c, bool cert, hipStream_t s) {
   if (!c->fused) return hipSuccess;
+  PassArgs a = c->args;
+  int P = c->grid;
+  if (c->gmode) {
+    a.partials = gslot(c, c->g_cur);
+    P = 1;
+  }
   switch (c->dtype) {
-    case kF32: return launch_flush_f32(cert, c->grid, c->args, s);
-    case kBF16: return launch_flush_bf16(cert, c->grid, c->args, s);
-    case kFP8: return launch_flush_fp8(cert, c->grid, c->args, s);
-    default: return launch_flush_f64(cert, c->grid, c->args, s);
+    case kF32: return launch_flush_f32(cert, P, c->gmode, a, s);
+    case kBF16: return launch_flush_bf16(cert, P, c->gmode, a, s);
+    case kFP8: return launch_flush_fp8(cert, P, c->gmode, a, s);
+    default: return launch_flush_f64(cert, P, c->gmode, a, s);
   }
 }
 
@@ -196,6 +219,11 @@ int start_test(scp_mwu_ctx *c, double alpha, int64_t T, bool early) {
   p.patience = c->patience;
   p.early = early ? 1 : 0;
   set_cur(c, 0);
+  if (c->gmode) {  // every global sum starts cleared (not in a captured graph)
+    int rc = c->hip(hipMemsetAsync(c->g_base, 0, sizeof(double) * 3 * (size_t)c->g_stride, c->stream), "sum clear");
+    if (rc) return rc;
+    c->g_cur = 0;
+  }
   hipError_t e;
   switch (c->dtype) {
     case kF32: e = launch_init_f32(c->args, p, c->problem, c->stream); break;
@@ -216,8 +244,8 @@ int start_test(scp_mwu_ctx *c, double alpha, int64_t T, bool early) {
 // of the last pass's records); capture launches nothing, so the slot is
 // restored afterwards and the graph's end slot kept.
 int build_graph(scp_mwu_ctx *c) {
-  const int p0 = c->cur;
-  if (c->gexec[p0]) return SCP_MWU_OK;
+  const int p0 = c->cur, g0 = c->g_cur;
+  if (c->gexec[p0][g0]) return SCP_MWU_OK;
   hipGraph_t g = nullptr;
   int rc = c->hip(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
   if (rc) return rc;
@@ -226,13 +254,15 @@ int build_graph(scp_mwu_ctx *c) {
   for (int k = 0; k < c->chunk && e == hipSuccess; ++k)
     e = pass(c, cert && k == c->chunk - 1, c->cap_stream);
   if (e == hipSuccess) e = flush(c, cert, c->cap_stream);
-  c->gend[p0] = c->cur;
+  c->gend[p0][g0] = c->cur;
+  c->gend_g[p0][g0] = c->g_cur;
   set_cur(c, p0);
+  c->g_cur = g0;
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess) return c->hip(e, "capture pass");
   rc = c->hip(e2, "end capture");
   if (rc) return rc;
-  e = hipGraphInstantiate(&c->gexec[p0], g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&c->gexec[p0][g0], g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   return c->hip(e, "graph instantiate");
 }
@@ -249,9 +279,11 @@ int run_iters(scp_mwu_ctx *c, int64_t k) {
     if (k >= c->chunk && c->chunk > 1) {
       rc = build_graph(c);
       if (rc) return rc;
-      rc = c->hip(hipGraphLaunch(c->gexec[c->cur], c->stream), "graph launch");
+      rc = c->hip(hipGraphLaunch(c->gexec[c->cur][c->g_cur], c->stream), "graph launch");
       if (rc) return rc;
-      set_cur(c, c->gend[c->cur]);
+      const int p1 = c->gend[c->cur][c->g_cur], g1 = c->gend_g[c->cur][c->g_cur];
+      set_cur(c, p1);
+      c->g_cur = g1;
       k -= c->chunk;
     } else {
       for (; k > 0; --k) {
@@ -347,12 +379,14 @@ const char *scp_mwu_last_error(const scp_mwu_ctx *ctx) {
 void scp_mwu_destroy(scp_mwu_ctx *c) {
   if (!c) return;
   hipStreamSynchronize(c->stream);
-  for (auto &g : c->gexec)
-    if (g) hipGraphExecDestroy(g);
+  for (auto &row : c->gexec)
+    for (auto &g : row)
+      if (g) hipGraphExecDestroy(g);
   if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   hipFree(c->st_base);
   hipFree(c->vec_base);
   hipFree(c->part_base);
+  hipFree(c->g_base);
   hipFree(c->mon);
   hipFree(c->owned);
   hipFree(c->owned_scales);
@@ -480,9 +514,12 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   if (const char *fe = getenv("SCPMWU_FUSED"))
     if (fe[0] == '0') c->fused = false;
   c->rec_stride = (int64_t)(grid + rec_groups(grid)) * pw;
+  c->gmode = c->fused && !(c->flags & SCP_MWU_FLAG_DETERMINISTIC);
+  c->g_stride = (pw + 31) / 32 * 32;
   if (hipMalloc(&c->st_base, 2 * sizeof(DevState)) != hipSuccess ||
       hipMalloc(&c->vec_base, 2 * sizeof(double) * kNumVec * c->d) != hipSuccess ||
       hipMalloc(&c->part_base, 2 * sizeof(double) * (size_t)c->rec_stride) != hipSuccess ||
+      hipMalloc(&c->g_base, 3 * sizeof(double) * (size_t)c->g_stride) != hipSuccess ||
       hipMalloc(&c->mon, sizeof(double) * (size_t)grid * 4) != hipSuccess ||
       hipHostMalloc((void **)&c->host_st, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
     return fail(SCP_MWU_E_NOMEM, "workspace allocation");

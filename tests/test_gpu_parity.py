@@ -68,7 +68,9 @@ def ses_compare_steps(V_dev, V64, alpha, T, K, flags_noearly=True, radii=None, v
     if radii is not None:
         import torch
         g = torch.from_numpy(radii).cuda()
-    m = mwu(V_dev, "ses", radii=g, v1=v1, flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP if flags_noearly else 0, **kw)
+    if "flags" not in kw:
+        kw["flags"] = scp.SCP_MWU_FLAG_NO_EARLY_STOP if flags_noearly else 0
+    m = mwu(V_dev, "ses", radii=g, v1=v1, **kw)
     assert abs(m.D - P.D) <= 1e-12 * P.D
     S = np.zeros(V64.shape[1])
     worst = dict(u=0.0, ubar=0.0, value=0.0, logC=0.0, f=0.0)
@@ -94,9 +96,10 @@ def ses_compare_steps(V_dev, V64, alpha, T, K, flags_noearly=True, radii=None, v
     return worst
 
 
-@pytest.mark.parametrize("n,d,grid,storage", [(50000, 64, 16, None), (40000, 100, 12, None), (30001, 100, 8, "bf16"),
-                                              (25000, 33, 8, None), (70000, 16, 24, "fp8")])
-def test_ses_step_parity_small_grids(n, d, grid, storage):
+@pytest.mark.parametrize("n,d,grid,storage,det", [(50000, 64, 16, None, False), (40000, 100, 12, None, False),
+                                                  (40000, 100, 12, None, True), (30001, 100, 8, "bf16", False),
+                                                  (25000, 33, 8, None, True), (70000, 16, 24, "fp8", False)])
+def test_ses_step_parity_small_grids(n, d, grid, storage, det):
     """Small grids (many rounds of batches per wave) through the fused pass:
     step outputs match the oracle at the summation-order bar (BF16 and FP8 at
     their step bar, on the stored values)."""
@@ -111,8 +114,11 @@ def test_ses_step_parity_small_grids(n, d, grid, storage):
         tol = BF16_STEP
     else:
         V64, tol = V.astype(np.float64), TIGHT
+    import paper_2405_09157_amd as scp
     P = oses.setup(V64)
-    ses_compare_steps(dev(V, torch.float32), V64, 0.8 * P.D, 2000, 25, tol=tol, grid=grid, storage=storage)
+    flags = scp.SCP_MWU_FLAG_NO_EARLY_STOP | (scp.SCP_MWU_FLAG_DETERMINISTIC if det else 0)
+    ses_compare_steps(dev(V, torch.float32), V64, 0.8 * P.D, 2000, 25, tol=tol, grid=grid, storage=storage,
+                      flags=flags)
 
 
 @pytest.mark.parametrize("n,d", [(3000, 100), (1001, 3), (517, 64), (2000, 256), (300, 7), (64, 1), (2, 5)])
@@ -209,13 +215,16 @@ def test_ses_fixed_schedule_and_determinism():
     r = oses.ftp(P, alpha, T, eta, early_stop=False)
     Vd = dev(V, torch.float32)
     outs = []
-    for rep in range(2):
-        m = mwu(Vd, "ses", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP, chunk=32)
+    # DETERMINISTIC: per-workgroup records combined in a fixed order; without
+    # it the fused pass adds into a global sum with atomics (order varies)
+    for flags in (scp.SCP_MWU_FLAG_DETERMINISTIC, scp.SCP_MWU_FLAG_DETERMINISTIC, 0):
+        m = mwu(Vd, "ses", flags=scp.SCP_MWU_FLAG_NO_EARLY_STOP | flags, chunk=32)
         info = m.step(alpha, T, T + 1)
         outs.append((np.array(m.vector(0)), info))
         m.close()
-    (ub0, i0), (ub1, i1) = outs
+    (ub0, i0), (ub1, i1), (ub2, i2) = outs
     assert np.array_equal(ub0, ub1) and i0["f_best"] == i1["f_best"]       # bitwise reproducible
+    assert np.linalg.norm(ub2 - ub0) / alpha <= TIGHT and abs(i2["f_best"] - i0["f_best"]) <= TIGHT * i0["f_best"]
     assert r.outcome == oses.T_REACHED and i0["outcome_name"] == "t_reached" and i0["t_end"] == T
     assert np.linalg.norm(ub0 - r.S / T) / alpha <= TIGHT
     assert abs(i0["f_best"] - r.f_best) / r.f_best <= TIGHT
