@@ -156,7 +156,19 @@ class FtpResult:
     t_best: int
     f_traj: List[float] = field(default_factory=list)
     values: List[float] = field(default_factory=list)
+    scales: List[float] = field(default_factory=list)
     logC: List[float] = field(default_factory=list)
+    # closest approach of the test's decisions to their thresholds, relative:
+    # the separation test (value against -tau * scale, in units of scale), the
+    # f < alpha exit (in units of alpha) and the stabilisation ratio (in units
+    # of delta), over every iteration the test ran; a rounding-level change
+    # can flip a decision only where its margin is that small
+    tie_margin: float = math.inf
+    # largest cancellation ratio sum_i ||w_i|| / ||sum_i w_i|| of the ORACLE's
+    # weighted sum over the test's iterations: the factor by which a relative
+    # change of the weights moves the direction of W, hence u (a trajectory
+    # through a near-zero W is sensitive to rounding from there on)
+    cancel_max: float = 1.0
 
 
 def step(P: SesSetup, S: np.ndarray, t_prev: int, alpha: float, eta: float,
@@ -191,10 +203,16 @@ def ftp(P: SesSetup, alpha: float, T: int, eta: float, delta: float = 1e-4,
     for t in range(1, T + 1):
         ubar_prev = S / (t - 1) if t > 1 else None
         W, s, logC = hyperplane(P, ubar_prev, alpha, t - 1, eta)
-        u, value, scale, _, _ = oracle(P, W, s, alpha, tau)
+        u, value, scale, Wsum, _ = oracle(P, W, s, alpha, tau)
+        nWs = float(np.linalg.norm(Wsum))
+        if t > 1:
+            res.cancel_max = max(res.cancel_max, float(np.sum(np.linalg.norm(W, axis=1))) / nWs if nWs > 0.0 else math.inf)
         if record:
             res.values.append(value)
+            res.scales.append(scale)
             res.logC.append(logC)
+        if scale > 0.0:
+            res.tie_margin = min(res.tie_margin, abs(value + tau * scale) / scale)
         if value < -tau * scale:
             res.outcome, res.t = SEPARATED, t
             break
@@ -208,10 +226,13 @@ def ftp(P: SesSetup, alpha: float, T: int, eta: float, delta: float = 1e-4,
             res.f_best, res.ubar_best, res.t_best = f, ubar.copy(), t
         if not early_stop:
             continue
+        res.tie_margin = min(res.tie_margin, abs(f - alpha) / alpha)
         if f < alpha:
             res.outcome, res.t = BEAT, t
             break
         if f_prev is not None:
+            if f_prev > 0.0:
+                res.tie_margin = min(res.tie_margin, abs(abs(f - f_prev) / f_prev - delta) / delta)
             if f_prev > 0.0 and abs(f - f_prev) / f_prev < delta:
                 cnt += 1
             else:
@@ -235,6 +256,8 @@ class SolveResult:
     steps: list
     converged: bool
     passes: int = 0             # k-way search: sum over rounds of the longest test
+    tie_margin: float = math.inf  # least FtpResult.tie_margin over the search's tests
+    cancel_max: float = 1.0       # largest FtpResult.cancel_max over the search's tests
 
 
 def solve(V, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Optional[int] = None,
@@ -256,6 +279,8 @@ def solve(V, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Optional[int] = 
     iters = 0
     steps = []
     converged = False
+    tie_margin = math.inf
+    cancel_max = 1.0
     for _ in range(max_steps):
         if U - L <= eps * L:
             converged = True
@@ -268,6 +293,8 @@ def solve(V, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Optional[int] = 
         T = max(T, min_T(P))
         eta = math.sqrt(math.log(P.r) / T)
         r = ftp(P, alpha, T, eta, delta, patience, tau, early_stop=not theory)
+        tie_margin = min(tie_margin, r.tie_margin)
+        cancel_max = max(cancel_max, r.cancel_max)
         iters += r.t
         steps.append((alpha, T, r.outcome, r.t, r.f_best))
         if r.f_best < Uc:
@@ -283,7 +310,8 @@ def solve(V, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Optional[int] = 
     else:
         converged = U - L <= eps * L
     return SolveResult(radius=Uc, center=center, lower=Lc, upper=Uc, L=L, U=U,
-                       iters=iters, steps=steps, converged=converged)
+                       iters=iters, steps=steps, converged=converged, tie_margin=tie_margin,
+                       cancel_max=cancel_max)
 
 
 def solve_kway(V, k: int, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Optional[int] = None,
@@ -311,6 +339,8 @@ def solve_kway(V, k: int, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Opt
     iters = passes = 0
     steps = []
     converged = False
+    tie_margin = math.inf
+    cancel_max = 1.0
     g = 2 * k + 1
     for _ in range(max_rounds):
         if U - L <= eps * L:
@@ -326,6 +356,8 @@ def solve_kway(V, k: int, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Opt
             T = max(T, min_T(P))
             eta = math.sqrt(math.log(P.r) / T)
             r = ftp(P, alpha, T, eta, delta, patience, tau, early_stop=not theory)
+            tie_margin = min(tie_margin, r.tie_margin)
+            cancel_max = max(cancel_max, r.cancel_max)
             round_.append((alpha, L + 2 * i * (U - L) / g, T, r))
             steps.append((alpha, T, r.outcome, r.t, r.f_best))
         iters += sum(r.t for _, _, _, r in round_)
@@ -343,4 +375,5 @@ def solve_kway(V, k: int, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Opt
     else:
         converged = U - L <= eps * L
     return SolveResult(radius=Uc, center=center, lower=Lc, upper=Uc, L=L, U=U, iters=iters,
-                       steps=steps, converged=converged, passes=passes)
+                       steps=steps, converged=converged, passes=passes, tie_margin=tie_margin,
+                       cancel_max=cancel_max)

@@ -148,6 +148,10 @@ class FtpResult:
     f_traj: List[float] = field(default_factory=list)
     values: List[float] = field(default_factory=list)
     logC: List[float] = field(default_factory=list)
+    # closest approach of the test's decisions to their thresholds, relative
+    # (as in the SES oracle): separation in units of scale, f above alpha in
+    # units of alpha, the stabilisation ratio in units of delta
+    tie_margin: float = math.inf
 
 
 def step(Pb: SvmSetup, Sw: np.ndarray, S1: float, S2: float, t_prev: int,
@@ -181,6 +185,8 @@ def ftp(Pb: SvmSetup, alpha: float, T: int, eta: float, delta: float = 1e-4,
         if record:
             res.values.append(value)
             res.logC.append(logC)
+        if scale > 0.0:
+            res.tie_margin = min(res.tie_margin, abs(value + tau * scale) / scale)
         if value < -tau * scale:
             res.outcome, res.t = SEPARATED, t
             break
@@ -194,10 +200,13 @@ def ftp(Pb: SvmSetup, alpha: float, T: int, eta: float, delta: float = 1e-4,
             res.f_best, res.wbar_best, res.t_best = f, wbar.copy(), t
         if not early_stop:
             continue
+        res.tie_margin = min(res.tie_margin, abs(f - alpha) / alpha)
         if f > alpha:
             res.outcome, res.t = BEAT, t
             break
         if f_prev is not None:
+            if f_prev > 0.0:
+                res.tie_margin = min(res.tie_margin, abs(abs(f - f_prev) / f_prev - delta) / delta)
             if f_prev > 0.0 and abs(f - f_prev) / f_prev < delta:
                 cnt += 1
             else:
@@ -220,6 +229,7 @@ class SolveResult:
     iters: int
     steps: list
     converged: bool
+    tie_margin: float = math.inf  # least FtpResult.tie_margin over the search's tests
 
 
 def solve(X, n_pos: int, eps: float = 1e-3, t_cap: Optional[int] = None,
@@ -239,6 +249,7 @@ def solve(X, n_pos: int, eps: float = 1e-3, t_cap: Optional[int] = None,
     iters = 0
     steps = []
     converged = False
+    tie_margin = math.inf
     for _ in range(max_steps):
         if U - L <= eps * U:
             converged = True
@@ -251,6 +262,7 @@ def solve(X, n_pos: int, eps: float = 1e-3, t_cap: Optional[int] = None,
         T = max(T, min_T(Pb))
         eta = math.sqrt(math.log(Pb.r) / T)
         r = ftp(Pb, alpha, T, eta, delta, patience, tau, early_stop=not theory)
+        tie_margin = min(tie_margin, r.tie_margin)
         iters += r.t
         steps.append((alpha, T, r.outcome, r.t, r.f_best))
         Uc = min(Uc, r.ub_best)
@@ -267,4 +279,4 @@ def solve(X, n_pos: int, eps: float = 1e-3, t_cap: Optional[int] = None,
     else:
         converged = U - L <= eps * U
     return SolveResult(margin=Lc, w=w_best, lower=Lc, upper=Uc, L=L, U=U,
-                       iters=iters, steps=steps, converged=converged)
+                       iters=iters, steps=steps, converged=converged, tie_margin=tie_margin)

@@ -233,9 +233,13 @@ def test_ses_fixed_schedule_and_determinism():
 @pytest.mark.parametrize("seed", [1, 2])
 def test_ses_end_to_end_small_config(seed):
     import torch
+    import paper_2405_09157_amd as scp
     V = synth.ses_uniform(2000, 3, seed)
     ref = oses.solve(V, eps=1e-3)
-    m = mwu(dev(V, torch.float64), "ses", eps=1e-3)
+    # the fixed-order record combine: the search path of this configuration
+    # passes near-zero W (oracle cancel_max ~1e6-1e7), where only a
+    # reproducible summation order keeps the comparison repeatable
+    m = mwu(dev(V, torch.float64), "ses", eps=1e-3, flags=scp.SCP_MWU_FLAG_DETERMINISTIC)
     out = m.solve()
     m.close()
     assert out["tests"] == len(ref.steps) and out["iters"] == ref.iters
@@ -320,8 +324,9 @@ def test_ses_bf16_solve_vs_original_points():
     V = synth.ses_gaussian_outliers(4000, 100, 7).astype(np.float32)
     V64 = V.astype(np.float64)
     _, Vq = bf16_points(V)
+    import paper_2405_09157_amd as scp
     ref = oses.solve(V64, eps=1e-2)
-    m = mwu(dev(V, torch.float32), "ses", eps=1e-2, storage="bf16")
+    m = mwu(dev(V, torch.float32), "ses", eps=1e-2, storage="bf16", flags=scp.SCP_MWU_FLAG_DETERMINISTIC)
     out = m.solve()
     m.close()
     c = np.array(out["center"])
@@ -456,6 +461,35 @@ def test_svm_end_to_end():
     assert abs(out["upper"] - ref.upper) / ref.upper <= RESULT_F32
     assert np.linalg.norm(np.array(out["w"]) - ref.w) <= RESULT_F32
     assert abs(out["s1"] + out["s2"] - ref.margin) / ref.margin <= RESULT_F32
+
+
+# SVM search paths with every decision of the oracle at least this far from
+# its threshold (relative; oracle/svm.py SolveResult.tie_margin): the GPU must
+# then reproduce the oracle's tests and iteration counts exactly.
+SVM_PINNED = 5e-5
+
+
+@pytest.mark.parametrize("seed", [6])
+def test_svm_end_to_end_mid_size(seed):
+    """SVM at 5,000 planted points (2,500 per class) in d = 32 with FP32
+    storage: the eps = 1e-2 search with a 1,000-iteration cap (the oracle's
+    share a few seconds) reproduces the oracle's tests and iterations, and the
+    margin, its certified upper bound and the normal within the FP32 result
+    bar."""
+    import torch
+    X, _ = synth.svm_planted(2500, 2500, 32, seed=seed)
+    X = X.astype(np.float32)
+    ref = osvm.solve(X.astype(np.float64), 2500, eps=1e-2, t_cap=1000)
+    assert ref.tie_margin >= SVM_PINNED
+    assert {st[2] for st in ref.steps} >= {osvm.SEPARATED, osvm.T_REACHED}
+    m = mwu(dev(X, torch.float32), "svm", n_pos=2500, eps=1e-2, t_cap=1000)
+    out = m.solve()
+    m.close()
+    assert out["tests"] == len(ref.steps) and out["iters"] == ref.iters, (out["tests"], out["iters"], ref.iters)
+    assert abs(out["value"] - ref.margin) <= RESULT_F32 * max(ref.margin, 1e-3)
+    assert abs(out["upper"] - ref.upper) / ref.upper <= RESULT_F32
+    if ref.w is not None:
+        assert np.linalg.norm(np.array(out["w"]) - ref.w) <= RESULT_F32
 
 
 # -------------------------------------------------- rows past n are never read

@@ -95,3 +95,27 @@ def test_practical_solve_certified_planted():
     # Section 5 practice: an actual margin, below the exact one, within the
     # accuracy the stabilisation rule allows here (a few percent).
     assert 0.9 * m_star <= r.margin <= m_star * (1 + 1e-12)
+
+
+def test_certify_svm_upper_pins():
+    """certify.svm_upper = ||P mu - Q gam|| over normalised simplex weights (the
+    dual polytope-distance problem, eq.(pd)): equal to the hull distance at the
+    closest points' weights (closed form), and never below the exact maximum
+    margin (direction enumeration in 2-D) for random weights, by weak duality."""
+    # closed form: the segment P from (0, 1) to (2, 1) and the point (1, -1)
+    X = np.array([[0.0, 1.0], [2.0, 1.0], [1.0, -1.0]])
+    assert abs(certify.svm_upper(X, 2, [0.5, 0.5], [1.0]) - 2.0) < 1e-15
+    assert abs(certify.svm_upper(X, 2, [1.0, 0.0], [1.0]) - np.sqrt(5.0)) < 1e-15
+    assert abs(certify.svm_upper(X, 2, [3.0, 3.0], [2.0]) - 2.0) < 1e-15    # weights are normalised
+    rng = np.random.default_rng(21)
+    for seed in range(5):
+        Xs, _ = synth.svm_planted(15, 12, 2, seed=seed, shift=0.6, margin=0.3)
+        m_star, _ = exact.svm2d(Xs, 15)
+        for _ in range(50):
+            mu, gam = rng.random(15), rng.random(12)
+            assert certify.svm_upper(Xs, 15, mu, gam) >= m_star * (1 - 1e-12)
+        # the weights of the two closest points (a vertex pair) reach the bound
+        # only when the hull distance is a vertex-vertex distance; an extreme
+        # weight vector is still an upper bound
+        i, j = 0, 0
+        assert certify.svm_upper(Xs, 15, np.eye(15)[i], np.eye(12)[j]) >= m_star * (1 - 1e-12)
