@@ -271,6 +271,23 @@ int scp_mwu_backward(scp_mwu_ctx *ctx, double grad_value, float *grad_points, do
                      int32_t checkpoint_every);
 
 /*
+ * scp_mwu_backward for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same reverse pass, arguments and results, with its workspace in a
+ * static device array of the library (128 MiB on every GPU the library runs
+ * on, held until the process ends) instead of a per-call allocation.  No
+ * hipMalloc, hipFree or allocating routine is called.  A call whose
+ * workspace would exceed the array (about (T/K + 2K) d + 2 K n + n d
+ * doubles with checkpoint_every = K; 2 T d + 100 n + n d for K = 0) fails
+ * with SCP_MWU_E_INVAL before any launch, its text naming the bytes needed.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (two streams, two host threads) race.  Blocks until the result is
+ * written, like scp_mwu_backward.
+ */
+int scp_mwu_backward_noalloc(scp_mwu_ctx *ctx, double grad_value, float *grad_points, double *value,
+                             int32_t checkpoint_every);
+
+/*
  * Inspect or replace the running sums of the current test (checkpoint /
  * resume, and step-level comparison with a reference).
  * sums (host): SES: d values sum_{tau<=t} u(tau); SVM: d + 2 values

@@ -28,7 +28,8 @@ OUTCOME_NAMES = {0: "running", 1: "separated", 2: "beat_alpha", 3: "stabilized",
                  4: "t_reached", 5: "numeric"}
 
 # symbols the header declares (checked by the CPU test suite)
-EXPORTS = ("scp_mwu_init", "scp_mwu_step", "scp_mwu_solve", "scp_mwu_backward", "scp_mwu_product_init",
+EXPORTS = ("scp_mwu_init", "scp_mwu_step", "scp_mwu_solve", "scp_mwu_backward", "scp_mwu_backward_noalloc",
+           "scp_mwu_product_init",
            "scp_mwu_product_exp", "scp_mwu_product_destroy",
            "scp_mwu_get_state", "scp_mwu_set_state", "scp_mwu_get_vector", "scp_mwu_get_D",
            "scp_mwu_destroy", "scp_mwu_last_error", "scp_mwu_strerror", "scp_mwu_cast_bf16",
@@ -138,6 +139,7 @@ def load() -> ctypes.CDLL:
         "scp_mwu_step": (i32, [vp, f64, i64, i32, i32, P(scp_mwu_stepinfo)]),
         "scp_mwu_solve": (i32, [vp, P(scp_mwu_result), P(f64)]),
         "scp_mwu_backward": (i32, [vp, f64, P(ctypes.c_float), P(f64), i32]),
+        "scp_mwu_backward_noalloc": (i32, [vp, f64, P(ctypes.c_float), P(f64), i32]),
         "scp_mwu_product_init": (i32, [i64, P(i64), i64, i64, vp, P(vp)]),
         "scp_mwu_product_exp": (i32, [vp, vp, f64, vp, P(f64)]),
         "scp_mwu_product_destroy": (None, [vp]),
@@ -211,6 +213,14 @@ def scp_mwu_backward(ctx, grad_value: float, grad_points_ptr, checkpoint_every: 
     value = ctypes.c_double()
     gp = ctypes.cast(grad_points_ptr, ctypes.POINTER(ctypes.c_float)) if grad_points_ptr else None
     _check(load().scp_mwu_backward(ctx, grad_value, gp, ctypes.byref(value), int(checkpoint_every)), ctx)
+    return value.value
+
+
+def scp_mwu_backward_noalloc(ctx, grad_value: float, grad_points_ptr, checkpoint_every: int = 50) -> float:
+    """scp_mwu_backward on the library's static workspace (no allocation)."""
+    value = ctypes.c_double()
+    gp = ctypes.cast(grad_points_ptr, ctypes.POINTER(ctypes.c_float)) if grad_points_ptr else None
+    _check(load().scp_mwu_backward_noalloc(ctx, grad_value, gp, ctypes.byref(value), int(checkpoint_every)), ctx)
     return value.value
 
 

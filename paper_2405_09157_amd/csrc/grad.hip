@@ -22,7 +22,9 @@
 // caller's FP32 buffer.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
+#include "../../include/scp_mwu.h"
 #include "grad.hpp"
 
 namespace scpmwu {
@@ -762,3 +764,42 @@ hipError_t run_backward(const Buffers &b, double gv, hipStream_t s) {
 
 }  // namespace grad
 }  // namespace scpmwu
+
+// ====================================================== no-alloc reverse pass
+// scp_mwu_backward for callers that may not allocate device memory: the same
+// kernels on a workspace held in this library's static device memory,
+// `scratch` (kScratchBytes on every GPU the library runs on, for the life of
+// the process).  In host code the array's name stands for the symbol, not a
+// device address: its address is looked up once per device, with that device
+// current, and only that pointer is handed to the kernels.  Every call on a
+// GPU shares its array, so calls that overlap on one GPU race; a call leaves
+// its contents behind, and the reverse pass clears what it accumulates into
+// (the gradient accumulator) before use.
+namespace {
+
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+extern "C" int scp_mwu_backward_noalloc(scp_mwu_ctx *ctx, double grad_value, float *grad_points, double *value,
+                                        int32_t checkpoint_every) {
+  if (!ctx) return SCP_MWU_E_INVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SCP_MWU_E_HIP;
+  void *ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void *p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SCP_MWU_E_HIP;
+      g_scratch_ptr[dev] = p;
+    }
+    ptr = g_scratch_ptr[dev];
+  }
+  return scpmwu::backward_with_workspace(ctx, grad_value, grad_points, value, checkpoint_every, ptr, kScratchBytes);
+}

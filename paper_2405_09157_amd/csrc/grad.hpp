@@ -10,7 +10,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
+
+struct scp_mwu_ctx;
 
 namespace scpmwu {
 namespace grad {
@@ -51,4 +54,10 @@ inline int64_t ck_count(int64_t T, int64_t K) { return T / K + 2; }
 hipError_t run_backward(const Buffers &b, double grad_value, hipStream_t s);
 
 }  // namespace grad
+
+// scp_mwu_backward on a workspace: allocated for the call when ws is nullptr,
+// else the caller's ws_bytes at ws (a call that needs more fails with
+// SCP_MWU_E_INVAL before any launch).  Defined with the C ABI's host code.
+int backward_with_workspace(scp_mwu_ctx *c, double grad_value, float *grad_points, double *value,
+                            int32_t checkpoint_every, void *ws, size_t ws_bytes);
 }  // namespace scpmwu

@@ -354,6 +354,78 @@ int read_vec(scp_mwu_ctx *c, int which, double *out) {
 
 }  // namespace
 
+// The reverse pass of scp_mwu_backward on a workspace: allocated here for
+// the call (ws == nullptr) or the caller's (ws_bytes long; too small is an
+// error and nothing is launched).
+int scpmwu::backward_with_workspace(scp_mwu_ctx *c, double grad_value, float *grad_points, double *value,
+                                    int32_t checkpoint_every, void *ws, size_t ws_bytes) {
+  if (!c) return SCP_MWU_E_INVAL;
+  if (!grad_points && !value) return c->fail(SCP_MWU_E_INVAL, "grad_points and value are both NULL");
+  if (!std::isfinite(grad_value)) return c->fail(SCP_MWU_E_INVAL, "grad_value is not finite");
+  if (checkpoint_every < 0 || checkpoint_every > grad::kSegment)
+    return c->fail(SCP_MWU_E_INVAL, "checkpoint_every must be 0 (keep the whole tape) or 1 .. 50");
+  if (c->problem != kSES || c->radii)
+    return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: SES on point sets only");
+  if (c->dtype != kF32 && c->dtype != kF64 && c->dtype != kBF16)
+    return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: points streamed as F32, F64 or BF16 only (no FP8 storage)");
+  if (c->d > 512) return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: d > 512");
+  if (!c->active) return c->fail(SCP_MWU_E_STATE, "backward before any test");
+  int rc = SCP_MWU_OK;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return c->fail(SCP_MWU_E_HIP, "device query failed");
+  grad::Buffers b{};
+  b.n = c->n;
+  b.d = c->d;
+  b.ld = c->ld;
+  b.v1 = c->v1;
+  b.T = c->T;
+  b.dtype = c->dtype == kF64 ? 1 : (c->dtype == kBF16 ? 2 : 0);
+  b.X = c->X;
+  b.alpha = c->alpha;
+  b.eta = c->eta;
+  // four workgroups per CU, at least 64 rows per workgroup
+  b.grid = (int)std::max<int64_t>(1, std::min<int64_t>(4 * (int64_t)std::max(cus, 1), (c->n + 63) / 64));
+  const bool full = checkpoint_every == 0;
+  b.full = full ? 1 : 0;
+  b.seg = full ? grad::kSegment : checkpoint_every;
+  const int64_t d = c->d, K = b.seg, L = full ? c->T : K;  // tape slots
+  // the value alone needs neither the per-row coefficients nor the accumulator
+  const int64_t rows = grad_points ? c->n : 0;
+  const int64_t sizes[] = {d, grad::ck_count(c->T, K) * d, (L + 1) * d, L * d, (L + 1) * 4,
+                           (int64_t)b.grid * (d + 2), d, K * d, d, d, 8, K * rows, K * rows, 2, rows * d};
+  int64_t total = 0;
+  for (int64_t v : sizes) total += (v + 31) / 32 * 32;
+  const size_t need = (size_t)total * sizeof(double);
+  void *mem = ws;
+  if (ws) {
+    if (need > ws_bytes)
+      return c->fail(SCP_MWU_E_INVAL, "backward: the call needs " + std::to_string(need) +
+                                           " bytes of workspace, more than the " + std::to_string(ws_bytes) +
+                                           " available (fewer rows, a smaller d or checkpoint_every)");
+  } else if (hipMalloc(&mem, need) != hipSuccess) {
+    return c->fail(SCP_MWU_E_NOMEM, "backward workspace");
+  }
+  double *p = (double *)mem;
+  double **dst[] = {&b.S, &b.ck, &b.tc, &b.tw, &b.ts, &b.part, &b.lam, &b.lw, &b.gv1, &b.ubar, &b.misc, &b.sa, &b.sb};
+  for (int k = 0; k < 13; ++k) {
+    *dst[k] = p;
+    p += (sizes[k] + 31) / 32 * 32;
+  }
+  b.idx = (int64_t *)p;
+  p += 32;
+  b.gacc = p;
+  b.grad = grad_points;
+  rc = c->hip(grad::run_backward(b, grad_value, c->stream), "backward");
+  double misc[3] = {0, 0, 0};
+  if (!rc) rc = c->hip(hipMemcpyAsync(misc, b.misc, sizeof(misc), hipMemcpyDeviceToHost, c->stream), "backward readback");
+  const hipError_t es = hipStreamSynchronize(c->stream);  // the workspace is freed (or reusable) only when idle
+  if (!rc) rc = c->hip(es, "backward sync");
+  if (!ws) hipFree(mem);
+  if (!rc && value) *value = misc[1];
+  return rc;
+}
+
 // ============================================================== C ABI
 extern "C" {
 
@@ -710,64 +782,7 @@ int scp_mwu_get_vector(scp_mwu_ctx *c, int32_t which, double *y) {
 
 int scp_mwu_backward(scp_mwu_ctx *c, double grad_value, float *grad_points, double *value,
                      int32_t checkpoint_every) {
-  if (!c) return SCP_MWU_E_INVAL;
-  if (!grad_points && !value) return c->fail(SCP_MWU_E_INVAL, "grad_points and value are both NULL");
-  if (!std::isfinite(grad_value)) return c->fail(SCP_MWU_E_INVAL, "grad_value is not finite");
-  if (checkpoint_every < 0 || checkpoint_every > grad::kSegment)
-    return c->fail(SCP_MWU_E_INVAL, "checkpoint_every must be 0 (keep the whole tape) or 1 .. 50");
-  if (c->problem != kSES || c->radii)
-    return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: SES on point sets only");
-  if (c->dtype != kF32 && c->dtype != kF64 && c->dtype != kBF16)
-    return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: points streamed as F32, F64 or BF16 only (no FP8 storage)");
-  if (c->d > 512) return c->fail(SCP_MWU_E_UNSUPPORTED, "backward: d > 512");
-  if (!c->active) return c->fail(SCP_MWU_E_STATE, "backward before any test");
-  int rc = SCP_MWU_OK;
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return c->fail(SCP_MWU_E_HIP, "device query failed");
-  grad::Buffers b{};
-  b.n = c->n;
-  b.d = c->d;
-  b.ld = c->ld;
-  b.v1 = c->v1;
-  b.T = c->T;
-  b.dtype = c->dtype == kF64 ? 1 : (c->dtype == kBF16 ? 2 : 0);
-  b.X = c->X;
-  b.alpha = c->alpha;
-  b.eta = c->eta;
-  // four workgroups per CU, at least 64 rows per workgroup
-  b.grid = (int)std::max<int64_t>(1, std::min<int64_t>(4 * (int64_t)std::max(cus, 1), (c->n + 63) / 64));
-  const bool full = checkpoint_every == 0;
-  b.full = full ? 1 : 0;
-  b.seg = full ? grad::kSegment : checkpoint_every;
-  const int64_t d = c->d, K = b.seg, L = full ? c->T : K;  // tape slots
-  // the value alone needs neither the per-row coefficients nor the accumulator
-  const int64_t rows = grad_points ? c->n : 0;
-  const int64_t sizes[] = {d, grad::ck_count(c->T, K) * d, (L + 1) * d, L * d, (L + 1) * 4,
-                           (int64_t)b.grid * (d + 2), d, K * d, d, d, 8, K * rows, K * rows, 2, rows * d};
-  int64_t total = 0;
-  for (int64_t v : sizes) total += (v + 31) / 32 * 32;
-  void *mem = nullptr;
-  if (hipMalloc(&mem, (size_t)total * sizeof(double)) != hipSuccess)
-    return c->fail(SCP_MWU_E_NOMEM, "backward workspace");
-  double *p = (double *)mem;
-  double **dst[] = {&b.S, &b.ck, &b.tc, &b.tw, &b.ts, &b.part, &b.lam, &b.lw, &b.gv1, &b.ubar, &b.misc, &b.sa, &b.sb};
-  for (int k = 0; k < 13; ++k) {
-    *dst[k] = p;
-    p += (sizes[k] + 31) / 32 * 32;
-  }
-  b.idx = (int64_t *)p;
-  p += 32;
-  b.gacc = p;
-  b.grad = grad_points;
-  rc = c->hip(grad::run_backward(b, grad_value, c->stream), "backward");
-  double misc[3] = {0, 0, 0};
-  if (!rc) rc = c->hip(hipMemcpyAsync(misc, b.misc, sizeof(misc), hipMemcpyDeviceToHost, c->stream), "backward readback");
-  const hipError_t es = hipStreamSynchronize(c->stream);  // the workspace is freed only when idle
-  if (!rc) rc = c->hip(es, "backward sync");
-  hipFree(mem);
-  if (!rc && value) *value = misc[1];
-  return rc;
+  return scpmwu::backward_with_workspace(c, grad_value, grad_points, value, checkpoint_every, nullptr, 0);
 }
 
 int scp_mwu_solve(scp_mwu_ctx *c, scp_mwu_result *res, double *y) {
