@@ -131,6 +131,9 @@ struct PassArgs {
   double *vec;            // kNumVec * d
   double *partials;       // gridDim.x * partial_width(d), 16-byte aligned
   const float *scales;    // FP8 storage: one binary32 scale per row; else nullptr
+  double *gsum;           // unfused single-problem pass: add the workgroup sums
+                          // into this one global sum (atomics) instead of
+                          // writing records; nullptr: records
 };
 
 // Parameters of a new alpha-feasibility test (written by the init kernel).

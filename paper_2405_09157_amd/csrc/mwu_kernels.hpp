@@ -478,8 +478,8 @@ struct StatePrologue {
   __device__ __forceinline__ void pre() {}
   __device__ __forceinline__ PassIn post() {
     const DevState *st = a.st;
-    return PassIn{st->status, st->kscale * (double)st->t, st->shift_bound, a.vec + kVecMean * a.d, a.partials,
-                  false};
+    return PassIn{st->status, st->kscale * (double)st->t, st->shift_bound, a.vec + kVecMean * a.d,
+                  a.gsum != nullptr ? a.gsum : a.partials, a.gsum != nullptr};
   }
 };
 
@@ -979,15 +979,29 @@ void svm_pass_kernel(PassArgs a) {
     s_sc[wave][6] = nslmin;
   }
   __syncthreads();
-  double *rec = a.partials + (int64_t)blockIdx.x * pw;
+  // the workgroup's record, or its sums added into the global sum
+  const bool to_gsum = a.gsum != nullptr;
+  double *rec = to_gsum ? a.gsum : a.partials + (int64_t)blockIdx.x * pw;
   const int dp = rec_dp(d);
-  for (int c = tid; c < d; c += kPassBlock) rec[c] = sum_waves(s_vec, c);
+  for (int c = tid; c < d; c += kPassBlock) {
+    const double v = sum_waves(s_vec, c);
+    if (to_gsum)
+      gsum_add(rec + c, v);
+    else
+      rec[c] = v;
+  }
   __syncthreads();
   if (g == 0)
 #pragma unroll
     for (int k = 0; k < EPL; ++k) s_vec[wave][cl * EPL + k] = accQ[k];
   __syncthreads();
-  for (int c = tid; c < d; c += kPassBlock) rec[dp + 8 + c] = sum_waves(s_vec, c);
+  for (int c = tid; c < d; c += kPassBlock) {
+    const double v = sum_waves(s_vec, c);
+    if (to_gsum)
+      gsum_add(rec + dp + 8 + c, v);
+    else
+      rec[dp + 8 + c] = v;
+  }
   if (tid < 8) {
     double v;
     if (tid < 2)
@@ -998,7 +1012,12 @@ void svm_pass_kernel(PassArgs a) {
       v = max_waves(s_sc, tid);
     else
       v = -INFINITY;
-    rec[dp + tid] = v;
+    if (!to_gsum)
+      rec[dp + tid] = v;
+    else if (tid < 2)
+      gsum_add(rec + dp + tid, v);
+    else if (tid >= 4 && tid < 7)
+      gsum_max(rec + dp + tid, v);
   }
 }
 
@@ -1375,8 +1394,9 @@ __device__ __forceinline__ void epilogue_stage(const PassArgs &a, const DevState
   if (L.st.status != kRunning || !(force || L.st.pending)) return;  // uniform: read from LDS
   if (gmode) {
     const int dp = rec_dp((int)a.d), ncols = rec_read_cols<PROB, CERT>((int)a.d);
+    const int nsc = PROB == kSES ? 5 : 4;  // summed scalars; then the maxima up to slot 6
     for (int c = threadIdx.x; c < ncols; c += NT)
-      L.comb[c] = (c == dp + 5 || c == dp + 6)
+      L.comb[c] = (c >= dp + nsc && c <= dp + 6)
                       ? from_max_key((unsigned long long)__double_as_longlong(rec[c])) : rec[c];
     __syncthreads();
   } else {
@@ -1401,11 +1421,15 @@ __device__ __forceinline__ void epilogue_store(EpiLDS<DMAX> &L, int d, int32_t p
 // record visible: no fences.  force: records of a pass that just ran are
 // there (the unfused iteration); otherwise only pending records are applied
 // (the flush after fused passes).
+// gmode: a.partials is one global sum; it is cleared after it is read (the
+// next unfused pass adds into it).
 template <typename T, int PROB, bool CERT, int NT = kCombBlock>
 __device__ __forceinline__ void epilogue_body(const PassArgs &a, int P, bool force = true, bool gmode = false) {
   __shared__ EpiLDS<kMaxD> L;
   epilogue_stage<T, PROB, CERT, NT, kMaxD>(a, a.st, a.vec, a.partials, P, force, L, gmode);
   epilogue_store<NT, kMaxD>(L, (int)a.d, 0, a.st, a.vec);
+  if (gmode)
+    for (int c = threadIdx.x; c < rec_width((int)a.d); c += NT) a.partials[c] = 0.0;
 }
 
 template <typename T, int PROB, bool CERT>
@@ -1675,6 +1699,12 @@ hipError_t launch_pass_t(int problem, const LaunchCfg &c, const PassArgs &a, hip
 
 template <typename T, int PROB, bool CERT>
 hipError_t launch_epilogue_p(int grid, const PassArgs &a, hipStream_t s) {
+  if (a.gsum != nullptr) {  // the pass added into one global sum
+    PassArgs e = a;
+    e.partials = a.gsum;
+    hipLaunchKernelGGL((epilogue_kernel<T, PROB, CERT>), dim3(1), dim3(kCombBlock), 0, s, e, 1, 1, 1);
+    return hipGetLastError();
+  }
   // records of the pass: a.partials[0 .. grid); group sums after them
   PassArgs e = a;
   int P = grid;

@@ -587,6 +587,9 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
     if (fe[0] == '0') c->fused = false;
   c->rec_stride = (int64_t)(grid + rec_groups(grid)) * pw;
   c->gmode = c->fused && !(c->flags & SCP_MWU_FLAG_DETERMINISTIC);
+  // unfused passes (SVM, SES with large records) add into one global sum
+  // that their epilogue reads and clears
+  const bool gsum_unfused = !c->fused && !(c->flags & SCP_MWU_FLAG_DETERMINISTIC);
   c->g_stride = (pw + 31) / 32 * 32;
   if (hipMalloc(&c->st_base, 2 * sizeof(DevState)) != hipSuccess ||
       hipMalloc(&c->vec_base, 2 * sizeof(double) * kNumVec * c->d) != hipSuccess ||
@@ -606,6 +609,11 @@ int scp_mwu_init(const scp_mwu_desc *desc, scp_mwu_ctx **out) {
   a.v1 = c->v1;
   a.n_pos = c->n_pos;
   a.scales = c->owned_scales;
+  if (gsum_unfused) {
+    if (hipMemsetAsync(c->g_base, 0, sizeof(double) * (size_t)c->g_stride, c->stream) != hipSuccess)
+      return fail(SCP_MWU_E_HIP, "sum clear");
+    a.gsum = c->g_base;
+  }
   a.st = c->st_base;
   a.vec = c->vec_base;
   a.partials = c->part_base;
