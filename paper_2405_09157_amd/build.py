@@ -23,6 +23,7 @@ LIB = os.path.join(PKG, "libscpmwu.so")
 ARCH = os.environ.get("SCPMWU_ARCH", "gfx950")
 
 SOURCES = ["pass_f32.hip", "pass_bf16.hip", "pass_f64.hip", "pass_fp8.hip", "batch_f32.hip", "batch_bf16.hip",
+           "kway_f32.hip", "kway_bf16.hip",
            "misc.hip", "grad.hip", "cone.hip", "scp_mwu_host.cpp", "batch_host.cpp"]
 
 

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -123,6 +124,10 @@ struct scp_mwu_batch {
   double *h_vec = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool any_test = false;
+  // 2 .. 4 instances over one point set (the k-way search): one pass loads
+  // each batch of rows once for all of them (column layout kw_epl, kw_vec,
+  // kw_grid workgroups = every instance's share count)
+  int kway = 0, kw_epl = 1, kw_vec = 1, kw_grid = 1;
   std::string err;
 
   int fail(int code, const std::string &msg) {
@@ -151,12 +156,23 @@ hipError_t epilogue_launch(scp_mwu_batch *b, hipStream_t s) {
                            : launch_epilogue_batch_f32(b->m, b->args, b->nrec, s);
 }
 
-// One iteration of every running instance.
-hipError_t iteration(scp_mwu_batch *b, hipStream_t s) {
+// The streaming pass of every running instance (one launch per layout, or
+// the shared-read pass of a k-way batch).
+hipError_t passes(scp_mwu_batch *b, hipStream_t s) {
+  if (b->kway)
+    return b->dtype == kBF16 ? launch_kway_batch_bf16(b->kw_epl, b->kw_vec, b->kway, b->kw_grid, b->args, s)
+                             : launch_kway_batch_f32(b->kw_epl, b->kw_vec, b->kway, b->kw_grid, b->args, s);
   for (const Layout &l : b->layouts) {
     const hipError_t e = pass_launch(b, l, s);
     if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+// One iteration of every running instance.
+hipError_t iteration(scp_mwu_batch *b, hipStream_t s) {
+  const hipError_t e = passes(b, s);
+  if (e != hipSuccess) return e;
   return epilogue_launch(b, s);
 }
 
@@ -462,6 +478,31 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
     if (hipMemcpy(l.tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
       return fail(SCP_MWU_E_HIP, "tile upload");
   }
+  // a k-way batch: 2 .. 4 instances over the same rows share each load
+  // (SCPMWU_KWAY_SHARED=0 keeps one pass per instance, for comparison)
+  bool same = m >= 2 && m <= 4;
+  if (const char *ke = getenv("SCPMWU_KWAY_SHARED"))
+    if (ke[0] == '0') same = false;
+  for (int k = 1; k < m && same; ++k)
+    same = b->inst[k].n == b->inst[0].n && b->inst[k].d == b->inst[0].d && b->inst[k].offset == b->inst[0].offset;
+  if (same) {
+    const Inst &I0 = b->inst[0];
+    int ce = 1;
+    while (kG * ce < I0.d) ce *= 2;
+    const int vf = std::min<int>(ce, (int)(16 / es));
+    const uintptr_t base = (uintptr_t)b->X + (uintptr_t)(I0.offset * es);
+    int cv = 1;
+    for (int v : {vf, vf >= 4 ? vf / 2 : 1, 1}) {
+      if (I0.d % v == 0 && base % (uintptr_t)(v * es) == 0) {
+        cv = v;
+        break;
+      }
+    }
+    b->kway = m;
+    b->kw_epl = ce;
+    b->kw_vec = cv;
+    b->kw_grid = I0.vg;
+  }
   // the state words start as "not running", so that a pass before any test
   // does nothing
   if (hipMemsetAsync(b->st, 0xFF, sizeof(DevState) * m, b->stream) != hipSuccess)
@@ -548,8 +589,7 @@ int scp_mwu_batch_time_iters(scp_mwu_batch *b, int32_t k, double *ms_pass, doubl
     if (!rc) rc = b->hip(hipEventCreate(&e), "event create");
   for (int i = 0; i < k && !rc; ++i) {
     rc = b->hip(hipEventRecord(ev[3 * i], b->stream), "event record");
-    for (const Layout &l : b->layouts)
-      if (!rc) rc = b->hip(pass_launch(b, l, b->stream), "pass launch");
+    if (!rc) rc = b->hip(passes(b, b->stream), "pass launch");
     if (!rc) rc = b->hip(hipEventRecord(ev[3 * i + 1], b->stream), "event record");
     if (!rc) rc = b->hip(epilogue_launch(b, b->stream), "epilogue launch");
     if (!rc) rc = b->hip(hipEventRecord(ev[3 * i + 2], b->stream), "event record");

@@ -21,6 +21,63 @@ void ses_pass_batch_kernel(const PassArgs *__restrict__ args, const BatchTile *_
   ses_pass_body<T, EPL, VEC, false, kPrefetchNone>(a, tl.vb, tl.vg);
 }
 
+// The k-way search's KS tests over one point set (instances 0 .. KS-1 share
+// the rows): each batch of rows is loaded once and every running test
+// computes its own distances, weights and sums from the registers; test j's
+// record goes to instance j's record block (workgroup vb of vg = gridDim.x).
+template <int KS>
+struct KwayPrologue {
+  const PassArgs *args;
+  __device__ __forceinline__ void pre() {}
+  __device__ __forceinline__ PassIn post() { return state_pass_in(args[0]); }
+  __device__ __forceinline__ PassIn slot(int j) { return state_pass_in(args[j]); }
+};
+
+template <typename T, int EPL, int VEC, int KS>
+__global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
+void ses_kway_batch_kernel(const PassArgs *__restrict__ args) {
+  const PassArgs a = args[0];
+  KwayPrologue<KS> pro{args};
+  ses_pass_body<T, EPL, VEC, false, kPrefetchNone, KwayPrologue<KS>, KS>(a, (int)blockIdx.x, (int)gridDim.x, pro);
+}
+
+template <typename T, int EPL, int VEC>
+hipError_t launch_kway_v(int ks, int grid, const PassArgs *args, hipStream_t s) {
+  switch (ks) {
+    case 2: hipLaunchKernelGGL((ses_kway_batch_kernel<T, EPL, VEC, 2>), dim3(grid), dim3(kPassBlock), 0, s, args); break;
+    case 3: hipLaunchKernelGGL((ses_kway_batch_kernel<T, EPL, VEC, 3>), dim3(grid), dim3(kPassBlock), 0, s, args); break;
+    case 4: hipLaunchKernelGGL((ses_kway_batch_kernel<T, EPL, VEC, 4>), dim3(grid), dim3(kPassBlock), 0, s, args); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int EPL>
+hipError_t launch_kway_e(int vec, int ks, int grid, const PassArgs *args, hipStream_t s) {
+  constexpr int VF = (16 / (int)sizeof(T)) < EPL ? (16 / (int)sizeof(T)) : EPL;
+  if (vec == VF) return launch_kway_v<T, EPL, VF>(ks, grid, args, s);
+  if constexpr (VF >= 4) {
+    if (vec == VF / 2) return launch_kway_v<T, EPL, VF / 2>(ks, grid, args, s);
+  }
+  if constexpr (VF > 1) {
+    if (vec == 1) return launch_kway_v<T, EPL, 1>(ks, grid, args, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_kway_batch_typed(int epl, int vec, int ks, int grid, const PassArgs *args, hipStream_t s) {
+  switch (epl) {
+    case 1: return launch_kway_e<T, 1>(vec, ks, grid, args, s);
+    case 2: return launch_kway_e<T, 2>(vec, ks, grid, args, s);
+    case 4: return launch_kway_e<T, 4>(vec, ks, grid, args, s);
+    case 8: return launch_kway_e<T, 8>(vec, ks, grid, args, s);
+    case 16: return launch_kway_e<T, 16>(vec, ks, grid, args, s);
+    case 32: return launch_kway_e<T, 32>(vec, ks, grid, args, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // Row-per-lane SES pass for instances with d <= DM <= 16 columns: every lane
 // owns RL = 2 whole rows of a batch (a wave batch is 128 rows), so a row's
 // squared distance is summed inside the lane and the binary64 chains of the

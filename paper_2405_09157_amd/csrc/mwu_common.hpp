@@ -166,7 +166,8 @@ struct BatchTile {
                                       const InitParams *params, hipStream_t s);                          \
   hipError_t launch_diameter_batch_##name(int m, const PassArgs *args, double *D, hipStream_t s);         \
   hipError_t launch_rows_batch_##name(int dm, int vec, int ntiles, const PassArgs *args,                  \
-                                      const BatchTile *tiles, hipStream_t s);
+                                      const BatchTile *tiles, hipStream_t s);                            \
+  hipError_t launch_kway_batch_##name(int epl, int vec, int ks, int grid, const PassArgs *args, hipStream_t s);
 SCPMWU_DECLARE_BATCH(f32)
 SCPMWU_DECLARE_BATCH(bf16)
 #undef SCPMWU_DECLARE_BATCH

@@ -240,10 +240,13 @@ struct Batch<uint8_t, SB, EPL, true> {
 };
 
 // Batch shape of the streaming pass (pass_steps): SB load steps of 4 rows.
-template <typename T, int EPL, int PROB, int PFM>
+// k-way slots keep KS sets of d accumulators in registers; from KS = 4 on
+// the batch takes half the load steps (four sets at full size spill).
+template <typename T, int EPL, int PROB, int PFM, int KS = 1>
 struct PassShape {
   static constexpr bool PACK = pass_packed((int)sizeof(T), EPL, PROB);
-  static constexpr int SB = pass_steps((int)sizeof(T), EPL, PROB, PFM);
+  static constexpr int SB0 = pass_steps((int)sizeof(T), EPL, PROB, PFM);
+  static constexpr int SB = KS >= 4 && SB0 > 1 ? SB0 / 2 : SB0;
   static constexpr int B = SB * kRowsPerStep;
   static_assert(B <= kWave, "the per-row phase holds one row per lane");
   using Regs = Batch<T, SB, EPL, PACK>;
@@ -473,19 +476,25 @@ __device__ __forceinline__ void gsum_max(double *p, double v) {
 // and returns the inputs (the fused kernel issues the previous pass's record
 // loads in pre() and runs that pass's epilogue in post()); the plain form
 // reads the state as it is.
+__device__ __forceinline__ PassIn state_pass_in(const PassArgs &a) {
+  const DevState *st = a.st;
+  return PassIn{st->status, st->kscale * (double)st->t, st->shift_bound, a.vec + kVecMean * a.d,
+                a.gsum != nullptr ? a.gsum : a.partials, a.gsum != nullptr};
+}
 struct StatePrologue {
   const PassArgs &a;
   __device__ __forceinline__ void pre() {}
-  __device__ __forceinline__ PassIn post() {
-    const DevState *st = a.st;
-    return PassIn{st->status, st->kscale * (double)st->t, st->shift_bound, a.vec + kVecMean * a.d,
-                  a.gsum != nullptr ? a.gsum : a.partials, a.gsum != nullptr};
-  }
+  __device__ __forceinline__ PassIn post() { return state_pass_in(a); }
 };
 
-template <typename T, int EPL, int VEC, bool CERT, int PFM, typename Pro>
+// KS > 1: the k-way search's tests over one point set (a: the set; slot j's
+// inputs from prologue.slot(j), j >= 1): each batch of rows is loaded once and
+// phases 1-3 run once per slot, each slot with its own mean, exponent scale,
+// sums and record.  KS = 1 is the single test.
+template <typename T, int EPL, int VEC, bool CERT, int PFM, typename Pro, int KS = 1>
 __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg, Pro &prologue) {
-  using Sh = PassShape<T, EPL, kSES, PFM>;
+  static_assert(KS >= 1 && (KS == 1 || (!CERT && PFM == kPrefetchNone)), "k-way slots: no certificate, no prefetch");
+  using Sh = PassShape<T, EPL, kSES, PFM, KS>;
   constexpr int SB = Sh::SB, B = Sh::B;
   using Regs = typename Sh::Regs;
   // BF16 storage: per-element arithmetic in binary32 (the row distance
@@ -500,7 +509,7 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
   __shared__ float s_scl[kPassWaves][FP8 ? B : 1];
   __shared__ double s_vec[kPassWaves][kG * EPL];
   __shared__ double s_sc[kPassWaves][8];
-  __shared__ double s_ctr[kG * EPL];  // the candidate (ubar or wbar), zero-padded
+  __shared__ double s_ctr[KS][kG * EPL];  // each slot's candidate (ubar), zero-padded
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -510,29 +519,44 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
   const T *__restrict__ X = reinterpret_cast<const T *>(a.X);
   const double *__restrict__ radii = a.radii;
   const int64_t v1 = a.v1;
-  // set by the prologue (grid-uniform), read by the phases below
-  int32_t status0 = kRunning;
-  double kappa = 0.0, Gb = 0.0;
-  double *rec_base = nullptr;
-  bool to_gsum = false;
+  // set by the prologue (grid-uniform per slot), read by the phases below
+  int32_t status[KS];
+  double kappa[KS], Gb[KS];
+  double *rec_base[KS];
+  bool to_gsum = false, any_running = false;
   auto start = [&]() {
-    const PassIn in = prologue.post();
-    status0 = __builtin_amdgcn_readfirstlane(in.status);
-    kappa = in.kappa;
-    Gb = in.Gb;
-    rec_base = in.rec;
-    to_gsum = in.gsum;
-    for (int c = tid; c < kG * EPL; c += kPassBlock) s_ctr[c] = c < d ? in.ybar[c] : 0.0;
-    // status0 is the same for the whole grid: either every wave returns
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      PassIn in;
+      if constexpr (KS == 1)
+        in = prologue.post();
+      else
+        in = j == 0 ? prologue.post() : prologue.slot(j);
+      status[j] = __builtin_amdgcn_readfirstlane(in.status);
+      kappa[j] = in.kappa;
+      Gb[j] = in.Gb;
+      rec_base[j] = in.rec;
+      to_gsum = in.gsum;
+      any_running = any_running || status[j] == kRunning;
+      for (int c = tid; c < kG * EPL; c += kPassBlock) s_ctr[j][c] = c < d ? in.ybar[c] : 0.0;
+    }
+    // each status is the same for the whole grid: either every wave returns
     // after this barrier or none does
     __syncthreads();
   };
-  double wacc[EPL], cacc[CERT ? EPL : 1];
+  double wacc[KS][EPL], cacc[CERT ? EPL : 1];
 #pragma unroll
-  for (int k = 0; k < EPL; ++k) wacc[k] = 0.0;
+  for (int j = 0; j < KS; ++j)
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) wacc[j][k] = 0.0;
 #pragma unroll
   for (int k = 0; k < (CERT ? EPL : 1); ++k) cacc[k] = 0.0;
-  double asum = 0.0, bsum = 0.0, esum = 0.0, gsum = 0.0, bd2 = 0.0, gmax = -INFINITY, fall = -INFINITY;
+  double asum[KS], bsum[KS], esum[KS], gsum[KS], gmax[KS], fall[KS], bd2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < KS; ++j) {
+    asum[j] = bsum[j] = esum[j] = gsum[j] = 0.0;
+    gmax[j] = fall[j] = -INFINITY;
+  }
 
   const int64_t nb = (n + B - 1) / B;
   const int64_t GW = (int64_t)vg * kPassWaves;
@@ -561,8 +585,8 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
     const int64_t r0 = b * B;
     load_rows(xs, r0, n - r0 < B ? n - r0 : B);
   };
-  // phases 1-3 on the rows [r0, r0 + rows) held in xs
-  auto process_rows = [&](Regs &xs, int64_t r0, int64_t rows) {
+  // phases 1-3 on the rows [r0, r0 + rows) held in xs, for slot j
+  auto process_slot = [&](Regs &xs, int64_t r0, int64_t rows, int j) {
     // re-read the candidate each batch: it stays out of registers in phases 2-3
     asm volatile("" ::: "memory");
     // binary32 storage types: the mean rounded to binary32, used by phases 1 and 3
@@ -574,7 +598,7 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
       }
       float *ub = ub32;
 #pragma unroll
-      for (int k = 0; k < EPL; ++k) ub[k] = (float)s_ctr[lane_col<VEC>(cl, k)];
+      for (int k = 0; k < EPL; ++k) ub[k] = (float)s_ctr[j][lane_col<VEC>(cl, k)];
 #pragma unroll
       for (int s = 0; s < SB; ++s) {
         const float sr = FP8 ? s_scl[wave][s * kRowsPerStep + g] : 1.f;
@@ -589,7 +613,7 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
     } else {
       double ub[EPL];
 #pragma unroll
-      for (int k = 0; k < EPL; ++k) ub[k] = s_ctr[lane_col<VEC>(cl, k)];
+      for (int k = 0; k < EPL; ++k) ub[k] = s_ctr[j][lane_col<VEC>(cl, k)];
 #pragma unroll
       for (int s = 0; s < SB; ++s) {
         double dsq = 0.0;
@@ -613,19 +637,20 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
       const double gi = xs.gi;  // 0 past n or without radii
       const double h = di + gi;
       // shifted lambda_+ = kappa (h - alpha) - kappa (G - alpha) <= ~0
-      const double ep = exp(kappa * (h - Gb));
-      const double om = -expm1(-2.0 * kappa * di);  // 1 - e^{lambda_- - lambda_+}
-      double aw = di > 0.0 ? ep * om / di : 2.0 * kappa * ep;
+      const double kap = kappa[j];
+      const double ep = exp(kap * (h - Gb[j]));
+      const double om = -expm1(-2.0 * kap * di);  // 1 - e^{lambda_- - lambda_+}
+      double aw = di > 0.0 ? ep * om / di : 2.0 * kap * ep;
       double bw = ep * (2.0 - om);
       double ew = ep * om * di;
       if (!incl) aw = bw = ew = 0.0;
-      asum += aw;
-      bsum += bw;
-      esum += ew;
-      gsum += gi * bw;
+      asum[j] += aw;
+      bsum[j] += bw;
+      esum[j] += ew;
+      gsum[j] += gi * bw;
       if (CERT) bd2 += bw * dsq;
-      if (incl) gmax = fmax(gmax, h);
-      if (valid) fall = fmax(fall, h);
+      if (incl) gmax[j] = fmax(gmax[j], h);
+      if (valid) fall[j] = fmax(fall[j], h);
       s_wa[wave][lane] = aw;
       if (CERT) s_wb[wave][lane] = bw;
     }
@@ -654,7 +679,7 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
         }
       }
 #pragma unroll
-      for (int k = 0; k < EPL; ++k) wacc[k] += (double)w32[k];
+      for (int k = 0; k < EPL; ++k) wacc[j][k] += (double)w32[k];
       if (CERT)
 #pragma unroll
         for (int k = 0; k < EPL; ++k) cacc[k] += (double)c32[k];
@@ -664,7 +689,7 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
       for (int s = 0; s < SB; ++s) {
         const double ar = s_wa[wave][s * kRowsPerStep + g];
 #pragma unroll
-        for (int k = 0; k < EPL; ++k) wacc[k] = fma(ar, xs.get(s, k), wacc[k]);
+        for (int k = 0; k < EPL; ++k) wacc[j][k] = fma(ar, xs.get(s, k), wacc[j][k]);
         if (CERT) {
           const double br = s_wb[wave][s * kRowsPerStep + g];
 #pragma unroll
@@ -673,6 +698,11 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
       }
     }
     wave_lds_sync();
+  };
+  auto process_rows = [&](Regs &xs, int64_t r0, int64_t rows) {
+#pragma unroll
+    for (int j = 0; j < KS; ++j)
+      if (KS == 1 || status[j] == kRunning) process_slot(xs, r0, rows, j);
   };
   auto process = [&](Regs &xs, int64_t b) {
     const int64_t r0 = b * B;
@@ -690,7 +720,7 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
     prologue.pre();
     load_batch(xa, b);
     start();
-    if (status0 != kRunning) return;
+    if (!any_running) return;
     while (b < nb) {
       const int64_t b1 = b + GW;
       load_batch(xb, b1);
@@ -708,44 +738,48 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
     prologue.pre();
     load_batch(xs, b0);
     start();
-    if (status0 != kRunning) return;
+    if (!any_running) return;
     for (int64_t b = b0; b < nb; b += GW) {
       if (b != b0) load_batch(xs, b);
       process(xs, b);
     }
   }
-  if (status0 != kRunning) return;
+  if (!any_running) return;
+  const int pw = rec_width(d);
+  const int dp = rec_dp(d);
 
-  // ---- workgroup record: W, C(cert), sums, maxima
+  // ---- workgroup record of each running slot: W, C(cert), sums, maxima
+#pragma unroll
+  for (int j = 0; j < KS; ++j) {
+  if (KS > 1 && status[j] != kRunning) continue;
+  if (KS > 1 && j > 0) __syncthreads();  // the previous slot's record is read from LDS
 #pragma unroll
   for (int k = 0; k < EPL; ++k) {
-    wacc[k] += __shfl_xor(wacc[k], 16);
-    wacc[k] += __shfl_xor(wacc[k], 32);
+    wacc[j][k] += __shfl_xor(wacc[j][k], 16);
+    wacc[j][k] += __shfl_xor(wacc[j][k], 32);
   }
-  const int pw = rec_width(d);
   if (g == 0)
 #pragma unroll
-    for (int k = 0; k < EPL; ++k) s_vec[wave][lane_col<VEC>(cl, k)] = wacc[k];
-  asum = wave_sum(asum);
-  bsum = wave_sum(bsum);
-  esum = wave_sum(esum);
-  gsum = wave_sum(gsum);
-  bd2 = wave_sum(bd2);
-  gmax = wave_max(gmax);
-  fall = wave_max(fall);
+    for (int k = 0; k < EPL; ++k) s_vec[wave][lane_col<VEC>(cl, k)] = wacc[j][k];
+  const double w_asum = wave_sum(asum[j]);
+  const double w_bsum = wave_sum(bsum[j]);
+  const double w_esum = wave_sum(esum[j]);
+  const double w_gsum = wave_sum(gsum[j]);
+  const double w_bd2 = wave_sum(bd2);
+  const double w_gmax = wave_max(gmax[j]);
+  const double w_fall = wave_max(fall[j]);
   if (lane == 0) {
-    s_sc[wave][0] = bsum;
-    s_sc[wave][1] = esum;
-    s_sc[wave][2] = gsum;
-    s_sc[wave][3] = bd2;
-    s_sc[wave][4] = asum;
-    s_sc[wave][5] = gmax;
-    s_sc[wave][6] = fall;
+    s_sc[wave][0] = w_bsum;
+    s_sc[wave][1] = w_esum;
+    s_sc[wave][2] = w_gsum;
+    s_sc[wave][3] = w_bd2;
+    s_sc[wave][4] = w_asum;
+    s_sc[wave][5] = w_gmax;
+    s_sc[wave][6] = w_fall;
   }
   __syncthreads();
   // the workgroup's record, or its sums added into the global sum
-  double *rec = to_gsum ? rec_base : rec_base + (int64_t)vb * pw;
-  const int dp = rec_dp(d);
+  double *rec = to_gsum ? rec_base[j] : rec_base[j] + (int64_t)vb * pw;
   for (int c = tid; c < d; c += kPassBlock) {
     const double v = sum_waves(s_vec, c);
     if (to_gsum)
@@ -786,6 +820,7 @@ __device__ __forceinline__ void ses_pass_body(const PassArgs &a, int vb, int vg,
       gsum_add(rec + dp + tid, v);
     else if (tid < 7)
       gsum_max(rec + dp + tid, v);
+  }
   }
 }
 
