@@ -230,8 +230,9 @@ def svm_leg(steps, warmup, solve_budget=60_000):
     """Hard-margin SVM at 500k x 256 (planted margin, P rows then Q rows):
     MWU iterations/s and the pass's bytes over its HIP-event time for FP32 and
     BF16 storage, then eps = 1e-3 solves (the search of Section 3 mirrored for
-    the min form, Section 5 exits) within an iteration budget, with their
-    certified margin (lower) and polytope-distance upper bound."""
+    the min form, Section 5 exits) within an iteration budget (none when the
+    budget is 0), with their certified margin (lower) and polytope-distance
+    upper bound."""
     import torch
     import paper_2405_09157_amd as scp
     import synth
@@ -256,9 +257,13 @@ def svm_leg(steps, warmup, solve_budget=60_000):
         ach = nb / (kms * 1e-3) / 1e9
         out[key] = dict(iters_per_s=round(1.0 / dt, 1), ms_per_iter=round(dt * 1e3, 5),
                         roofline=dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                                      frac=round(ach / HBM_PEAK_GBS, 4), kernel_ms=round(kms, 5),
+                                      frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_for("svm_" + key),
+                                      kernel_ms=round(kms, 5),
                                       kernel=f"svm_pass_kernel<{'uint16_t' if storage else 'float'},16,"
                                              f"{8 if storage else 4},0>", bytes_per_launch=nb))
+        if not solve_budget:
+            print(f"# svm {key}: {out[key]}", file=sys.stderr, flush=True)
+            continue
         m = scp.MWU(Xd, "svm", n_pos=c["n_pos"], eps=1e-3, storage=storage, chunk=64, max_iters=solve_budget)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -324,7 +329,8 @@ def beyond_cache(steps):
         nb = 2_000_000 * 100 * es
         ach = nb / (r["kernel_ms"] * 1e-3) / 1e9
         out[storage or "f32"] = dict(ms_per_iter=round(r["ms_per_step"], 5), kernel_ms=round(r["kernel_ms"], 5),
-                                     bytes=nb, GBs=round(ach, 1), hbm_frac=round(ach / HBM_PEAK_GBS, 4))
+                                     bytes=nb, GBs=round(ach, 1), hbm_frac=round(ach / HBM_PEAK_GBS, 4),
+                                     traffic=traffic_for((storage or "f32") + "_2e6"))
     out["bf16_over_f32_iteration_rate"] = round(out["f32"]["ms_per_iter"] / out["bf16"]["ms_per_iter"], 4)
     print(f"# beyond cache: {out}", file=sys.stderr, flush=True)
     del X
@@ -568,7 +574,7 @@ def main(argv=None):
     cone = None if a.no_cone else product_cone()
     if cone:
         print(f"# product cone: {cone}", file=sys.stderr, flush=True)
-    svm = None if a.no_svm else svm_leg(min(a.steps, 640), a.warmup)
+    svm = None if a.no_svm else svm_leg(min(a.steps, 640), a.warmup, solve_budget=0 if a.no_solve else 60_000)
     small = None if a.no_small else small_config()
     big = None if a.no_big else beyond_cache(min(max(a.steps, 64), 640))
     cpu = None if a.no_cpu else cpu_baseline(V)
@@ -579,7 +585,7 @@ def main(argv=None):
     ach = algo_bytes / (f32["kernel_ms"] * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic_for("f32"),
-                kernel="ses_fused_kernel<float,8,4,false,0>", kernel_ms=round(f32["kernel_ms"], 5),
+                kernel="ses_fused_kernel<float,8,4,false,0,true>", kernel_ms=round(f32["kernel_ms"], 5),
                 bytes_per_launch=algo_bytes, read_reference_GBs=rref["f32"]["GBs"],
                 frac_of_read_reference=round(ach / rref["f32"]["GBs"], 4))
     line = dict(metric=METRIC, value=round(1e3 / f32["ms_per_step"], 1), unit="iters/s", n_gpus=1,
@@ -589,7 +595,7 @@ def main(argv=None):
                 config=dict(workload=w["name"], n=w["n"], d=w["d"], storage="f32",
                             points="N(0,I), 1% rows x5, seed 0", problem="SES"),
                 roofline=roof, cpu_baseline=cpu)
-    kname = dict(bf16="ses_fused_kernel<uint16_t,8,8,false,0>", fp8="ses_fused_kernel<uint8_t,8,8,false,0>")
+    kname = dict(bf16="ses_fused_kernel<uint16_t,8,4,false,0,true>", fp8="ses_fused_kernel<uint8_t,8,4,false,0,true>")
     for k, nb in narrow.items():
         r = res[k]
         b_ach = nb / (r["kernel_ms"] * 1e-3) / 1e9

@@ -478,9 +478,10 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
     if (hipMemcpy(l.tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
       return fail(SCP_MWU_E_HIP, "tile upload");
   }
-  // a k-way batch: 2 .. 4 instances over the same rows share each load
-  // (SCPMWU_KWAY_SHARED=0 keeps one pass per instance, for comparison)
-  bool same = m >= 2 && m <= 4;
+  // a k-way batch: 2 or 3 instances over the same rows with d <= 128 share
+  // each load (the per-test work makes a shared pass of four tests slower
+  // than four passes; SCPMWU_KWAY_SHARED=0 keeps one pass per instance)
+  bool same = m >= 2 && m <= 3 && b->inst[0].d <= kG * 8;
   if (const char *ke = getenv("SCPMWU_KWAY_SHARED"))
     if (ke[0] == '0') same = false;
   for (int k = 1; k < m && same; ++k)

@@ -46,7 +46,6 @@ hipError_t launch_kway_v(int ks, int grid, const PassArgs *args, hipStream_t s) 
   switch (ks) {
     case 2: hipLaunchKernelGGL((ses_kway_batch_kernel<T, EPL, VEC, 2>), dim3(grid), dim3(kPassBlock), 0, s, args); break;
     case 3: hipLaunchKernelGGL((ses_kway_batch_kernel<T, EPL, VEC, 3>), dim3(grid), dim3(kPassBlock), 0, s, args); break;
-    case 4: hipLaunchKernelGGL((ses_kway_batch_kernel<T, EPL, VEC, 4>), dim3(grid), dim3(kPassBlock), 0, s, args); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -72,8 +71,6 @@ hipError_t launch_kway_batch_typed(int epl, int vec, int ks, int grid, const Pas
     case 2: return launch_kway_e<T, 2>(vec, ks, grid, args, s);
     case 4: return launch_kway_e<T, 4>(vec, ks, grid, args, s);
     case 8: return launch_kway_e<T, 8>(vec, ks, grid, args, s);
-    case 16: return launch_kway_e<T, 16>(vec, ks, grid, args, s);
-    case 32: return launch_kway_e<T, 32>(vec, ks, grid, args, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -657,6 +657,13 @@ __global__ __launch_bounds__(kBlk) void final_kernel(Buffers b, double gv) {
   }
 }
 
+// zero fill by a kernel (not a memset node, which a caller's graph capture
+// would record)
+__global__ __launch_bounds__(kBlk) void zero_kernel(double *dst, int64_t count) {
+  for (int64_t k = (int64_t)blockIdx.x * kBlk + threadIdx.x; k < count; k += (int64_t)gridDim.x * kBlk)
+    dst[k] = 0.0;
+}
+
 __global__ __launch_bounds__(kBlk) void round_kernel(const double *src, float *dst, int64_t count) {
   for (int64_t k = (int64_t)blockIdx.x * kBlk + threadIdx.x; k < count; k += (int64_t)gridDim.x * kBlk)
     dst[k] = (float)src[k];
@@ -666,10 +673,7 @@ template <typename P, int PER, bool ROWS, bool V4 = false>
 hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
   const int G = b.grid;
   const int64_t T = b.T;
-  if (b.grad) {
-    hipError_t e = hipMemsetAsync(b.gacc, 0, (size_t)b.n * b.d * sizeof(double), s);
-    if (e != hipSuccess) return e;
-  }
+  if (b.grad) zero_kernel<<<G, kBlk, 0, s>>>(b.gacc, b.n * b.d);
   init_kernel<P><<<1, kBlk, 0, s>>>(b);
   far_pass<P, ROWS ? 1 : PER><<<G, kBlk, 0, s>>>(b, b.ubar, b.v1);
   far_final<<<1, kW, 0, s>>>(b, 1);

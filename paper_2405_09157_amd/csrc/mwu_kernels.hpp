@@ -240,13 +240,12 @@ struct Batch<uint8_t, SB, EPL, true> {
 };
 
 // Batch shape of the streaming pass (pass_steps): SB load steps of 4 rows.
-// k-way slots keep KS sets of d accumulators in registers; from KS = 4 on
-// the batch takes half the load steps (four sets at full size spill).
+// k-way slots (KS <= 3) keep KS sets of accumulators in registers beside the
+// batch.
 template <typename T, int EPL, int PROB, int PFM, int KS = 1>
 struct PassShape {
   static constexpr bool PACK = pass_packed((int)sizeof(T), EPL, PROB);
-  static constexpr int SB0 = pass_steps((int)sizeof(T), EPL, PROB, PFM);
-  static constexpr int SB = KS >= 4 && SB0 > 1 ? SB0 / 2 : SB0;
+  static constexpr int SB = pass_steps((int)sizeof(T), EPL, PROB, PFM);
   static constexpr int B = SB * kRowsPerStep;
   static_assert(B <= kWave, "the per-row phase holds one row per lane");
   using Regs = Batch<T, SB, EPL, PACK>;
@@ -1492,18 +1491,20 @@ __global__ __launch_bounds__(kCombBlock) void epilogue_kernel(PassArgs a, int P,
 constexpr int kFuseMaxD = 128;
 constexpr int kRecInFlight = 32;
 
-// With global sums (g_in != nullptr) the previous pass left one sum in g_in
-// instead of P records: each thread loads one of its columns, the pass adds
-// into g_out, and workgroup 0 clears g_zero (the slot the pass after next
-// adds into, last read by the previous pass) -- three slots in rotation.
-template <typename T, int NT, int DMAX>
+// With global sums (GS) the previous pass left one sum in g_in instead of P
+// records: each thread loads one of its columns, the pass adds into g_out,
+// and workgroup 0 clears g_zero (the slot the pass after next adds into, last
+// read by the previous pass) -- three slots in rotation.  GS is a template
+// parameter so that the global-sum kernel does not hold the record loads'
+// registers across its first batch of rows.
+template <typename T, int NT, int DMAX, bool GS>
 struct FusedPrologue {
   const PassArgs &a;
   int cur, P;
   int64_t rec_stride;
   double *g_in, *g_out, *g_zero;
   EpiLDS<DMAX> &L;
-  double2 rv[kRecInFlight];
+  double2 rv[GS ? 1 : kRecInFlight];
   double gv;           // gmode: a column of the global sum
   double sv, vv, v1v;  // a state word, a vector element, an element of row v1
 
@@ -1515,17 +1516,19 @@ struct FusedPrologue {
     const int d = (int)a.d, tid = threadIdx.x;
     const int pw = rec_width(d), np = npairs(), groups = comb_groups(np);
     const double *rec = a.partials + cur * rec_stride;
-    if (g_in != nullptr) gv = tid < 2 * np ? g_in[tid] : 0.0;
+    if constexpr (GS) gv = tid < 2 * np ? g_in[tid] : 0.0;
     // state, vectors and row v1 into registers (written to LDS in post())
     sv = tid < kStateWords ? reinterpret_cast<const double *>(a.st + cur)[tid] : 0.0;
     vv = tid < kNumVec * d ? a.vec[cur * (int64_t)kNumVec * d + tid] : 0.0;
     v1v = tid < d ? row_value<T>(a, a.v1, tid) : 0.0;
-    if (g_in == nullptr && tid < np * groups) {
-      const int c0 = 2 * (tid % np), g0 = tid / np;
+    if constexpr (!GS) {
+      if (tid < np * groups) {
+        const int c0 = 2 * (tid % np), g0 = tid / np;
 #pragma unroll
-      for (int r = 0; r < kRecInFlight; ++r) {
-        const int b = g0 + r * groups;
-        rv[r] = b < P ? *reinterpret_cast<const double2 *>(rec + (int64_t)b * pw + c0) : make_double2(0.0, 0.0);
+        for (int r = 0; r < kRecInFlight; ++r) {
+          const int b = g0 + r * groups;
+          rv[r] = b < P ? *reinterpret_cast<const double2 *>(rec + (int64_t)b * pw + c0) : make_double2(0.0, 0.0);
+        }
       }
     }
   }
@@ -1540,13 +1543,13 @@ struct FusedPrologue {
     if (tid < kStateWords) reinterpret_cast<double *>(&L.st)[tid] = sv;
     if (tid < kNumVec * d) L.vout[tid] = vv;
     if (tid < d) L.v1[tid] = v1v;
-    if (g_in != nullptr && tid < ncols)
+    if (GS && tid < ncols)
       L.comb[tid] = (tid == dp + 5 || tid == dp + 6) ? from_max_key((unsigned long long)__double_as_longlong(gv)) : gv;
     if (blockIdx.x == 0 && g_zero != nullptr)
       for (int c = tid; c < pw; c += NT) g_zero[c] = 0.0;
     __syncthreads();
-    if (L.st.status == kRunning && L.st.pending && g_in != nullptr) {
-      epilogue_tail<T, kSES, false, NT, DMAX>(a, L);
+    if constexpr (GS) {
+      if (L.st.status == kRunning && L.st.pending) epilogue_tail<T, kSES, false, NT, DMAX>(a, L);
     } else if (L.st.status == kRunning && L.st.pending) {  // uniform: read from LDS
       for (int jp = tid; jp < items; jp += NT) {
         const int j = jp % np, grp = jp / np;
@@ -1556,7 +1559,7 @@ struct FusedPrologue {
         int b = grp;
         if (jp == tid) {  // the item whose loads are in flight
 #pragma unroll
-          for (int r = 0; r < kRecInFlight; ++r) {
+          for (int r = 0; r < (GS ? 1 : kRecInFlight); ++r) {
             if (b < P) {
               acc0 = m0 ? fmax(acc0, rv[r].x) : acc0 + rv[r].x;
               acc1 = m1 ? fmax(acc1, rv[r].y) : acc1 + rv[r].y;
@@ -1584,20 +1587,20 @@ struct FusedPrologue {
     }
     if (blockIdx.x == 0)
       epilogue_store<NT, DMAX>(L, d, L.st.status == kRunning ? 1 : 0, a.st + (1 - cur), a.vec + (1 - cur) * vs);
-    if (g_in != nullptr)
+    if constexpr (GS)
       return PassIn{L.st.status, L.st.kscale * (double)L.st.t, L.st.shift_bound, L.vout + kVecMean * d, g_out, true};
     return PassIn{L.st.status, L.st.kscale * (double)L.st.t, L.st.shift_bound, L.vout + kVecMean * d,
                   a.partials + (1 - cur) * rec_stride, false};
   }
 };
 
-template <typename T, int EPL, int VEC, bool CERT, int PFM>
+template <typename T, int EPL, int VEC, bool CERT, int PFM, bool GS>
 __global__ __launch_bounds__(kPassBlock) __attribute__((amdgpu_waves_per_eu(SCPMWU_PASS_WAVES)))
 void ses_fused_kernel(PassArgs a, int cur, int P, int64_t rec_stride, double *g_in, double *g_out,
                       double *g_zero) {
   static_assert(kG * EPL <= kFuseMaxD, "fused pass: d <= 128");
   __shared__ EpiLDS<kFuseMaxD> L;
-  FusedPrologue<T, kPassBlock, kFuseMaxD> pro{a, cur, P, rec_stride, g_in, g_out, g_zero, L};
+  FusedPrologue<T, kPassBlock, kFuseMaxD, GS> pro{a, cur, P, rec_stride, g_in, g_out, g_zero, L};
   ses_pass_body<T, EPL, VEC, CERT, PFM>(a, (int)blockIdx.x, (int)gridDim.x, pro);
 }
 
@@ -1766,16 +1769,22 @@ hipError_t launch_flush_typed(bool cert, int P, bool gmode, const PassArgs &a, h
   return hipGetLastError();
 }
 
+template <typename T, int EPL, int VEC, int PFM, bool GS>
+hipError_t launch_fused_g(bool cert, int grid, const PassArgs &a, const FusedSlots &f, hipStream_t s) {
+  if (cert)
+    hipLaunchKernelGGL((ses_fused_kernel<T, EPL, VEC, true, PFM, GS>), dim3(grid), dim3(kPassBlock), 0, s, a, f.cur,
+                       grid, f.rec_stride, f.g_in, f.g_out, f.g_zero);
+  else
+    hipLaunchKernelGGL((ses_fused_kernel<T, EPL, VEC, false, PFM, GS>), dim3(grid), dim3(kPassBlock), 0, s, a, f.cur,
+                       grid, f.rec_stride, f.g_in, f.g_out, f.g_zero);
+  return hipGetLastError();
+}
+
 template <typename T, int EPL, int VEC, int PFM>
 hipError_t launch_fused_p(bool cert, int grid, const PassArgs &a, const FusedSlots &f, hipStream_t s) {
   if constexpr (kG * EPL <= kFuseMaxD) {
-    if (cert)
-      hipLaunchKernelGGL((ses_fused_kernel<T, EPL, VEC, true, PFM>), dim3(grid), dim3(kPassBlock), 0, s, a, f.cur, grid,
-                         f.rec_stride, f.g_in, f.g_out, f.g_zero);
-    else
-      hipLaunchKernelGGL((ses_fused_kernel<T, EPL, VEC, false, PFM>), dim3(grid), dim3(kPassBlock), 0, s, a, f.cur,
-                         grid, f.rec_stride, f.g_in, f.g_out, f.g_zero);
-    return hipGetLastError();
+    return f.g_in != nullptr ? launch_fused_g<T, EPL, VEC, PFM, true>(cert, grid, a, f, s)
+                             : launch_fused_g<T, EPL, VEC, PFM, false>(cert, grid, a, f, s);
   } else {
     return hipErrorInvalidValue;
   }

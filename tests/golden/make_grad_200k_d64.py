@@ -14,7 +14,7 @@ Calls only oracle/ and synth/ (test infrastructure):
      the same rows (pi_i (v_i - c) / R from the MWU weights of the last
      iteration, c = ubar_T), for the loose Danskin comparison.
 
-    python tests/golden/make_grad_200k_d64.py     (about 20-40 min on one core)
+    python tests/golden/make_grad_200k_d64.py     (about 1.5 h on one core)
 """
 import json
 import math
@@ -41,15 +41,13 @@ def main():
     print(f"solve: radius {alpha:.12g} lower {sol.lower:.12g} tests {len(sol.steps)} iters {sol.iters} "
           f"({time.time() - t0:.0f} s)", flush=True)
     T = 2000
-    R, G = ses_grad.radius_grad(V, alpha, T)
+    fw = ses_grad.forward(V, alpha, T)
+    R, G = ses_grad.radius_grad(V, alpha, T, fw=fw)
     print(f"grad: R {R:.12g} ({time.time() - t0:.0f} s)", flush=True)
-    P = ses.setup(V)
+    P = fw.P
+    eta = fw.eta
     # the final mean and the weights of iteration T + 1 (the dual weights pi)
-    S = np.zeros(V.shape[1])
-    eta = math.sqrt(math.log(P.r) / T)
-    for t in range(1, T + 1):
-        S = ses.step(P, S, t - 1, alpha, eta)["S"]
-    c = S / T
+    c = fw.S[T] / T
     W, s, _ = ses.hyperplane(P, c, alpha, T, eta)
     pi = np.zeros(V.shape[0])
     pi[P.F] = s / np.sum(s)                    # trace weights of the blocks, normalised
