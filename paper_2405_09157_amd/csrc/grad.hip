@@ -14,12 +14,15 @@
 //   v1 collects lambda (u(t) = v1 + ...); D collects -kappa_t/D sum_i (da_i/dkappa)(delta_i . lambda_W)
 // and finally R's own term at its active row and D's at v1 and its far row.
 //
-// Lanes run over the columns of a row (d <= 512: PER <= 8 columns per lane);
-// each wave takes rows kRB at a time (all loads issued before the arithmetic)
-// and reduces a row's sums with a butterfly.  All arithmetic is binary64 on the
-// stored values (FP32, FP64 or BF16 points, widened exactly); the
-// gradient is accumulated in a binary64 workspace and rounded once to the
-// caller's FP32 buffer.
+// Lanes run over the columns of a row (16 lanes per row for d <= 64, else 64
+// lanes with PER <= 8 columns each); each wave takes rows kRB at a time (all
+// loads issued before the arithmetic) and reduces a row's sums with a
+// butterfly.  The per-iteration passes run one workgroup per CU, so that
+// their one-workgroup epilogues sum one partial row per CU; the per-segment
+// contraction of the rows' coefficients is a binary64 MFMA product.  All
+// arithmetic is binary64 on the stored values (FP32, FP64 or BF16 points,
+// widened exactly); the gradient is accumulated in a binary64 workspace and
+// rounded once to the caller's FP32 buffer.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -33,6 +36,10 @@ namespace grad {
 constexpr int kBlk = 256, kW = 64, kNW = kBlk / kW, kMaxPer = 8, kRB = 4;
 constexpr int kEpi = 1024;  // threads of the one-workgroup epilogues
 constexpr int kMaxCols = kMaxPer * kW;
+// The per-iteration passes run one workgroup per CU (grid `pgrid`), so that
+// their epilogues sum one partial row per CU: 16 waves for the forward pass,
+// 12 for the reverse pass (whose registers allow three waves per SIMD).
+constexpr int kFwdBlk = 1024, kBwdBlk = 768;
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -98,8 +105,10 @@ __device__ void reduce_parts(const double *part, int G, int ncol, double *dst, d
 
 // ---- forward iteration t = t0 + 1 + slot: partial sums of W_t
 template <typename P, int PER>
-__global__ __launch_bounds__(kBlk) void fwd_pass(Buffers b, int slot) {
-  __shared__ double red[kNW][kMaxCols];
+__global__ __launch_bounds__(kFwdBlk) void fwd_pass(Buffers b, int slot) {
+  constexpr int RB = PER >= 8 ? 2 : kRB;  // rows in flight per wave (registers)
+  constexpr int NW = kFwdBlk / kW;
+  __shared__ double red[NW][kMaxCols];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
   const double *c = b.tc + (int64_t)slot * d;
   const double kap = b.ts[slot * 4 + 0], sh = b.ts[slot * 4 + 1];
@@ -111,11 +120,11 @@ __global__ __launch_bounds__(kBlk) void fwd_pass(Buffers b, int slot) {
     acc[j] = 0.0;
   }
   if (kap > 0.0) {
-    const int64_t stride = (int64_t)gridDim.x * kNW;
-    for (int64_t base = (int64_t)blockIdx.x * kNW + w; base < b.n; base += kRB * stride) {
-      double x[kRB][PER];
+    const int64_t stride = (int64_t)gridDim.x * NW;
+    for (int64_t base = (int64_t)blockIdx.x * NW + w; base < b.n; base += RB * stride) {
+      double x[RB][PER];
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
+      for (int r = 0; r < RB; ++r) {
         const int64_t i = base + r * stride;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
@@ -124,7 +133,7 @@ __global__ __launch_bounds__(kBlk) void fwd_pass(Buffers b, int slot) {
         }
       }
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
+      for (int r = 0; r < RB; ++r) {
         const int64_t i = base + r * stride;
         if (i >= b.n || i == b.v1) continue;
         double dl[PER], s2 = 0.0;
@@ -146,8 +155,13 @@ __global__ __launch_bounds__(kBlk) void fwd_pass(Buffers b, int slot) {
   for (int j = 0; j < PER; ++j) red[w][lane + j * kW] = acc[j];
   __syncthreads();
   double *p = b.part + (int64_t)blockIdx.x * (d + 2);
-  for (int col = threadIdx.x; col < d + 2; col += kBlk)
-    p[col] = col < d ? (red[0][col] + red[1][col]) + (red[2][col] + red[3][col]) : 0.0;
+  for (int col = threadIdx.x; col < d + 2; col += kFwdBlk) {
+    double v = 0.0;
+    if (col < d)
+#pragma unroll
+      for (int q = 0; q < NW; ++q) v += red[q][col];
+    p[col] = v;
+  }
 }
 
 // ---- forward epilogue of iteration t: u(t), S_t, the tape of slot and the
@@ -156,7 +170,7 @@ template <typename P>
 __global__ __launch_bounds__(kEpi) void fwd_epi(Buffers b, int slot, int64_t t, int write_ck) {
   __shared__ double s_W[kMaxCols + 2], tmp[kEpi], s_r[kEpi / kW];
   const int tid = threadIdx.x, d = (int)b.d;
-  reduce_parts<kEpi>(b.part, b.grid, d + 2, s_W, tmp);
+  reduce_parts<kEpi>(b.part, b.pgrid, d + 2, s_W, tmp);
   double p = 0.0;
   for (int col = tid; col < d; col += kEpi) p += s_W[col] * s_W[col];
   const double nW = sqrt(bsum<kEpi>(p, s_r));
@@ -209,14 +223,15 @@ __global__ __launch_bounds__(kBlk) void seg_init(Buffers b, int64_t t0) {
 
 // lambda_W of slot from lambda, computed by every workgroup of the reverse
 // pass; workgroup 0 also stores it for the epilogue.
+template <int NT>
 __device__ __forceinline__ void lambda_w(const Buffers &b, int slot, double *s_lw, double *s_r) {
   const int tid = threadIdx.x, d = (int)b.d;
   const double *Wh = b.tw + (int64_t)slot * d;
   const double nW = b.ts[slot * 4 + 2];
   double p = 0.0;
-  for (int col = tid; col < d; col += kBlk) p += Wh[col] * b.lam[col];
-  p = bsum<kBlk>(p, s_r);
-  for (int col = tid; col < d; col += kBlk) {
+  for (int col = tid; col < d; col += NT) p += Wh[col] * b.lam[col];
+  p = bsum<NT>(p, s_r);
+  for (int col = tid; col < d; col += NT) {
     const double v = nW > 0.0 ? b.alpha * (b.lam[col] - Wh[col] * p) / nW : 0.0;
     s_lw[col] = v;
     if (blockIdx.x == 0) b.lw[(int64_t)slot * d + col] = v;
@@ -226,11 +241,13 @@ __device__ __forceinline__ void lambda_w(const Buffers &b, int slot, double *s_l
 
 // ---- reverse iteration t = t0 + 1 + slot (t >= 2)
 template <typename P, int PER>
-__global__ __launch_bounds__(kBlk) void bwd_pass(Buffers b, int slot) {
-  __shared__ double red[kNW][kMaxCols];
-  __shared__ double s_lw[kMaxCols], s_r[kNW], s_a[kNW], s_k[kNW];
+__global__ __launch_bounds__(kBwdBlk) void bwd_pass(Buffers b, int slot) {
+  constexpr int RB = PER >= 8 ? 2 : kRB;  // rows in flight per wave (registers)
+  constexpr int NW = kBwdBlk / kW;
+  __shared__ double red[NW][kMaxCols];
+  __shared__ double s_lw[kMaxCols], s_r[NW], s_a[NW], s_k[NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
-  lambda_w(b, slot, s_lw, s_r);
+  lambda_w<kBwdBlk>(b, slot, s_lw, s_r);
   const double *c = b.tc + (int64_t)slot * d;
   const double kap = b.ts[slot * 4 + 0], sh = b.ts[slot * 4 + 1], nW = b.ts[slot * 4 + 2];
   double cr[PER], lw[PER], accB[PER];
@@ -245,11 +262,11 @@ __global__ __launch_bounds__(kBlk) void bwd_pass(Buffers b, int slot) {
   const bool live = kap > 0.0 && nW > 0.0;
   double *sa = b.sa + (int64_t)slot * b.n, *sb = b.sb + (int64_t)slot * b.n;
   {
-    const int64_t stride = (int64_t)gridDim.x * kNW;
-    for (int64_t base = (int64_t)blockIdx.x * kNW + w; base < b.n; base += kRB * stride) {
-      double x[kRB][PER];
+    const int64_t stride = (int64_t)gridDim.x * NW;
+    for (int64_t base = (int64_t)blockIdx.x * NW + w; base < b.n; base += RB * stride) {
+      double x[RB][PER];
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
+      for (int r = 0; r < RB; ++r) {
         const int64_t i = base + r * stride;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
@@ -258,7 +275,7 @@ __global__ __launch_bounds__(kBlk) void bwd_pass(Buffers b, int slot) {
         }
       }
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
+      for (int r = 0; r < RB; ++r) {
         const int64_t i = base + r * stride;
         if (i >= b.n) continue;
         double dl[PER], s2 = 0.0, q = 0.0;
@@ -300,14 +317,12 @@ __global__ __launch_bounds__(kBlk) void bwd_pass(Buffers b, int slot) {
   }
   __syncthreads();
   double *p = b.part + (int64_t)blockIdx.x * (d + 2);
-  for (int col = threadIdx.x; col < d + 2; col += kBlk) {
-    double v;
-    if (col < d)
-      v = (red[0][col] + red[1][col]) + (red[2][col] + red[3][col]);
-    else if (col == d)
-      v = (s_a[0] + s_a[1]) + (s_a[2] + s_a[3]);
-    else
-      v = (s_k[0] + s_k[1]) + (s_k[2] + s_k[3]);
+  for (int col = threadIdx.x; col < d + 2; col += kBwdBlk) {
+    const double *src = col < d ? &red[0][col] : (col == d ? s_a : s_k);
+    const int step = col < d ? kMaxCols : 1;
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) v += src[q * step];
     p[col] = v;
   }
 }
@@ -349,9 +364,17 @@ __device__ __forceinline__ void load_cols(const Buffers &b, int64_t i, int cl, c
   }
 }
 
+// A wave's four row groups (lanes cl, cl + 16, cl + 32, cl + 48) summed in a
+// fixed order; lane cl of group 0 holds the result.
+__device__ __forceinline__ double rowgroup_sum(double v) {
+  v += __shfl_xor(v, 16, kW);
+  return v + __shfl_xor(v, 32, kW);
+}
+
 template <typename P, int CPL, bool V4>
-__global__ __launch_bounds__(kBlk) void fwd_rows(Buffers b, int slot) {
-  __shared__ double red[kNW * kRPW][kLPR * CPL];
+__global__ __launch_bounds__(kFwdBlk) void fwd_rows(Buffers b, int slot) {
+  constexpr int NW = kFwdBlk / kW;
+  __shared__ double red[NW][kLPR * CPL];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
   const int rg = lane >> 4, cl = lane & 15;
   const double *c = b.tc + (int64_t)slot * d;
@@ -364,8 +387,8 @@ __global__ __launch_bounds__(kBlk) void fwd_rows(Buffers b, int slot) {
     acc[j] = 0.0;
   }
   if (kap > 0.0) {
-    const int64_t wstride = (int64_t)gridDim.x * kNW * kRPW;
-    for (int64_t wb = ((int64_t)blockIdx.x * kNW + w) * kRPW; wb < b.n; wb += kRB * wstride) {
+    const int64_t wstride = (int64_t)gridDim.x * NW * kRPW;
+    for (int64_t wb = ((int64_t)blockIdx.x * NW + w) * kRPW; wb < b.n; wb += kRB * wstride) {
       double x[kRB][CPL];
 #pragma unroll
       for (int r = 0; r < kRB; ++r) load_cols<P, CPL, V4>(b, wb + r * wstride + rg, cl, cr, x[r]);
@@ -388,25 +411,29 @@ __global__ __launch_bounds__(kBlk) void fwd_rows(Buffers b, int slot) {
     }
   }
 #pragma unroll
-  for (int j = 0; j < CPL; ++j) red[w * kRPW + rg][cl * CPL + j] = acc[j];
+  for (int j = 0; j < CPL; ++j) {
+    const double v = rowgroup_sum(acc[j]);
+    if (rg == 0) red[w][cl * CPL + j] = v;
+  }
   __syncthreads();
   double *p = b.part + (int64_t)blockIdx.x * (d + 2);
-  for (int col = threadIdx.x; col < d + 2; col += kBlk) {
+  for (int col = threadIdx.x; col < d + 2; col += kFwdBlk) {
     double v = 0.0;
     if (col < d)
 #pragma unroll
-      for (int q = 0; q < kNW * kRPW; ++q) v += red[q][col];
+      for (int q = 0; q < NW; ++q) v += red[q][col];
     p[col] = v;
   }
 }
 
 template <typename P, int CPL, bool V4>
-__global__ __launch_bounds__(kBlk) void bwd_rows(Buffers b, int slot) {
-  __shared__ double red[kNW * kRPW][kLPR * CPL];
-  __shared__ double s_lw[kMaxCols], s_r[kNW], s_a[kNW], s_k[kNW];
+__global__ __launch_bounds__(kBwdBlk) void bwd_rows(Buffers b, int slot) {
+  constexpr int NW = kBwdBlk / kW;
+  __shared__ double red[NW][kLPR * CPL];
+  __shared__ double s_lw[kMaxCols], s_r[NW], s_a[NW], s_k[NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
   const int rg = lane >> 4, cl = lane & 15;
-  lambda_w(b, slot, s_lw, s_r);
+  lambda_w<kBwdBlk>(b, slot, s_lw, s_r);
   const double *c = b.tc + (int64_t)slot * d;
   const double kap = b.ts[slot * 4 + 0], sh = b.ts[slot * 4 + 1], nW = b.ts[slot * 4 + 2];
   double cr[CPL], lw[CPL], accB[CPL];
@@ -421,8 +448,8 @@ __global__ __launch_bounds__(kBlk) void bwd_rows(Buffers b, int slot) {
   const bool live = kap > 0.0 && nW > 0.0;
   double *sa = b.sa + (int64_t)slot * b.n, *sb = b.sb + (int64_t)slot * b.n;
   {
-    const int64_t wstride = (int64_t)gridDim.x * kNW * kRPW;
-    for (int64_t wb = ((int64_t)blockIdx.x * kNW + w) * kRPW; wb < b.n; wb += kRB * wstride) {
+    const int64_t wstride = (int64_t)gridDim.x * NW * kRPW;
+    for (int64_t wb = ((int64_t)blockIdx.x * NW + w) * kRPW; wb < b.n; wb += kRB * wstride) {
       double x[kRB][CPL];
 #pragma unroll
       for (int r = 0; r < kRB; ++r) load_cols<P, CPL, V4>(b, wb + r * wstride + rg, cl, cr, x[r]);
@@ -461,7 +488,10 @@ __global__ __launch_bounds__(kBlk) void bwd_rows(Buffers b, int slot) {
     }
   }
 #pragma unroll
-  for (int j = 0; j < CPL; ++j) red[w * kRPW + rg][cl * CPL + j] = accB[j];
+  for (int j = 0; j < CPL; ++j) {
+    const double v = rowgroup_sum(accB[j]);
+    if (rg == 0) red[w][cl * CPL + j] = v;
+  }
   accA = wsum(accA);
   accK = wsum(accK);
   if (lane == 0) {
@@ -470,60 +500,126 @@ __global__ __launch_bounds__(kBlk) void bwd_rows(Buffers b, int slot) {
   }
   __syncthreads();
   double *p = b.part + (int64_t)blockIdx.x * (d + 2);
-  for (int col = threadIdx.x; col < d + 2; col += kBlk) {
+  for (int col = threadIdx.x; col < d + 2; col += kBwdBlk) {
     double v = 0.0;
     if (col < d) {
 #pragma unroll
-      for (int q = 0; q < kNW * kRPW; ++q) v += red[q][col];
-    } else if (col == d) {
-      v = (s_a[0] + s_a[1]) + (s_a[2] + s_a[3]);
+      for (int q = 0; q < NW; ++q) v += red[q][col];
     } else {
-      v = (s_k[0] + s_k[1]) + (s_k[2] + s_k[3]);
+      const double *src = col == d ? s_a : s_k;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) v += src[q];
     }
     p[col] = v;
   }
 }
 
-// ---- the rows' share of a walked-back segment, slots [jlo, jhi):
-// grad_i += sum_j a_{j,i} lambda_W(j) + beta_{j,i} (v_i - c(j)).  A workgroup
-// holds the segment's lambda_W and c for its 64 columns in LDS and stages the
-// coefficients of kCR rows at a time (coalesced loads along the rows); each
-// wave then takes one of those rows at a time, a lane one column.
-constexpr int kCR = 16;
+// ---- the rows' share of a walked-back segment, slots [jlo, jhi), as one
+// product on the binary64 matrix cores.  With m = jhi - jlo slots, for row i
+// and column c
+//   g_ic += sum_j a_{j,i} lambda_W(j)_c - beta_{j,i} c(j)_c + x_ic sum_j beta_{j,i},
+// i.e. the (rows x 2m) matrix [a | -beta] times the (2m x columns) matrix
+// [lambda_W ; c], plus x_ic times the row's beta sum.  A wave takes 16 rows
+// and a 64-column tile as four 16 x 16 tiles of v_mfma_f64_16x16x4 (A
+// operand: lane l holds row l % 16 at k = 4 s + l / 16; B operand: column
+// l % 16 at the same k; result r = 0 .. 3 of lane l is row 4 r + l / 16 of
+// column l % 16).  [lambda_W ; c] of the column tile sits in
+// LDS; each lane loads its own row's coefficients (16 adjacent rows per k).
+constexpr int kMK = 2 * kSegment;  // the longest k extent
+constexpr int kCS = 5;             // k steps whose operands are loaded together
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename P>
-__global__ __launch_bounds__(kBlk) void seg_contract(Buffers b, int jlo, int jhi) {
-  __shared__ double s_l[kSegment][kW], s_c[kSegment][kW];
-  __shared__ double s_a[kSegment][kCR], s_b[kSegment][kCR];
+__global__ __launch_bounds__(kBlk) void seg_contract_mfma(Buffers b, int jlo, int jhi) {
+  __shared__ double s_B[kMK][kW];
+  __shared__ double s_bs[kNW][16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
-  const int col = blockIdx.y * kW + lane;
-  const int nj = jhi - jlo;
-  for (int k = threadIdx.x; k < nj * kW; k += kBlk) {
-    const int j = jlo + k / kW, cc = blockIdx.y * kW + (k % kW);
-    s_l[j][k % kW] = cc < d ? b.lw[(int64_t)j * d + cc] : 0.0;
-    s_c[j][k % kW] = cc < d ? b.tc[(int64_t)j * d + cc] : 0.0;
-  }
-  const int64_t nsteps = (b.n + kCR - 1) / kCR;
-  for (int64_t st = blockIdx.x; st < nsteps; st += gridDim.x) {
-    const int64_t i0 = st * kCR;
-    __syncthreads();  // the previous rows' readers are done
-    for (int k = threadIdx.x; k < nj * kCR; k += kBlk) {
-      const int j = jlo + k / kCR, r = k % kCR;
-      const int64_t i = i0 + r;
-      s_a[j][r] = i < b.n ? b.sa[(int64_t)j * b.n + i] : 0.0;
-      s_b[j][r] = i < b.n ? b.sb[(int64_t)j * b.n + i] : 0.0;
+  const int m = jhi - jlo, K2 = 2 * m, KS = (K2 + 3) / 4;  // k steps of 4
+  const int c0 = blockIdx.y * kW;
+  for (int k = threadIdx.x; k < 4 * KS * kW; k += kBlk) {
+    const int kk = k / kW, cc = c0 + k % kW;
+    double v = 0.0;
+    if (cc < d) {
+      if (kk < m)
+        v = b.lw[(int64_t)(jlo + kk) * d + cc];
+      else if (kk < K2)
+        v = b.tc[(int64_t)(jlo + kk - m) * d + cc];
     }
-    __syncthreads();
-    if (col < d) {
-      for (int r = w; r < kCR; r += kNW) {
-        const int64_t i = i0 + r;
-        if (i >= b.n) break;
-        const double x = xval<P>(b, i, col);
-        double acc = 0.0;
-        for (int j = jlo; j < jhi; ++j) acc += s_a[j][r] * s_l[j][lane] + s_b[j][r] * (x - s_c[j][lane]);
-        b.gacc[i * b.d + col] += acc;
+    s_B[kk][k % kW] = v;
+  }
+  __syncthreads();
+  const int mr = lane & 15, kq = lane >> 4;
+  const int64_t rstride = (int64_t)gridDim.x * kNW * 16;
+  for (int64_t i0 = ((int64_t)blockIdx.x * kNW + w) * 16; i0 < b.n; i0 += rstride) {
+    const int64_t i = i0 + mr;
+    // this lane's A operands (k = 4 st + kq: a_{k,i} for k < m, beta_{k-m,i}
+    // after), kCS k steps at a time, the next group's loads issued before
+    // this group's products
+    const bool live = i < b.n;
+    const int64_t ia = (int64_t)(jlo + kq) * b.n + (live ? i : 0), ib = ia - (int64_t)m * b.n;
+    const int64_t step = 4 * b.n;
+    double bs = 0.0;
+    auto load_group = [&](int s0, double *av) {
+#pragma unroll
+      for (int u = 0; u < kCS; ++u) {
+        const int st = s0 + u, k = 4 * st + kq;
+        double a = 0.0;
+        if (st < KS && live) {
+          if (k < m) {
+            a = b.sa[ia + st * step];
+          } else if (k < K2) {
+            const double be = b.sb[ib + st * step];
+            a = -be;
+            bs += be;
+          }
+        }
+        av[u] = a;
+      }
+    };
+    f64x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double av[kCS], an[kCS];
+    load_group(0, av);
+    for (int s0 = 0; s0 < KS; s0 += kCS) {
+      if (s0 + kCS < KS) load_group(s0 + kCS, an);  // uniform
+#pragma unroll
+      for (int u = 0; u < kCS; ++u) {
+        if (s0 + u < KS) {  // uniform
+          const int k = 4 * (s0 + u) + kq;
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], s_B[k][16 * t + mr], acc[t], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kCS; ++u) av[u] = an[u];
+    }
+    // the row's beta sum over its four k groups, then handed to the lanes
+    // that hold the row's results
+    bs += __shfl_xor(bs, 16, kW);
+    bs += __shfl_xor(bs, 32, kW);
+    if (kq == 0) s_bs[w][mr] = bs;
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = i0 + 4 * r + kq;
+      const double brow = s_bs[w][4 * r + kq];
+      if (row < b.n) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int col = c0 + 16 * t + mr;
+          if (col < d) b.gacc[row * b.d + col] += acc[t][r] + xval<P>(b, row, col) * brow;
+        }
       }
     }
+    wave_lds_sync();  // s_bs is rewritten by the next rows
   }
 }
 
@@ -531,7 +627,7 @@ __global__ __launch_bounds__(kBlk) void seg_contract(Buffers b, int jlo, int jhi
 __global__ __launch_bounds__(kEpi) void bwd_epi(Buffers b, int slot, int64_t t) {
   __shared__ double s_P[kMaxCols + 2], tmp[kEpi];
   const int tid = threadIdx.x, d = (int)b.d;
-  if (t >= 2) reduce_parts<kEpi>(b.part, b.grid, d + 2, s_P, tmp);
+  if (t >= 2) reduce_parts<kEpi>(b.part, b.pgrid, d + 2, s_P, tmp);
   for (int col = tid; col < d; col += kEpi) {
     const double lam = b.lam[col];
     b.gv1[col] += lam;
@@ -671,7 +767,7 @@ __global__ __launch_bounds__(kBlk) void round_kernel(const double *src, float *d
 
 template <typename P, int PER, bool ROWS, bool V4 = false>
 hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
-  const int G = b.grid;
+  const int G = b.grid, PG = b.pgrid;
   const int64_t T = b.T;
   if (b.grad) zero_kernel<<<G, kBlk, 0, s>>>(b.gacc, b.n * b.d);
   init_kernel<P><<<1, kBlk, 0, s>>>(b);
@@ -697,9 +793,9 @@ hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
     for (int64_t t = t0 + 1; t <= t1; ++t) {
       const int slot = (int)(t - t0 - 1);
       if constexpr (ROWS)
-        fwd_rows<P, PER, V4><<<G, kBlk, 0, s>>>(bx, slot);
+        fwd_rows<P, PER, V4><<<PG, kFwdBlk, 0, s>>>(bx, slot);
       else
-        fwd_pass<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
+        fwd_pass<P, PER><<<PG, kFwdBlk, 0, s>>>(bx, slot);
       fwd_epi<P><<<1, kEpi, 0, s>>>(bx, slot, t, 1);
     }
   }
@@ -717,9 +813,9 @@ hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
       for (int64_t t = t0 + 1; t <= t1; ++t) {
         const int slot = (int)(t - t0 - 1);
         if constexpr (ROWS)
-          fwd_rows<P, PER, V4><<<G, kBlk, 0, s>>>(bx, slot);
+          fwd_rows<P, PER, V4><<<PG, kFwdBlk, 0, s>>>(bx, slot);
         else
-          fwd_pass<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
+          fwd_pass<P, PER><<<PG, kFwdBlk, 0, s>>>(bx, slot);
         fwd_epi<P><<<1, kEpi, 0, s>>>(bx, slot, t, 0);
       }
     }
@@ -727,15 +823,15 @@ hipError_t run_typed(const Buffers &b, double gv, hipStream_t s) {
       const int slot = (int)(t - t0 - 1);
       if (t >= 2) {
         if constexpr (ROWS)
-          bwd_rows<P, PER, V4><<<G, kBlk, 0, s>>>(bx, slot);
+          bwd_rows<P, PER, V4><<<PG, kBwdBlk, 0, s>>>(bx, slot);
         else
-          bwd_pass<P, PER><<<G, kBlk, 0, s>>>(bx, slot);
+          bwd_pass<P, PER><<<PG, kBwdBlk, 0, s>>>(bx, slot);
       }
       bwd_epi<<<1, kEpi, 0, s>>>(bx, slot, t);
     }
     const int jlo = t0 == 0 ? 1 : 0, jhi = (int)(t1 - t0);  // slots of t >= 2
     if (jhi > jlo)
-      seg_contract<P><<<dim3(G, (unsigned)((b.d + kW - 1) / kW)), kBlk, 0, s>>>(bx, jlo, jhi);
+      seg_contract_mfma<P><<<dim3(G, (unsigned)((b.d + kW - 1) / kW)), kBlk, 0, s>>>(bx, jlo, jhi);
   }
   final_kernel<P><<<1, kBlk, 0, s>>>(b, gv);
   round_kernel<<<G, kBlk, 0, s>>>(b.gacc, b.grad, b.n * b.d);
@@ -759,7 +855,8 @@ hipError_t run_per(const Buffers &b, double gv, hipStream_t s) {
 }
 
 hipError_t run_backward(const Buffers &b, double gv, hipStream_t s) {
-  if (b.d < 1 || b.d > kMaxCols || b.n < 2 || b.T < 1 || b.grid < 1 || b.seg < 1 || b.seg > kSegment)
+  if (b.d < 1 || b.d > kMaxCols || b.n < 2 || b.T < 1 || b.grid < 1 || b.pgrid < 1 || b.pgrid > b.grid || b.seg < 1 ||
+      b.seg > kSegment)
     return hipErrorInvalidValue;
   if (b.dtype == 1) return run_per<double>(b, gv, s);
   if (b.dtype == 2) return run_per<uint16_t>(b, gv, s);

@@ -26,7 +26,8 @@ struct Buffers {
   int dtype;         // 0: float points, 1: double points, 2: BF16 points
   const void *X;
   double alpha, eta;     // kappa_t = eta (t - 1) / (3D), D recomputed on the device
-  int grid;
+  int grid;          // workgroups of the 256-thread kernels
+  int pgrid;         // workgroups of the per-iteration passes (<= grid)
   int seg;           // segment length K (1 .. kSegment)
   int full;          // 1: the tape holds all T iterations (no recomputation)
   // running sum and its checkpoints S_{j K}
@@ -34,7 +35,7 @@ struct Buffers {
   // tape of one segment (K slots; all T with `full`), slot j = iteration t0 + 1 + j:
   //   tc: c_t (one slot more), tw: W_t/||W_t||, ts: {kappa_t, s_t, ||W_t||, 0} (one slot more)
   double *tc, *tw, *ts;
-  double *part;      // grid x (d + 2) per-workgroup partial sums
+  double *part;      // per-workgroup partial sums: pgrid x (d + 2), or 2 grid (far rows)
   double *lam;       // adjoint of S_t
   double *lw;        // lambda_W of each slot of the segment (K x d)
   double *sa, *sb;   // a_i and beta_i of each slot and row (K x n each)

@@ -384,8 +384,10 @@ int scpmwu::backward_with_workspace(scp_mwu_ctx *c, double grad_value, float *gr
   b.X = c->X;
   b.alpha = c->alpha;
   b.eta = c->eta;
-  // four workgroups per CU, at least 64 rows per workgroup
+  // four 256-thread workgroups per CU, at least 64 rows per workgroup; the
+  // per-iteration passes one workgroup per CU
   b.grid = (int)std::max<int64_t>(1, std::min<int64_t>(4 * (int64_t)std::max(cus, 1), (c->n + 63) / 64));
+  b.pgrid = (int)std::max<int64_t>(1, std::min<int64_t>(std::max(cus, 1), (c->n + 63) / 64));
   const bool full = checkpoint_every == 0;
   b.full = full ? 1 : 0;
   b.seg = full ? grad::kSegment : checkpoint_every;

@@ -1,6 +1,8 @@
-"""Writes grad_200k_d64_T2000.json: the FP64 oracle's reference for the
-gradient workload (n = 200,000 points N(0, I) in d = 64, FP32, seed 0;
-T = 2000 fixed-alpha iterations; alpha held at the oracle's solved radius).
+"""Writes grad_200k_d64_T<T>.json (T = 2000 by default): the FP64 oracle's
+reference for the gradient workload (n = 200,000 points N(0, I) in d = 64,
+FP32, seed 0; T fixed-alpha iterations; alpha held at the oracle's solved
+radius).  With T other than 2000 the solved radius is read from
+grad_200k_d64_T2000.json (written by this script) when that file exists.
 
 Calls only oracle/ and synth/ (test infrastructure):
   1. the radius R* of the oracle's adaptive search, eps = 1e-2 (Section 3
@@ -14,7 +16,9 @@ Calls only oracle/ and synth/ (test infrastructure):
      the same rows (pi_i (v_i - c) / R from the MWU weights of the last
      iteration, c = ubar_T), for the loose Danskin comparison.
 
-    python tests/golden/make_grad_200k_d64.py     (about 1.5 h on one core)
+    python tests/golden/make_grad_200k_d64.py [T]   (T = 2000: about 1.5 h on
+                                                     one core; T = 500 with the
+                                                     stored radius: about 10 min)
 """
 import json
 import math
@@ -30,17 +34,24 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 from oracle import ses, ses_grad  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "grad_200k_d64_T2000.json")
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def main():
+def main(T=2000):
     t0 = time.time()
+    out_path = os.path.join(HERE, f"grad_200k_d64_T{T}.json")
+    ref_path = os.path.join(HERE, "grad_200k_d64_T2000.json")
     V = synth.ses_gaussian_outliers(200_000, 64, 0, frac=0.0, dtype=np.float32).astype(np.float64)
-    sol = ses.solve(V, eps=1e-2)
-    alpha = float(sol.radius)
-    print(f"solve: radius {alpha:.12g} lower {sol.lower:.12g} tests {len(sol.steps)} iters {sol.iters} "
-          f"({time.time() - t0:.0f} s)", flush=True)
-    T = 2000
+    if T != 2000 and os.path.exists(ref_path):
+        with open(ref_path) as f:
+            ref = json.load(f)
+        alpha, lower = float(ref["alpha"]), float(ref["solve_lower"])
+        print(f"solved radius from {ref_path}: {alpha:.12g}", flush=True)
+    else:
+        sol = ses.solve(V, eps=1e-2)
+        alpha, lower = float(sol.radius), float(sol.lower)
+        print(f"solve: radius {alpha:.12g} lower {lower:.12g} tests {len(sol.steps)} iters {sol.iters} "
+              f"({time.time() - t0:.0f} s)", flush=True)
     fw = ses_grad.forward(V, alpha, T)
     R, G = ses_grad.radius_grad(V, alpha, T, fw=fw)
     print(f"grad: R {R:.12g} ({time.time() - t0:.0f} s)", flush=True)
@@ -61,7 +72,7 @@ def main():
     out = dict(
         source="FP64 oracle (oracle/ses.py solve, oracle/ses_grad.py radius_grad); "
                "written by tests/golden/make_grad_200k_d64.py",
-        n=200_000, d=64, seed=0, T=T, eps_solve=1e-2, alpha=alpha, solve_lower=float(sol.lower),
+        n=200_000, d=64, seed=0, T=T, eps_solve=1e-2, alpha=alpha, solve_lower=lower,
         R=float(R), istar=istar, jstar=jstar, rows=rows,
         grad_rows=G[rows].tolist(), max_abs_grad=float(np.abs(G).max()),
         dir_seed=1, dir_deriv=float(np.sum(G * z)),
@@ -69,10 +80,10 @@ def main():
         danskin_rows=danskin.tolist(), pi_top=float(np.max(pi)),
         danskin_cos=float(np.sum(G[rows] * danskin) / (np.linalg.norm(G[rows]) * np.linalg.norm(danskin))),
     )
-    with open(OUT, "w") as f:
+    with open(out_path, "w") as f:
         json.dump(out, f)
-    print(f"wrote {OUT} ({time.time() - t0:.0f} s)", flush=True)
+    print(f"wrote {out_path} ({time.time() - t0:.0f} s)", flush=True)
 
 
 if __name__ == "__main__":
-    main()
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 2000)

