@@ -96,6 +96,9 @@ struct Layout {
   int rows, epl, vec;
   BatchTile *tiles;  // device
   int ntiles;
+  std::vector<BatchTile> htiles;  // host copy of tiles
+  BatchTile *act = nullptr;       // device: the tiles of the instances listed as running
+  int nact = 0;
 };
 
 }  // namespace
@@ -124,6 +127,15 @@ struct scp_mwu_batch {
   double *h_vec = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool any_test = false;
+  // the solve's running instances: their tiles (Layout::act) and their
+  // PassArgs and record counts back to back, so that the launches of an
+  // iteration cover only them; rebuilt as instances finish
+  std::vector<PassArgs> h_args;
+  std::vector<int32_t> h_nrec;
+  PassArgs *act_args = nullptr;
+  int32_t *act_nrec = nullptr;
+  int nact = 0;
+  bool use_act = false;
   // 2 .. 4 instances over one point set (the k-way search): one pass loads
   // each batch of rows once for all of them (column layout kw_epl, kw_vec,
   // kw_grid workgroups = every instance's share count)
@@ -144,16 +156,60 @@ struct scp_mwu_batch {
 namespace {
 
 hipError_t pass_launch(scp_mwu_batch *b, const Layout &l, hipStream_t s) {
+  const int nt = b->use_act ? l.nact : l.ntiles;
+  const BatchTile *tl = b->use_act ? l.act : l.tiles;
+  if (nt == 0) return hipSuccess;
   if (l.rows)
-    return b->dtype == kBF16 ? launch_rows_batch_bf16(l.epl, l.vec, l.ntiles, b->args, l.tiles, s)
-                             : launch_rows_batch_f32(l.epl, l.vec, l.ntiles, b->args, l.tiles, s);
-  return b->dtype == kBF16 ? launch_pass_batch_bf16(l.epl, l.vec, l.ntiles, b->args, l.tiles, s)
-                           : launch_pass_batch_f32(l.epl, l.vec, l.ntiles, b->args, l.tiles, s);
+    return b->dtype == kBF16 ? launch_rows_batch_bf16(l.epl, l.vec, nt, b->args, tl, s)
+                             : launch_rows_batch_f32(l.epl, l.vec, nt, b->args, tl, s);
+  return b->dtype == kBF16 ? launch_pass_batch_bf16(l.epl, l.vec, nt, b->args, tl, s)
+                           : launch_pass_batch_f32(l.epl, l.vec, nt, b->args, tl, s);
 }
 
 hipError_t epilogue_launch(scp_mwu_batch *b, hipStream_t s) {
-  return b->dtype == kBF16 ? launch_epilogue_batch_bf16(b->m, b->args, b->nrec, s)
-                           : launch_epilogue_batch_f32(b->m, b->args, b->nrec, s);
+  const int m = b->use_act ? b->nact : b->m;
+  const PassArgs *args = b->use_act ? b->act_args : b->args;
+  const int32_t *nrec = b->use_act ? b->act_nrec : b->nrec;
+  if (m == 0) return hipSuccess;
+  return b->dtype == kBF16 ? launch_epilogue_batch_bf16(m, args, nrec, s)
+                           : launch_epilogue_batch_f32(m, args, nrec, s);
+}
+
+void drop_graph(scp_mwu_batch *b) {
+  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+}
+
+// List the instances marked active as the only running ones: their tiles per
+// layout and their PassArgs / record counts, uploaded once; the captured
+// graph is dropped so that the next chunk is captured with the new counts.
+// An instance left out must stay out of every launch until the next call,
+// so this runs only between chunks and only over the instances that will
+// run (every other instance's state says its test has ended).
+int set_active(scp_mwu_batch *b, bool on) {
+  drop_graph(b);
+  b->use_act = on;
+  if (!on) return SCP_MWU_OK;
+  std::vector<PassArgs> aa;
+  std::vector<int32_t> an;
+  for (int k = 0; k < b->m; ++k)
+    if (b->inst[k].active) {
+      aa.push_back(b->h_args[k]);
+      an.push_back(b->h_nrec[k]);
+    }
+  b->nact = (int)aa.size();
+  if (b->nact && (hipMemcpy(b->act_args, aa.data(), sizeof(PassArgs) * aa.size(), hipMemcpyHostToDevice) != hipSuccess ||
+                  hipMemcpy(b->act_nrec, an.data(), sizeof(int32_t) * an.size(), hipMemcpyHostToDevice) != hipSuccess))
+    return b->fail(SCP_MWU_E_HIP, "running-instance upload");
+  for (Layout &l : b->layouts) {
+    std::vector<BatchTile> t;
+    for (const BatchTile &x : l.htiles)
+      if (b->inst[x.inst].active) t.push_back(x);
+    l.nact = (int)t.size();
+    if (l.nact && hipMemcpy(l.act, t.data(), sizeof(BatchTile) * t.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return b->fail(SCP_MWU_E_HIP, "running-tile upload");
+  }
+  return SCP_MWU_OK;
 }
 
 // The streaming pass of every running instance (one launch per layout, or
@@ -304,7 +360,12 @@ void scp_mwu_batch_destroy(scp_mwu_batch *b) {
   if (!b) return;
   if (b->gexec) hipGraphExecDestroy(b->gexec);
   if (b->cap_stream) hipStreamDestroy(b->cap_stream);
-  for (Layout &l : b->layouts) hipFree(l.tiles);
+  for (Layout &l : b->layouts) {
+    hipFree(l.tiles);
+    hipFree(l.act);
+  }
+  hipFree(b->act_args);
+  hipFree(b->act_nrec);
   hipFree(b->args);
   hipFree(b->st);
   hipFree(b->vec);
@@ -432,6 +493,8 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
       hipMalloc(&b->partials, sizeof(double) * (size_t)rec_total) != hipSuccess ||
       hipMalloc(&b->Dd, sizeof(double) * m) != hipSuccess || hipMalloc(&b->nrec, sizeof(int32_t) * m) != hipSuccess ||
       hipMalloc(&b->list, sizeof(int32_t) * m) != hipSuccess ||
+      hipMalloc(&b->act_args, sizeof(PassArgs) * m) != hipSuccess ||
+      hipMalloc(&b->act_nrec, sizeof(int32_t) * m) != hipSuccess ||
       hipMalloc(&b->params, sizeof(InitParams) * m) != hipSuccess ||
       hipHostMalloc((void **)&b->h_st, sizeof(DevState) * m, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&b->h_list, sizeof(int32_t) * m, hipHostMallocDefault) != hipSuccess ||
@@ -462,6 +525,8 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
   if (hipMemcpy(b->args, hargs.data(), sizeof(PassArgs) * m, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->nrec, hn.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice) != hipSuccess)
     return fail(SCP_MWU_E_HIP, "instance table upload");
+  b->h_args = hargs;
+  b->h_nrec = hn;
   for (auto &kv : groups) {
     // tiles interleaved by share index: share v of every instance of the
     // layout, then share v + 1, ...  Instances over the same rows (the
@@ -473,7 +538,12 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
       for (int k : kv.second)
         if (v < b->inst[k].vg) tiles.push_back(BatchTile{k, v, b->inst[k].vg, 0});
     Layout l{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), nullptr, (int)tiles.size()};
-    if (hipMalloc(&l.tiles, sizeof(BatchTile) * tiles.size()) != hipSuccess) return fail(SCP_MWU_E_NOMEM, "tiles");
+    if (hipMalloc(&l.tiles, sizeof(BatchTile) * tiles.size()) != hipSuccess ||
+        hipMalloc(&l.act, sizeof(BatchTile) * tiles.size()) != hipSuccess) {
+      hipFree(l.tiles);
+      return fail(SCP_MWU_E_NOMEM, "tiles");
+    }
+    l.htiles = tiles;
     b->layouts.push_back(l);
     if (hipMemcpy(l.tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice) != hipSuccess)
       return fail(SCP_MWU_E_HIP, "tile upload");
@@ -642,6 +712,14 @@ int scp_mwu_batch_solve(scp_mwu_batch *b, scp_mwu_result *res, double *y) {
     b->inst[k].active = false;
   }
   if ((rc = b->hip(hipMemsetAsync(b->st, 0xFF, sizeof(DevState) * m, b->stream), "state clear"))) return rc;
+  // as instances finish their searches, the launches shrink to the running
+  // ones (relisted whenever a quarter of the listed instances has finished);
+  // the full lists are restored when the solve returns
+  struct FullLists {
+    scp_mwu_batch *b;
+    ~FullLists() { set_active(b, false); }
+  } full_lists{b};
+  int listed = m;
   while (true) {
     // start the next test of every instance without one
     int count = 0;
@@ -660,9 +738,13 @@ int scp_mwu_batch_solve(scp_mwu_batch *b, scp_mwu_result *res, double *y) {
       ++count;
     }
     if ((rc = start_tests(b, count))) return rc;
-    bool running = false;
-    for (int k = 0; k < m; ++k) running = running || b->inst[k].active;
-    if (!running) break;
+    int nrun = 0;
+    for (int k = 0; k < m; ++k) nrun += b->inst[k].active ? 1 : 0;
+    if (nrun == 0) break;
+    if (4 * nrun <= 3 * listed) {
+      if ((rc = set_active(b, true))) return rc;
+      listed = nrun;
+    }
     if ((rc = run_iters(b, b->chunk))) return rc;
     // finished tests: outcome, best centre
     bool need_vec = false;
