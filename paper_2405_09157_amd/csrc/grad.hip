@@ -47,6 +47,14 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
+// Lanes of one wave exchange values through LDS: a wave's DS instructions
+// run in order, so a compiler barrier is all that is needed.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Sum over the NT threads of one workgroup (every thread gets the result).
 template <int NT>
 __device__ __forceinline__ double bsum(double v, double *s_r) {
@@ -331,6 +339,8 @@ __global__ __launch_bounds__(kBwdBlk) void bwd_pass(Buffers b, int slot) {
 // wave at a time, CPL <= 4 adjacent columns per lane): the row sums take a
 // 4-step butterfly inside the 16 lanes and serve 4 rows at once.
 constexpr int kLPR = 16, kRPW = kW / kLPR;
+constexpr int kRBR = 8;                    // row steps of one wave per loop
+constexpr int kRowsPerLoop = kRBR * kRPW;  // rows of one wave per loop (32)
 
 __device__ __forceinline__ double gsum16(double v) {
 #pragma unroll
@@ -375,6 +385,7 @@ template <typename P, int CPL, bool V4>
 __global__ __launch_bounds__(kFwdBlk) void fwd_rows(Buffers b, int slot) {
   constexpr int NW = kFwdBlk / kW;
   __shared__ double red[NW][kLPR * CPL];
+  __shared__ double s_row[NW][kRowsPerLoop];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
   const int rg = lane >> 4, cl = lane & 15;
   const double *c = b.tc + (int64_t)slot * d;
@@ -388,26 +399,39 @@ __global__ __launch_bounds__(kFwdBlk) void fwd_rows(Buffers b, int slot) {
   }
   if (kap > 0.0) {
     const int64_t wstride = (int64_t)gridDim.x * NW * kRPW;
-    for (int64_t wb = ((int64_t)blockIdx.x * NW + w) * kRPW; wb < b.n; wb += kRB * wstride) {
-      double x[kRB][CPL];
+    for (int64_t wb = ((int64_t)blockIdx.x * NW + w) * kRPW; wb < b.n; wb += kRBR * wstride) {
+      double x[kRBR][CPL];
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) load_cols<P, CPL, V4>(b, wb + r * wstride + rg, cl, cr, x[r]);
+      for (int r = 0; r < kRBR; ++r) load_cols<P, CPL, V4>(b, wb + r * wstride + rg, cl, cr, x[r]);
+      // squared distances of the loop's 32 rows (row r, group rg at r * 4 + rg)
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
-        const int64_t i = wb + r * wstride + rg;
-        double dl[CPL], s2 = 0.0;
+      for (int r = 0; r < kRBR; ++r) {
+        double s2 = 0.0;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
-          dl[j] = x[r][j] - cr[j];
-          s2 += dl[j] * dl[j];
+          const double dl = x[r][j] - cr[j];
+          s2 += dl * dl;
         }
-        const double di = sqrt(gsum16(s2));
+        s2 = gsum16(s2);
+        if (cl == 0) s_row[w][r * kRPW + rg] = s2;
+      }
+      wave_lds_sync();
+      // the cone exponentials: one row per lane (lanes 0 .. 31)
+      if (lane < kRowsPerLoop) {
+        const int64_t i = wb + (lane / kRPW) * wstride + lane % kRPW;
+        const double di = sqrt(s_row[w][lane]);
         const bool valid = i < b.n && i != b.v1 && di > 0.0;
         const double ep = exp(kap * di - sh), em = exp(-kap * di - sh);
-        const double a = valid ? (ep - em) / di : 0.0;
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) acc[j] += a * dl[j];
+        s_row[w][lane] = valid ? (ep - em) / di : 0.0;
       }
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < kRBR; ++r) {
+        const double a = s_row[w][r * kRPW + rg];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) acc[j] += a * (x[r][j] - cr[j]);
+      }
+      wave_lds_sync();
     }
   }
 #pragma unroll
@@ -431,6 +455,7 @@ __global__ __launch_bounds__(kBwdBlk) void bwd_rows(Buffers b, int slot) {
   constexpr int NW = kBwdBlk / kW;
   __shared__ double red[NW][kLPR * CPL];
   __shared__ double s_lw[kMaxCols], s_r[NW], s_a[NW], s_k[NW];
+  __shared__ double s_row[NW][kRowsPerLoop], s_q[NW][kRowsPerLoop];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
   const int rg = lane >> 4, cl = lane & 15;
   lambda_w<kBwdBlk>(b, slot, s_lw, s_r);
@@ -449,42 +474,57 @@ __global__ __launch_bounds__(kBwdBlk) void bwd_rows(Buffers b, int slot) {
   double *sa = b.sa + (int64_t)slot * b.n, *sb = b.sb + (int64_t)slot * b.n;
   {
     const int64_t wstride = (int64_t)gridDim.x * NW * kRPW;
-    for (int64_t wb = ((int64_t)blockIdx.x * NW + w) * kRPW; wb < b.n; wb += kRB * wstride) {
-      double x[kRB][CPL];
+    for (int64_t wb = ((int64_t)blockIdx.x * NW + w) * kRPW; wb < b.n; wb += kRBR * wstride) {
+      double x[kRBR][CPL];
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) load_cols<P, CPL, V4>(b, wb + r * wstride + rg, cl, cr, x[r]);
+      for (int r = 0; r < kRBR; ++r) load_cols<P, CPL, V4>(b, wb + r * wstride + rg, cl, cr, x[r]);
+      // squared distances and projections on lambda_W of the loop's 32 rows
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
-        const int64_t i = wb + r * wstride + rg;
-        double dl[CPL], s2 = 0.0, q = 0.0;
+      for (int r = 0; r < kRBR; ++r) {
+        double s2 = 0.0, q = 0.0;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
-          dl[j] = x[r][j] - cr[j];
-          s2 += dl[j] * dl[j];
-          q += dl[j] * lw[j];
+          const double dl = x[r][j] - cr[j];
+          s2 += dl * dl;
+          q += dl * lw[j];
         }
         s2 = gsum16(s2);
         q = gsum16(q);
-        const double di = sqrt(s2);
+        if (cl == 0) {
+          s_row[w][r * kRPW + rg] = s2;
+          s_q[w][r * kRPW + rg] = q;
+        }
+      }
+      wave_lds_sync();
+      // a_i and beta_i: one row per lane (lanes 0 .. 31); the row's
+      // coefficients are kept for the contraction after the segment
+      if (lane < kRowsPerLoop) {
+        const int64_t i = wb + (lane / kRPW) * wstride + lane % kRPW;
+        const double di = sqrt(s_row[w][lane]), q = s_q[w][lane];
         const bool valid = live && i < b.n && i != b.v1 && di > 0.0;
         double a = 0.0, beta = 0.0;
-        if (valid) {  // a row's 16 lanes agree
+        if (valid) {
           const double ep = exp(kap * di - sh), em = exp(-kap * di - sh);
           a = (ep - em) / di;
           const double a1 = (kap * (ep + em) * di - (ep - em)) / (di * di);
           beta = a1 * q / di;
-#pragma unroll
-          for (int j = 0; j < CPL; ++j) accB[j] += beta * dl[j];
-          if (cl == 0) {
-            accA += a;
-            accK += (ep + em) * q;
-          }
+          accA += a;
+          accK += (ep + em) * q;
         }
-        if (cl == 0 && i < b.n) {  // the row's coefficients, contracted after the segment
+        if (i < b.n) {
           sa[i] = a;
           sb[i] = beta;
         }
+        s_row[w][lane] = beta;
       }
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < kRBR; ++r) {
+        const double beta = s_row[w][r * kRPW + rg];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) accB[j] += beta * (x[r][j] - cr[j]);
+      }
+      wave_lds_sync();
     }
   }
 #pragma unroll
@@ -528,12 +568,6 @@ __global__ __launch_bounds__(kBwdBlk) void bwd_rows(Buffers b, int slot) {
 constexpr int kMK = 2 * kSegment;  // the longest k extent
 constexpr int kCS = 5;             // k steps whose operands are loaded together
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <typename P>
 __global__ __launch_bounds__(kBlk) void seg_contract_mfma(Buffers b, int jlo, int jhi) {
