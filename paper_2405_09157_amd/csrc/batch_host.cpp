@@ -459,16 +459,18 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
     I.n = desc->n[k];
     I.d = desc->d[k];
     I.offset = desc->offset[k];
-    // d <= 16: one lane per row, epl = columns held per lane (2, 4, 8, 16);
-    // otherwise 16 lanes per row with epl columns each
+    // d <= 16: one lane per row, epl = columns held per lane (2, 3, 4, 8, 16;
+    // d = 3 exactly, loaded one value at a time); otherwise 16 lanes per row
+    // with epl columns each
     I.rows = I.d <= 16 ? 1 : 0;
     if (I.rows) {
       I.epl = 2;
       while (I.epl < I.d) I.epl *= 2;
+      if (I.d == 3) I.epl = 3;
     } else {
       while (kG * I.epl < I.d) I.epl *= 2;
     }
-    const int vf = std::min<int>(I.epl, (int)(16 / es));
+    const int vf = I.epl == 3 ? 1 : std::min<int>(I.epl, (int)(16 / es));
     const uintptr_t base = (uintptr_t)b->X + (uintptr_t)(I.offset * es);
     for (int v : {vf, vf >= 4 ? vf / 2 : 1, 1}) {
       if (I.d % v == 0 && base % (uintptr_t)(v * es) == 0) {

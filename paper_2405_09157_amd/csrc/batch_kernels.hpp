@@ -329,6 +329,10 @@ hipError_t launch_rows_batch_typed(int dm, int vec, int ntiles, const PassArgs *
                                    hipStream_t s) {
   switch (dm) {
     case 2: return launch_rows_batch_v<T, 2>(vec, ntiles, args, tiles, s);
+    case 3:  // exactly three columns, one value per load
+      if (vec != 1) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((ses_rows_batch_kernel<T, 3, 1>), dim3(ntiles), dim3(kPassBlock), 0, s, args, tiles);
+      return hipGetLastError();
     case 4: return launch_rows_batch_v<T, 4>(vec, ntiles, args, tiles, s);
     case 8: return launch_rows_batch_v<T, 8>(vec, ntiles, args, tiles, s);
     case 16: return launch_rows_batch_v<T, 16>(vec, ntiles, args, tiles, s);
