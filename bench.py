@@ -147,10 +147,14 @@ def solve_kway(X, k):
 def solve(X, storage):
     """eps = 1e-3 solve with the Section 5 exits and weight certificates (the
     dual lower bound of eq.(ses_qp) from the pass's weights, taken once per
-    graph chunk): wall time, iterations, tests, radius and certified bounds."""
+    graph chunk): wall time, iterations, tests, radius and certified bounds.
+    The partial sums are combined in a fixed order, so that the search path
+    (which rounding decides near a test's decision points) and the figures
+    are the same from run to run."""
     import torch
     import paper_2405_09157_amd as scp
-    m = scp.MWU(X, "ses", eps=1e-3, storage=storage, chunk=64, flags=scp.SCP_MWU_FLAG_CERTIFICATES)
+    m = scp.MWU(X, "ses", eps=1e-3, storage=storage, chunk=64,
+                flags=scp.SCP_MWU_FLAG_CERTIFICATES | scp.SCP_MWU_FLAG_DETERMINISTIC)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = m.solve()

@@ -322,13 +322,19 @@ def solve_kway(V, k: int, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Opt
     the one it spells out; reading K1): each round cuts [L, U] into 2k + 1
     equal parts and runs the k alpha-feasibility tests at
     alpha_i = L + (2i - 1)(U - L)/(2k + 1) with eps_i = (U - L)/((2k + 1) alpha_i),
-    so that (1 + eps_i) alpha_i = L + 2i (U - L)/(2k + 1).  After the round,
-    every separated test raises L to its alpha (a certificate); every other
-    test whose alpha is not below the new L lowers U to its conclusion (f_best
-    when f beat alpha, else L + 2i (U - L)/(2k + 1)); every f seen tightens U and
-    the certified radius.  k = 1 is solve()'s search.  `passes` counts the
-    iterations of the rounds when the k tests advance together (the longest
-    test of each round)."""
+    so that (1 + eps_i) alpha_i = L + 2i (U - L)/(2k + 1).  The tests advance
+    together; in the order in which they end (ties: the lower alpha first), an
+    ended test stops the tests its outcome makes moot: a separated test those
+    below it (their alphas are below a certified lower bound), any other test
+    those above it (their alphas are above the conclusion (1 + eps_i) alpha_i).
+    A stopped test decides nothing.  After the round, every separated test
+    raises L to its alpha (a certificate); every other deciding test whose
+    alpha is not below the new L lowers U to its conclusion (f_best when f
+    beat alpha, else L + 2i (U - L)/(2k + 1)); every deciding test's f tightens
+    U and the certified radius.  k = 1 is solve()'s search.  A stopped test
+    counts the iterations it ran until it was stopped; `passes` counts the
+    iterations of the rounds when the k tests advance together (each round
+    lasts until its last deciding test ends)."""
     P = setup(V, gamma, v1)
     n = P.V.shape[0]
     if t_cap is None:
@@ -360,15 +366,29 @@ def solve_kway(V, k: int, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Opt
             cancel_max = max(cancel_max, r.cancel_max)
             round_.append((alpha, L + 2 * i * (U - L) / g, T, r))
             steps.append((alpha, T, r.outcome, r.t, r.f_best))
-        iters += sum(r.t for _, _, _, r in round_)
-        passes += max(r.t for _, _, _, r in round_)
-        for alpha, concl, T, r in round_:
+        # the moot tests, in the order in which the tests end
+        stop = [None] * k
+        live = set(range(k))
+        for i in sorted(range(k), key=lambda i: (round_[i][3].t, i)):
+            if i not in live:
+                continue
+            live.discard(i)
+            moot = range(i) if round_[i][3].outcome == SEPARATED else range(i + 1, k)
+            for j in moot:
+                if j in live:
+                    live.discard(j)
+                    stop[j] = round_[i][3].t
+        ran = [r.t if stop[i] is None else min(r.t, stop[i]) for i, (_, _, _, r) in enumerate(round_)]
+        iters += sum(ran)
+        passes += max(ran)
+        deciding = [x for i, x in enumerate(round_) if stop[i] is None]
+        for alpha, concl, T, r in deciding:
             if r.f_best < Uc:
                 Uc, center = r.f_best, r.ubar_best.copy()
-        L_new = max([L] + [a for a, _, _, r in round_ if r.outcome == SEPARATED])
+        L_new = max([L] + [a for a, _, _, r in deciding if r.outcome == SEPARATED])
         Lc = max(Lc, L_new)
         U_new = min(U, Uc)
-        for alpha, concl, T, r in round_:
+        for alpha, concl, T, r in deciding:
             if r.outcome != SEPARATED and alpha >= L_new:
                 U_new = min(U_new, r.f_best if r.outcome == BEAT else concl)
         L, U = L_new, U_new

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -834,18 +835,52 @@ int scp_mwu_batch_solve_kway(scp_mwu_batch *b, scp_mwu_result *res, double *y) {
       b->h_params[i - 1] = test_params(b, I, alpha[i - 1], T, early);
     }
     if ((rc = start_tests(b, k))) return rc;
+    // the tests advance together; between chunks, the tests that ended are
+    // taken in the order in which they ended (ties: the lower alpha first),
+    // and each stops the tests its outcome makes moot: a separated test those
+    // below it, any other test those above it.  A stopped test decides
+    // nothing and counts the iterations it ran until it was stopped.
+    std::vector<int64_t> stop(k, -1);  // the iteration at which a moot test was stopped
+    std::vector<bool> seen(k, false);   // ended tests already taken
     while (true) {
       if ((rc = run_iters(b, b->chunk))) return rc;
+      std::vector<int> ended;
+      for (int j = 0; j < k; ++j)
+        if (!seen[j] && stop[j] < 0 && b->h_st[j].status != kRunning) ended.push_back(j);
+      std::sort(ended.begin(), ended.end(), [&](int x, int z) {
+        return b->h_st[x].t_end != b->h_st[z].t_end ? b->h_st[x].t_end < b->h_st[z].t_end : x < z;
+      });
+      for (int i : ended) {
+        if (stop[i] >= 0) continue;  // made moot by a test that ended before it
+        seen[i] = true;
+        const bool sep = b->h_st[i].status == kSeparated;
+        for (int j = sep ? 0 : i + 1; j < (sep ? i : k); ++j) {
+          if (seen[j] || stop[j] >= 0) continue;
+          stop[j] = b->h_st[i].t_end;
+          if (b->h_st[j].status == kRunning) {
+            // end the test on the device (the stream is idle between chunks)
+            const int32_t st = kTReached;
+            if ((rc = b->hip(hipMemcpy((char *)(b->st + j) + offsetof(DevState, status), &st, sizeof(st),
+                                       hipMemcpyHostToDevice),
+                             "stop a moot test")))
+              return rc;
+            b->h_st[j].status = kTReached;
+          }
+        }
+      }
       if (!any_running(b)) break;
     }
     bool need_vec = false;
     int64_t longest = 0;
     for (int j = 0; j < k; ++j) {
       const DevState &s = b->h_st[j];
-      if (s.status == kNumeric) return b->fail(SCP_MWU_E_NUMERIC, "non-finite value in the iteration");
-      need_vec = need_vec || s.f_best < Uc;
-      iters += s.t_end;
-      longest = std::max<int64_t>(longest, s.t_end);
+      if (stop[j] < 0 && s.status == kNumeric) return b->fail(SCP_MWU_E_NUMERIC, "non-finite value in the iteration");
+      // a moot test ended (or would have ended) no earlier than the test that
+      // made it moot
+      const int64_t ran = stop[j] >= 0 ? stop[j] : s.t_end;
+      if (stop[j] < 0) need_vec = need_vec || s.f_best < Uc;
+      iters += ran;
+      longest = std::max<int64_t>(longest, ran);
       b->inst[j].active = false;
     }
     passes += longest;
@@ -853,19 +888,20 @@ int scp_mwu_batch_solve_kway(scp_mwu_batch *b, scp_mwu_result *res, double *y) {
     if (need_vec && (rc = read_vectors(b))) return rc;
     for (int j = 0; j < k; ++j) {
       const DevState &s = b->h_st[j];
-      if (s.f_best < Uc) {
+      if (stop[j] < 0 && s.f_best < Uc) {
         Uc = s.f_best;
         std::memcpy(best.data(), b->h_vec + b->inst[j].vec_off + kVecBest * d, sizeof(double) * d);
       }
     }
     double Ln = L;
     for (int j = 0; j < k; ++j)
-      if (b->h_st[j].status == kSeparated) Ln = std::max(Ln, alpha[j]);
+      if (stop[j] < 0 && b->h_st[j].status == kSeparated) Ln = std::max(Ln, alpha[j]);
     Lc = std::max(Lc, Ln);
     double Un = std::min(U, Uc);
     for (int j = 0; j < k; ++j) {
       const DevState &s = b->h_st[j];
-      if (s.status != kSeparated && alpha[j] >= Ln) Un = std::min(Un, s.status == kBeat ? s.f_best : concl[j]);
+      if (stop[j] < 0 && s.status != kSeparated && alpha[j] >= Ln)
+        Un = std::min(Un, s.status == kBeat ? s.f_best : concl[j]);
     }
     L = Ln;
     U = Un;
