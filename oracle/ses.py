@@ -258,6 +258,7 @@ class SolveResult:
     passes: int = 0             # k-way search: sum over rounds of the longest test
     tie_margin: float = math.inf  # least FtpResult.tie_margin over the search's tests
     cancel_max: float = 1.0       # largest FtpResult.cancel_max over the search's tests
+    stopped: Optional[list] = None  # k-way search: per step, whether the round stopped the test (moot)
 
 
 def solve(V, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Optional[int] = None,
@@ -344,6 +345,7 @@ def solve_kway(V, k: int, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Opt
     center = P.V[v1].copy()
     iters = passes = 0
     steps = []
+    stopped_steps = []
     converged = False
     tie_margin = math.inf
     cancel_max = 1.0
@@ -378,6 +380,7 @@ def solve_kway(V, k: int, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Opt
                 if j in live:
                     live.discard(j)
                     stop[j] = round_[i][3].t
+        stopped_steps += [stop[i] is not None for i in range(k)]
         ran = [r.t if stop[i] is None else min(r.t, stop[i]) for i, (_, _, _, r) in enumerate(round_)]
         iters += sum(ran)
         passes += max(ran)
@@ -396,4 +399,4 @@ def solve_kway(V, k: int, gamma=None, v1: int = 0, eps: float = 1e-3, t_cap: Opt
         converged = U - L <= eps * L
     return SolveResult(radius=Uc, center=center, lower=Lc, upper=Uc, L=L, U=U, iters=iters,
                        steps=steps, converged=converged, passes=passes, tie_margin=tie_margin,
-                       cancel_max=cancel_max)
+                       cancel_max=cancel_max, stopped=stopped_steps)

@@ -202,6 +202,37 @@ def test_kway_theory_solve_within_eps_of_exact(k):
     assert len(r.steps) % k == 0
 
 
+@pytest.mark.parametrize("k,seed", [(2, 12), (3, 12), (4, 5), (3, 7)])
+def test_kway_stopped_tests_are_implied_by_theorem_meta(k, seed):
+    """A stopped test decides nothing, which loses nothing only if its own
+    outcome follows from the round's deciding tests.  With T = T_theory,
+    Theorem meta gives that outcome: a test at alpha >= OPT never separates,
+    one with (1 + eps) alpha < OPT always does; a separation certifies
+    alpha < OPT.  So a test below a separated deciding test separates
+    ((1 + eps_j) alpha_j <= L + 2j (U - L)/(2k + 1) < alpha_i < OPT), and a
+    test above a non-separated deciding test i does not
+    (OPT <= (1 + eps_i) alpha_i < alpha_j).  The oracle runs every test to its
+    end, so each stopped test's own outcome is checked against the deciding
+    tests of its round."""
+    V = synth.ses_uniform(8, 2, seed)
+    r = ses.solve_kway(V, k, eps=0.1, theory=True)
+    assert len(r.stopped) == len(r.steps) and len(r.steps) % k == 0
+    n_stopped = 0
+    for r0 in range(0, len(r.steps), k):
+        rnd = list(zip(r.steps[r0:r0 + k], r.stopped[r0:r0 + k]))
+        dec = [st for st, s in rnd if not s]
+        assert dec, "a round keeps at least one deciding test"
+        for st, s in rnd:
+            if not s:
+                continue
+            n_stopped += 1
+            above_sep = any(x[2] == ses.SEPARATED and x[0] > st[0] for x in dec)
+            below_not = any(x[2] != ses.SEPARATED and x[0] < st[0] for x in dec)
+            assert above_sep or below_not
+            assert (st[2] == ses.SEPARATED) == above_sep
+    assert n_stopped > 0
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("k", [2, 4])
 def test_kway_practical_solve_brackets_exact(k):
