@@ -292,11 +292,8 @@ SMALL = dict(name="ses_2000_d3_f64", n=2000, d=3, seeds=list(range(10)))
 
 def small_config():
     """SES 2000 x 3 uniform in [-1, 1]^3 with FP64 storage, eps = 1e-3: the GPU
-    solve of each of 10 seeds (solves/s from the median wall time), with the
-    fixed-order combine of the partial sums, so that each solve is
-    reproducible (without it the sums' last bits, hence the search path near
-    its decision points, vary from run to run).  The CPU baseline's full
-    solve of seed 0 is in cpu_baseline."""
+    solve of each of 10 seeds (solves/s from the median wall time).  The CPU
+    baseline's full solve of seed 0 is in cpu_baseline."""
     import torch
     import paper_2405_09157_amd as scp
     import synth
@@ -304,7 +301,7 @@ def small_config():
     for seed in SMALL["seeds"]:
         V = synth.ses_uniform(SMALL["n"], SMALL["d"], seed)
         Vd = torch.from_numpy(V).cuda()
-        m = scp.MWU(Vd, "ses", eps=1e-3, flags=scp.SCP_MWU_FLAG_DETERMINISTIC)
+        m = scp.MWU(Vd, "ses", eps=1e-3)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = m.solve()

@@ -216,9 +216,17 @@ int set_active(scp_mwu_batch *b, bool on) {
 // The streaming pass of every running instance (one launch per layout, or
 // the shared-read pass of a k-way batch).
 hipError_t passes(scp_mwu_batch *b, hipStream_t s) {
-  if (b->kway)
-    return b->dtype == kBF16 ? launch_kway_batch_bf16(b->kw_epl, b->kw_vec, b->kway, b->kw_grid, b->args, s)
-                             : launch_kway_batch_f32(b->kw_epl, b->kw_vec, b->kway, b->kw_grid, b->args, s);
+  if (b->kway) {
+    // 2 or 3 tests: one shared pass; 4 tests: two shared passes of two
+    const int ks = b->kway == 4 ? 2 : b->kway;
+    for (int j0 = 0; j0 < b->kway; j0 += ks) {
+      const hipError_t e =
+          b->dtype == kBF16 ? launch_kway_batch_bf16(b->kw_epl, b->kw_vec, ks, b->kw_grid, b->args + j0, s)
+                            : launch_kway_batch_f32(b->kw_epl, b->kw_vec, ks, b->kw_grid, b->args + j0, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   for (const Layout &l : b->layouts) {
     const hipError_t e = pass_launch(b, l, s);
     if (e != hipSuccess) return e;
@@ -552,9 +560,10 @@ int scp_mwu_batch_init(const scp_mwu_batch_desc *desc, scp_mwu_batch **out) {
       return fail(SCP_MWU_E_HIP, "tile upload");
   }
   // a k-way batch: 2 or 3 instances over the same rows with d <= 128 share
-  // each load (the per-test work makes a shared pass of four tests slower
-  // than four passes; SCPMWU_KWAY_SHARED=0 keeps one pass per instance)
-  bool same = m >= 2 && m <= 3 && b->inst[0].d <= kG * 8;
+  // each load; 4 instances share it in pairs (the per-test work makes a
+  // shared pass of four tests slower than four passes; SCPMWU_KWAY_SHARED=0
+  // keeps one pass per instance)
+  bool same = m >= 2 && m <= 4 && b->inst[0].d <= kG * 8;
   if (const char *ke = getenv("SCPMWU_KWAY_SHARED"))
     if (ke[0] == '0') same = false;
   for (int k = 1; k < m && same; ++k)
