@@ -186,7 +186,7 @@ typedef struct scp_mwu_result {
   int64_t passes;      /* streaming passes over the points: iters, except for
                           the k-way search (scp_mwu_batch_solve_kway), whose k
                           tests of a round share passes (sum over rounds of
-                          the longest test) */
+                          the round's length) */
 } scp_mwu_result;
 
 typedef struct scp_mwu_ctx scp_mwu_ctx;
@@ -411,13 +411,19 @@ int scp_mwu_batch_solve(scp_mwu_batch *b, scp_mwu_result *res, double *y);
  * that are the same point set (equal n, d and offset); they serve as the k
  * test slots.  Each round cuts [L, U] into 2k + 1 equal parts and runs the k
  * alpha-feasibility tests at alpha_i = L + (2i - 1)(U - L)/(2k + 1) with
- * eps_i = (U - L)/((2k + 1) alpha_i) together (their workgroups interleaved
- * by rows, so that the k reads of a row block coincide in the cache); after
- * the round every separation raises L to its alpha, every other test whose
- * alpha is not below the new L lowers U to f_best (f beat alpha) or to
- * L + 2i(U - L)/(2k + 1), and every f seen tightens U and the certified
- * radius.  k = 1 is the search of scp_mwu_solve.  res (host, one entry): as
- * scp_mwu_solve, with passes = sum over rounds of the longest test; y (host,
+ * eps_i = (U - L)/((2k + 1) alpha_i) together (2 or 3 tests share each read
+ * of the rows, 4 tests in pairs, with d <= 128; otherwise one pass per test,
+ * their workgroups interleaved by rows so that the reads of a row block
+ * coincide in the cache).  In the order in which the tests end (ties: the
+ * lower alpha first), an ended test stops the tests its outcome makes moot:
+ * a separated test those below it, any other test those above it; a stopped
+ * test decides nothing.  After the round every deciding separation raises L
+ * to its alpha, every other deciding test whose alpha is not below the new L
+ * lowers U to f_best (f beat alpha) or to L + 2i(U - L)/(2k + 1), and every
+ * deciding test's f tightens U and the certified radius.  k = 1 is the search
+ * of scp_mwu_solve.  res (host, one entry): as scp_mwu_solve, with iters
+ * counting a stopped test's iterations until it was stopped and passes = sum
+ * over rounds of the round's length (its last deciding test's end); y (host,
  * d + 1 doubles, may be NULL): centre then radius.  OK / STOPPED as
  * scp_mwu_solve.  Errors: E_INVAL (instances not all the same point set,
  * res NULL), E_HIP, E_NUMERIC.
