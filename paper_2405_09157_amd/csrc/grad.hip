@@ -176,20 +176,24 @@ __global__ __launch_bounds__(kFwdBlk) void fwd_pass(Buffers b, int slot) {
 // centre, kappa and shift of the next iteration (slot + 1).
 template <typename P>
 __global__ __launch_bounds__(kEpi) void fwd_epi(Buffers b, int slot, int64_t t, int write_ck) {
+  static_assert(kMaxCols <= kEpi, "one column per thread");
   __shared__ double s_W[kMaxCols + 2], tmp[kEpi], s_r[kEpi / kW];
   const int tid = threadIdx.x, d = (int)b.d;
+  // this thread's column of S and of row v1, and the slot's kappa and D,
+  // requested together with the partial sums
+  const int col = tid;
+  const double S0 = col < d ? b.S[col] : 0.0;
+  const double v1c = col < d ? xval<P>(b, b.v1, col) : 0.0;
+  const double kap = b.ts[slot * 4 + 0], D = b.misc[2];
   reduce_parts<kEpi>(b.part, b.pgrid, d + 2, s_W, tmp);
-  double p = 0.0;
-  for (int col = tid; col < d; col += kEpi) p += s_W[col] * s_W[col];
+  const double p = col < d ? s_W[col] * s_W[col] : 0.0;
   const double nW = sqrt(bsum<kEpi>(p, s_r));
-  const double kap = b.ts[slot * 4 + 0];
   const bool ok = kap > 0.0 && nW > 0.0;
   const double tt = (double)t;
   double q = 0.0;
-  for (int col = tid; col < d; col += kEpi) {
-    const double v1c = xval<P>(b, b.v1, col);
+  if (col < d) {
     const double wh = ok ? s_W[col] / nW : 0.0;
-    const double S = b.S[col] + (v1c + b.alpha * wh);
+    const double S = S0 + (v1c + b.alpha * wh);
     b.S[col] = S;
     b.tw[(int64_t)slot * d + col] = wh;
     const double cn = S / tt;
@@ -200,10 +204,10 @@ __global__ __launch_bounds__(kEpi) void fwd_epi(Buffers b, int slot, int64_t t, 
   q = bsum<kEpi>(q, s_r);
   if (tid == 0) {
     b.ts[slot * 4 + 2] = ok ? nW : 0.0;
-    const double kn = b.eta * tt / (3.0 * b.misc[2]);
+    const double kn = b.eta * tt / (3.0 * D);
     b.ts[(slot + 1) * 4 + 0] = kn;
     // kappa d_i <= kappa (||v_i - v1|| + ||v1 - c||) <= kappa (D + ||v1 - c||)
-    b.ts[(slot + 1) * 4 + 1] = kn * (b.misc[2] + sqrt(q));
+    b.ts[(slot + 1) * 4 + 1] = kn * (D + sqrt(q));
   }
 }
 
@@ -659,18 +663,25 @@ __global__ __launch_bounds__(kBlk) void seg_contract_mfma(Buffers b, int jlo, in
 
 // ---- reverse epilogue of iteration t: v1's share, the D share, lambda_{t-1}.
 __global__ __launch_bounds__(kEpi) void bwd_epi(Buffers b, int slot, int64_t t) {
+  static_assert(kMaxCols <= kEpi, "one column per thread");
   __shared__ double s_P[kMaxCols + 2], tmp[kEpi];
   const int tid = threadIdx.x, d = (int)b.d;
+  // this thread's column of lambda, v1's accumulator and lambda_W, and the
+  // slot's kappa and D, requested together with the partial sums
+  const int col = tid;
+  const double lam = col < d ? b.lam[col] : 0.0;
+  const double g1 = col < d ? b.gv1[col] : 0.0;
+  const double lwc = col < d && t >= 2 ? b.lw[(int64_t)slot * d + col] : 0.0;
+  const double kap = b.ts[slot * 4 + 0], D = b.misc[2];
   if (t >= 2) reduce_parts<kEpi>(b.part, b.pgrid, d + 2, s_P, tmp);
-  for (int col = tid; col < d; col += kEpi) {
-    const double lam = b.lam[col];
-    b.gv1[col] += lam;
+  if (col < d) {
+    b.gv1[col] = g1 + lam;
     if (t >= 2) {
-      const double lc = -s_P[d] * b.lw[(int64_t)slot * d + col] - s_P[col];
+      const double lc = -s_P[d] * lwc - s_P[col];
       b.lam[col] = lam + lc / (double)(t - 1);
     }
   }
-  if (tid == 0 && t >= 2) b.misc[0] += -(b.ts[slot * 4 + 0] / b.misc[2]) * s_P[d + 1];
+  if (tid == 0 && t >= 2) b.misc[0] += -(kap / D) * s_P[d + 1];
 }
 
 // ---- farthest row from a centre (ties: smallest index), per workgroup
