@@ -82,7 +82,10 @@ hipError_t launch_kway_batch_typed(int epl, int vec, int ks, int grid, const Pas
 // weighted sums are kept per lane and reduced once per workgroup.  Point sets
 // only (no radii).  Arithmetic is binary64 per element for every storage
 // type; with BF16 storage the weighted sums are taken about fl32(ubar), the
-// origin its epilogue expects.  The record has the layout of ses_pass_body's.
+// origin its epilogue expects: summed about ubar and moved to fl32(ubar) once
+// per lane, sum a_i (x_i - fl32(ubar)) = sum a_i (x_i - ubar) + (ubar -
+// fl32(ubar)) sum a_i, which keeps a second copy of the mean out of the
+// registers.  The record has the layout of ses_pass_body's.
 template <typename T, int DM, int VEC>
 __device__ __forceinline__ void ses_rows_body(const PassArgs &a, int vb, int vg) {
   static_assert(DM % VEC == 0 && DM <= 16, "row layout");
@@ -103,11 +106,10 @@ __device__ __forceinline__ void ses_rows_body(const PassArgs &a, int vb, int vg)
   const double kappa = st->kscale * (double)st->t;
   const double Gb = st->shift_bound;
   const int64_t v1 = a.v1;
-  double ub[DM], org[DM], acc[DM];
+  double ub[DM], acc[DM];
 #pragma unroll
   for (int c = 0; c < DM; ++c) {
     ub[c] = c < d ? a.vec[kVecMean * d + c] : 0.0;
-    org[c] = M32 ? (double)(float)ub[c] : 0.0;
     acc[c] = 0.0;
   }
   double asum = 0.0, bsum = 0.0, esum = 0.0, gmax = -INFINITY, fall = -INFINITY;
@@ -161,7 +163,10 @@ __device__ __forceinline__ void ses_rows_body(const PassArgs &a, int vb, int vg)
       if (incl) gmax = fmax(gmax, di);
       if (valid) fall = fmax(fall, di);
 #pragma unroll
-      for (int c = 0; c < DM; ++c) acc[c] = fma(aw, to_f64(x[j][c / VEC].v[c % VEC]) - org[c], acc[c]);
+      for (int c = 0; c < DM; ++c) {
+        const double xv = to_f64(x[j][c / VEC].v[c % VEC]);
+        acc[c] = fma(aw, M32 ? xv - ub[c] : xv, acc[c]);
+      }
     }
   }
   if (status0 != kRunning) return;
@@ -169,6 +174,7 @@ __device__ __forceinline__ void ses_rows_body(const PassArgs &a, int vb, int vg)
   // ---- workgroup record: sums, maxima
 #pragma unroll
   for (int c = 0; c < DM; ++c) {
+    if constexpr (M32) acc[c] = fma(ub[c] - (double)(float)ub[c], asum, acc[c]);
     const double v = wave_sum(acc[c]);
     if (lane == 0) s_vec[wave][c] = v;
   }
