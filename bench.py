@@ -509,8 +509,8 @@ def main(argv=None):
                     help="also time a plain copy of the matrix (counter calibration)")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the row-sharded design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(sharding would split the point rows and all-reduce each iteration's sums)", file=sys.stderr)
         return 2
     import numpy as np
     import torch
