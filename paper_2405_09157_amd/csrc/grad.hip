@@ -173,7 +173,12 @@ __global__ __launch_bounds__(kFwdBlk) void fwd_pass(Buffers b, int slot) {
 }
 
 // ---- forward epilogue of iteration t: u(t), S_t, the tape of slot and the
-// centre, kappa and shift of the next iteration (slot + 1).
+// centre, kappa and shift of the next iteration (slot + 1).  The shift bound:
+// c_t - v1 is alpha times a mean of unit vectors (u(1) = v1), so d_i <=
+// ||v_i - v1|| + ||v1 - c_t|| <= D + alpha and kappa (D + alpha) caps every
+// exponent at 0, while the largest stays above -2 kappa alpha (the row at
+// distance D from v1 lies at least D - ||v1 - c_t|| from c_t); the map does
+// not depend on the shift.
 template <typename P>
 __global__ __launch_bounds__(kEpi) void fwd_epi(Buffers b, int slot, int64_t t, int write_ck) {
   static_assert(kMaxCols <= kEpi, "one column per thread");
@@ -190,46 +195,35 @@ __global__ __launch_bounds__(kEpi) void fwd_epi(Buffers b, int slot, int64_t t, 
   const double nW = sqrt(bsum<kEpi>(p, s_r));
   const bool ok = kap > 0.0 && nW > 0.0;
   const double tt = (double)t;
-  double q = 0.0;
   if (col < d) {
     const double wh = ok ? s_W[col] / nW : 0.0;
     const double S = S0 + (v1c + b.alpha * wh);
     b.S[col] = S;
     b.tw[(int64_t)slot * d + col] = wh;
-    const double cn = S / tt;
-    b.tc[(int64_t)(slot + 1) * d + col] = cn;
-    q += (v1c - cn) * (v1c - cn);
+    b.tc[(int64_t)(slot + 1) * d + col] = S / tt;
     if (write_ck && t % b.seg == 0) b.ck[(t / b.seg) * d + col] = S;
   }
-  q = bsum<kEpi>(q, s_r);
   if (tid == 0) {
     b.ts[slot * 4 + 2] = ok ? nW : 0.0;
     const double kn = b.eta * tt / (3.0 * D);
     b.ts[(slot + 1) * 4 + 0] = kn;
-    // kappa d_i <= kappa (||v_i - v1|| + ||v1 - c||) <= kappa (D + ||v1 - c||)
-    b.ts[(slot + 1) * 4 + 1] = kn * (D + sqrt(q));
+    b.ts[(slot + 1) * 4 + 1] = kn * (D + b.alpha);  // the shift bound
   }
 }
 
 // ---- start of the segment whose first iteration is t0 + 1: S = S_{t0}.
 template <typename P>
 __global__ __launch_bounds__(kBlk) void seg_init(Buffers b, int64_t t0) {
-  __shared__ double s_r[kNW];
   const int tid = threadIdx.x, d = (int)b.d;
-  double q = 0.0;
   for (int col = tid; col < d; col += kBlk) {
     const double S = b.ck[(t0 / b.seg) * d + col];
-    const double v1c = xval<P>(b, b.v1, col);
-    const double cn = t0 > 0 ? S / (double)t0 : v1c;
     b.S[col] = S;
-    b.tc[col] = cn;
-    q += (v1c - cn) * (v1c - cn);
+    b.tc[col] = t0 > 0 ? S / (double)t0 : xval<P>(b, b.v1, col);
   }
-  q = bsum<kBlk>(q, s_r);
   if (tid == 0) {
     const double k0 = b.eta * (double)t0 / (3.0 * b.misc[2]);
     b.ts[0] = k0;
-    b.ts[1] = k0 * (b.misc[2] + sqrt(q));
+    b.ts[1] = k0 * (b.misc[2] + b.alpha);  // the shift bound of the forward epilogue
   }
 }
 
