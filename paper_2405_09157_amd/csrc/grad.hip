@@ -81,31 +81,43 @@ __device__ __forceinline__ double xval<uint16_t>(const Buffers &b, int64_t i, in
 }
 
 // dst[c] = sum over the grid's partial rows of column c, c < ncol, by the NT
-// threads of one workgroup (fixed order; four loads in flight per thread).
+// threads of one workgroup (fixed order).  Rows are part_stride(ncol - 2)
+// apart; each thread sums one pair of adjacent columns (16-byte loads, four
+// in flight), which halves the load instructions of the one compute unit
+// that runs the epilogue.  tmp holds 2 NT doubles.
 template <int NT>
 __device__ void reduce_parts(const double *part, int G, int ncol, double *dst, double *tmp) {
-  const int tid = threadIdx.x;
-  const int groups = ncol <= NT ? NT / ncol : 1;
-  for (int c0 = 0; c0 < ncol; c0 += NT) {
-    const int span = ncol - c0 < NT ? ncol - c0 : NT;
-    const int grp = tid / span, col = c0 + tid - grp * span;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const int tid = threadIdx.x, np = (ncol + 1) / 2;
+  const int64_t ps = part_stride(ncol - 2);
+  for (int p0 = 0; p0 < np; p0 += NT) {
+    const int span = np - p0 < NT ? np - p0 : NT;
+    const int groups = NT / span;
+    const int grp = tid / span, c = 2 * (p0 + tid - grp * span);
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
     if (grp < groups) {
+      const double *col = part + c;
       int g = grp;
       for (; g + 3 * groups < G; g += 4 * groups) {
-        a0 += part[(int64_t)g * ncol + col];
-        a1 += part[(int64_t)(g + groups) * ncol + col];
-        a2 += part[(int64_t)(g + 2 * groups) * ncol + col];
-        a3 += part[(int64_t)(g + 3 * groups) * ncol + col];
+        const double2 v0 = *reinterpret_cast<const double2 *>(col + (int64_t)g * ps);
+        const double2 v1 = *reinterpret_cast<const double2 *>(col + (int64_t)(g + groups) * ps);
+        const double2 v2 = *reinterpret_cast<const double2 *>(col + (int64_t)(g + 2 * groups) * ps);
+        const double2 v3 = *reinterpret_cast<const double2 *>(col + (int64_t)(g + 3 * groups) * ps);
+        a0.x += v0.x, a0.y += v0.y, a1.x += v1.x, a1.y += v1.y;
+        a2.x += v2.x, a2.y += v2.y, a3.x += v3.x, a3.y += v3.y;
       }
-      for (; g < G; g += groups) a0 += part[(int64_t)g * ncol + col];
+      for (; g < G; g += groups) {
+        const double2 v = *reinterpret_cast<const double2 *>(col + (int64_t)g * ps);
+        a0.x += v.x, a0.y += v.y;
+      }
     }
-    tmp[tid] = (a0 + a1) + (a2 + a3);
+    tmp[2 * tid] = (a0.x + a1.x) + (a2.x + a3.x);
+    tmp[2 * tid + 1] = (a0.y + a1.y) + (a2.y + a3.y);
     __syncthreads();
-    if (tid < span) {
+    for (int e = tid; e < 2 * span; e += NT) {  // column 2 p0 + e
+      const int k = e >> 1, h = e & 1;
       double r = 0.0;
-      for (int q = 0; q < groups; ++q) r += tmp[q * span + tid];
-      dst[c0 + tid] = r;
+      for (int q = 0; q < groups; ++q) r += tmp[2 * (q * span + k) + h];
+      if (2 * p0 + e < ncol) dst[2 * p0 + e] = r;
     }
     __syncthreads();
   }
@@ -162,8 +174,8 @@ __global__ __launch_bounds__(kFwdBlk) void fwd_pass(Buffers b, int slot) {
 #pragma unroll
   for (int j = 0; j < PER; ++j) red[w][lane + j * kW] = acc[j];
   __syncthreads();
-  double *p = b.part + (int64_t)blockIdx.x * (d + 2);
-  for (int col = threadIdx.x; col < d + 2; col += kFwdBlk) {
+  double *p = b.part + (int64_t)blockIdx.x * part_stride(d);
+  for (int col = threadIdx.x; col < part_stride(d); col += kFwdBlk) {
     double v = 0.0;
     if (col < d)
 #pragma unroll
@@ -182,7 +194,7 @@ __global__ __launch_bounds__(kFwdBlk) void fwd_pass(Buffers b, int slot) {
 template <typename P>
 __global__ __launch_bounds__(kEpi) void fwd_epi(Buffers b, int slot, int64_t t, int write_ck) {
   static_assert(kMaxCols <= kEpi, "one column per thread");
-  __shared__ double s_W[kMaxCols + 2], tmp[kEpi], s_r[kEpi / kW];
+  __shared__ double s_W[kMaxCols + 2], tmp[2 * kEpi], s_r[kEpi / kW];
   const int tid = threadIdx.x, d = (int)b.d;
   // this thread's column of S and of row v1, and the slot's kappa and D,
   // requested together with the partial sums
@@ -322,13 +334,14 @@ __global__ __launch_bounds__(kBwdBlk) void bwd_pass(Buffers b, int slot) {
     s_k[w] = accK;
   }
   __syncthreads();
-  double *p = b.part + (int64_t)blockIdx.x * (d + 2);
-  for (int col = threadIdx.x; col < d + 2; col += kBwdBlk) {
+  double *p = b.part + (int64_t)blockIdx.x * part_stride(d);
+  for (int col = threadIdx.x; col < part_stride(d); col += kBwdBlk) {
     const double *src = col < d ? &red[0][col] : (col == d ? s_a : s_k);
     const int step = col < d ? kMaxCols : 1;
     double v = 0.0;
+    if (col < d + 2)
 #pragma unroll
-    for (int q = 0; q < NW; ++q) v += src[q * step];
+      for (int q = 0; q < NW; ++q) v += src[q * step];
     p[col] = v;
   }
 }
@@ -438,8 +451,8 @@ __global__ __launch_bounds__(kFwdBlk) void fwd_rows(Buffers b, int slot) {
     if (rg == 0) red[w][cl * CPL + j] = v;
   }
   __syncthreads();
-  double *p = b.part + (int64_t)blockIdx.x * (d + 2);
-  for (int col = threadIdx.x; col < d + 2; col += kFwdBlk) {
+  double *p = b.part + (int64_t)blockIdx.x * part_stride(d);
+  for (int col = threadIdx.x; col < part_stride(d); col += kFwdBlk) {
     double v = 0.0;
     if (col < d)
 #pragma unroll
@@ -537,13 +550,13 @@ __global__ __launch_bounds__(kBwdBlk) void bwd_rows(Buffers b, int slot) {
     s_k[w] = accK;
   }
   __syncthreads();
-  double *p = b.part + (int64_t)blockIdx.x * (d + 2);
-  for (int col = threadIdx.x; col < d + 2; col += kBwdBlk) {
+  double *p = b.part + (int64_t)blockIdx.x * part_stride(d);
+  for (int col = threadIdx.x; col < part_stride(d); col += kBwdBlk) {
     double v = 0.0;
     if (col < d) {
 #pragma unroll
       for (int q = 0; q < NW; ++q) v += red[q][col];
-    } else {
+    } else if (col < d + 2) {
       const double *src = col == d ? s_a : s_k;
 #pragma unroll
       for (int q = 0; q < NW; ++q) v += src[q];
@@ -658,7 +671,7 @@ __global__ __launch_bounds__(kBlk) void seg_contract_mfma(Buffers b, int jlo, in
 // ---- reverse epilogue of iteration t: v1's share, the D share, lambda_{t-1}.
 __global__ __launch_bounds__(kEpi) void bwd_epi(Buffers b, int slot, int64_t t) {
   static_assert(kMaxCols <= kEpi, "one column per thread");
-  __shared__ double s_P[kMaxCols + 2], tmp[kEpi];
+  __shared__ double s_P[kMaxCols + 2], tmp[2 * kEpi];
   const int tid = threadIdx.x, d = (int)b.d;
   // this thread's column of lambda, v1's accumulator and lambda_W, and the
   // slot's kappa and D, requested together with the partial sums

@@ -35,7 +35,7 @@ struct Buffers {
   // tape of one segment (K slots; all T with `full`), slot j = iteration t0 + 1 + j:
   //   tc: c_t (one slot more), tw: W_t/||W_t||, ts: {kappa_t, s_t, ||W_t||, 0} (one slot more)
   double *tc, *tw, *ts;
-  double *part;      // per-workgroup partial sums: pgrid x (d + 2), or 2 grid (far rows)
+  double *part;      // per-workgroup partial sums: pgrid x part_stride(d), or 2 grid (far rows)
   double *lam;       // adjoint of S_t
   double *lw;        // lambda_W of each slot of the segment (K x d)
   double *sa, *sb;   // a_i and beta_i of each slot and row (K x n each)
@@ -49,6 +49,9 @@ struct Buffers {
 
 // Sizes of the buffers (in doubles) for given d, T.
 inline int64_t ck_count(int64_t T, int64_t K) { return T / K + 2; }
+// Row stride (doubles) of the per-workgroup partial sums: d + 2 columns
+// rounded up to even, so that column pairs are 16-byte aligned.
+__host__ __device__ inline int64_t part_stride(int64_t d) { return (d + 3) & ~int64_t(1); }
 
 // Launch the whole reverse pass (forward with checkpoints, reverse segments,
 // the terms of R and D) on stream s.  grad_value scales the result.

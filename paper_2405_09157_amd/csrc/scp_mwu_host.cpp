@@ -395,7 +395,7 @@ int scpmwu::backward_with_workspace(scp_mwu_ctx *c, double grad_value, float *gr
   // the value alone needs neither the per-row coefficients nor the accumulator
   const int64_t rows = grad_points ? c->n : 0;
   const int64_t sizes[] = {d, grad::ck_count(c->T, K) * d, (L + 1) * d, L * d, (L + 1) * 4,
-                           (int64_t)b.grid * (d + 2), d, K * d, d, d, 8, K * rows, K * rows, 2, rows * d};
+                           (int64_t)b.grid * grad::part_stride(d), d, K * d, d, d, 8, K * rows, K * rows, 2, rows * d};
   int64_t total = 0;
   for (int64_t v : sizes) total += (v + 31) / 32 * 32;
   const size_t need = (size_t)total * sizeof(double);
