@@ -402,18 +402,21 @@ __global__ __launch_bounds__(kFwdBlk) void fwd_rows(Buffers b, int slot) {
   const double *c = b.tc + (int64_t)slot * d;
   const double kap = b.ts[slot * 4 + 0], sh = b.ts[slot * 4 + 1];
   double cr[CPL], acc[CPL];
+  const double zero[CPL] = {};
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
     const int col = cl * CPL + j;
     cr[j] = col < d ? c[col] : 0.0;
     acc[j] = 0.0;
   }
-  if (kap > 0.0) {
+  // kappa = 0 (the first iteration) leaves every a_i zero; the rows' loads
+  // do not wait for kappa or the centre (zeros stand in past n and d)
+  {
     const int64_t wstride = (int64_t)gridDim.x * NW * kRPW;
     for (int64_t wb = ((int64_t)blockIdx.x * NW + w) * kRPW; wb < b.n; wb += kRBR * wstride) {
       double x[kRBR][CPL];
 #pragma unroll
-      for (int r = 0; r < kRBR; ++r) load_cols<P, CPL, V4>(b, wb + r * wstride + rg, cl, cr, x[r]);
+      for (int r = 0; r < kRBR; ++r) load_cols<P, CPL, V4>(b, wb + r * wstride + rg, cl, zero, x[r]);
       // squared distances of the loop's 32 rows (row r, group rg at r * 4 + rg)
 #pragma unroll
       for (int r = 0; r < kRBR; ++r) {
@@ -431,7 +434,7 @@ __global__ __launch_bounds__(kFwdBlk) void fwd_rows(Buffers b, int slot) {
       if (lane < kRowsPerLoop) {
         const int64_t i = wb + (lane / kRPW) * wstride + lane % kRPW;
         const double di = sqrt(s_row[w][lane]);
-        const bool valid = i < b.n && i != b.v1 && di > 0.0;
+        const bool valid = kap > 0.0 && i < b.n && i != b.v1 && di > 0.0;
         const double ep = exp(kap * di - sh), em = exp(-kap * di - sh);
         s_row[w][lane] = valid ? (ep - em) / di : 0.0;
       }
@@ -469,7 +472,7 @@ __global__ __launch_bounds__(kBwdBlk) void bwd_rows(Buffers b, int slot) {
   __shared__ double s_row[NW][kRowsPerLoop], s_q[NW][kRowsPerLoop];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, d = (int)b.d;
   const int rg = lane >> 4, cl = lane & 15;
-  lambda_w<kBwdBlk>(b, slot, s_lw, s_r);
+  // the slot's centre and scalars are requested with lambda_W's inputs
   const double *c = b.tc + (int64_t)slot * d;
   const double kap = b.ts[slot * 4 + 0], sh = b.ts[slot * 4 + 1], nW = b.ts[slot * 4 + 2];
   double cr[CPL], lw[CPL], accB[CPL];
@@ -478,8 +481,13 @@ __global__ __launch_bounds__(kBwdBlk) void bwd_rows(Buffers b, int slot) {
   for (int j = 0; j < CPL; ++j) {
     const int col = cl * CPL + j;
     cr[j] = col < d ? c[col] : 0.0;
-    lw[j] = col < d ? s_lw[col] : 0.0;
     accB[j] = 0.0;
+  }
+  lambda_w<kBwdBlk>(b, slot, s_lw, s_r);
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int col = cl * CPL + j;
+    lw[j] = col < d ? s_lw[col] : 0.0;
   }
   const bool live = kap > 0.0 && nW > 0.0;
   double *sa = b.sa + (int64_t)slot * b.n, *sb = b.sb + (int64_t)slot * b.n;
