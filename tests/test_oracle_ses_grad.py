@@ -103,3 +103,25 @@ def test_gradient_approaches_the_dual_weight_gradient():
         errs.append(np.abs(G - Gd).max())
     assert R / Rs - 1.0 < 3e-3
     assert errs[1] < errs[0] and errs[1] <= 0.2 * np.abs(Gd).max()
+
+
+@pytest.mark.parametrize("seed,alpha_frac", [(0, 0.55), (1, 0.8), (2, 1.0)])
+def test_shift_bound_along_the_map(seed, alpha_frac):
+    """Along the map every exponent kappa_t d_i (i != v1) stays at or below
+    kappa_t (D + alpha), and the largest stays within 2 kappa_t alpha of it:
+    the common shift the reverse pass takes (c_t - v1 is alpha times a mean of
+    unit vectors, and the row at distance D from v1 keeps its distance to c_t
+    above D - ||v1 - c_t||)."""
+    V = synth.ses_gaussian_outliers(400, 6, seed, frac=0.02)
+    T = 300
+    P = ses.setup(V)
+    alpha = alpha_frac * P.D
+    fw = ses_grad.forward(V, alpha, T)
+    for t in range(2, T + 1):
+        c = fw.S[t - 1] / (t - 1)
+        assert np.linalg.norm(c - P.V[P.v1]) <= alpha * (1 + 1e-12)
+        kap = fw.eta * (t - 1) / (3.0 * P.D)
+        top = kap * (P.D + alpha)
+        largest = float(np.max(kap * np.linalg.norm(P.V[P.F] - c[None, :], axis=1)))
+        assert largest <= top * (1 + 1e-12)
+        assert largest >= top - 2.0 * kap * alpha - 1e-12 * top
